@@ -1,0 +1,225 @@
+"""Plain FP64 CPU oracle of the MOL^T recursive-convolution wave solver.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The HIP library
+never does, and nothing here imports the HIP library.
+
+Contents
+--------
+* ``molt_oracle.c`` (ctypes, FP64): O1 -- L^{-1} on a line by the two
+  exponential recurrences plus the boundary correction (Sec. 2); the
+  directional and ADI operators (Sec. 4, eqs. LD_gam, C_def_ADI(_3),
+  D_def_ADI(_3)); the order-2P update with the Table 2 schedule; the
+  three-level time step and the start step (Sec. 3.2).
+* ``direct.py``: O2 -- the same discrete convolution evaluated directly as an
+  O(M^2) Gauss-Legendre quadrature of the Green's function (eq. L_Inverse),
+  with no recurrence and no closed-form weights.
+* ``scheme.py``: A_p(beta) (Sec. 3, the A_p equation), c_{p,m} (eq. Full_2D),
+  beta_max(P) (Theorem of Sec. 3.1, eq. Stab_cond).
+* ``lines.py``: line objects of an embedded boundary (Sec. 4.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import scheme  # noqa: F401  (re-export)
+from .scheme import stage_coefficients, beta_max, A_p  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "molt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+DIRICHLET = 0
+PERIODIC = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile molt_oracle.c with gcc (FP64, -O2, OpenMP over lines)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.or_linv_line.argtypes = [ctypes.c_long, dp, dp, ctypes.c_double, dp, dp]
+        L.or_linv_periodic_line.argtypes = [ctypes.c_long, ctypes.c_double, dp, ctypes.c_double, dp]
+        for name in ("or_apply_C", "or_apply_D"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, dp, dp]
+        for name in ("or_apply_linv", "or_apply_Dg"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
+        L.or_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp]
+        L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp, dp]
+        L.or_start.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp]
+        L.or_run.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp, ctypes.c_long]
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_count_get.restype = ctypes.c_long
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise RuntimeError("oracle call failed with status %d" % rc)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_long * 3),
+        ("h", ctypes.c_double * 3),
+        ("bc", ctypes.c_int * 3),
+        ("alpha", ctypes.c_double),
+        ("nseg", ctypes.c_long * 3),
+        ("seg_idx", ctypes.c_void_p * 3),
+        ("seg_th", ctypes.c_void_p * 3),
+        ("mask", ctypes.c_void_p),
+    ]
+
+
+class Problem:
+    """A grid problem: shape (C-order, x fastest), spacing, boundary types and
+    alpha = beta/(c dt) (Sec. 2, eq. L_def).  ``segments`` = per-axis
+    (seg_idx[n,3] int64, seg_th[n,2] float64) for embedded line objects
+    (2D only), ``mask`` = uint8 inside indicator in the field's shape."""
+
+    def __init__(self, shape, h, bc, alpha, segments=None, mask=None):
+        shape = tuple(int(s) for s in shape)
+        self.shape = shape
+        self.ndim = len(shape)
+        nx = list(reversed(shape))  # n[0] = x (fastest)
+        hh = list(h) if np.ndim(h) else [float(h)] * self.ndim
+        bb = list(bc) if np.ndim(bc) else [int(bc)] * self.ndim
+        s = _Problem()
+        s.ndim = self.ndim
+        for d in range(3):
+            s.n[d] = nx[d] if d < self.ndim else 1
+            s.h[d] = float(hh[d]) if d < self.ndim else 1.0
+            s.bc[d] = int(bb[d]) if d < self.ndim else 0
+        s.alpha = float(alpha)
+        self._keep = []
+        if segments is not None:
+            for d, seg in enumerate(segments):
+                if seg is None:
+                    continue
+                idx = np.ascontiguousarray(seg[0], dtype=np.int64)
+                th = np.ascontiguousarray(seg[1], dtype=np.float64)
+                self._keep += [idx, th]
+                s.nseg[d] = idx.shape[0]
+                s.seg_idx[d] = idx.ctypes.data
+                s.seg_th[d] = th.ctypes.data
+        if mask is not None:
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            assert m.shape == shape
+            self._keep.append(m)
+            s.mask = m.ctypes.data
+        self._s = s
+        self.alpha = float(alpha)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self._s)
+
+    def _io(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert v.shape == self.shape, (v.shape, self.shape)
+        return v, np.empty_like(v)
+
+    def linv(self, v, axis):
+        """L_gamma^{-1} along grid axis ``axis`` (0 = x, 1 = y, 2 = z)."""
+        v, out = self._io(v)
+        _check(lib().or_apply_linv(self.ref, axis, _p(v), _p(out)))
+        return out
+
+    def Dg(self, v, axis):
+        """D_gamma = 1 - L_gamma^{-1} (eq. LD_gam)."""
+        v, out = self._io(v)
+        _check(lib().or_apply_Dg(self.ref, axis, _p(v), _p(out)))
+        return out
+
+    def C(self, v):
+        v, out = self._io(v)
+        _check(lib().or_apply_C(self.ref, _p(v), _p(out)))
+        return out
+
+    def D(self, v):
+        v, out = self._io(v)
+        _check(lib().or_apply_D(self.ref, _p(v), _p(out)))
+        return out
+
+    def rhs(self, u, P, beta):
+        u, out = self._io(u)
+        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
+        _check(lib().or_rhs(self.ref, P, _p(c), _p(u), _p(out)))
+        return out
+
+    def step(self, u_prev, u_curr, P, beta):
+        u_prev, _ = self._io(u_prev)
+        u_curr, out = self._io(u_curr)
+        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
+        _check(lib().or_step(self.ref, P, _p(c), _p(u_prev), _p(u_curr), _p(out)))
+        return out
+
+    def start(self, u0, P, beta):
+        u0, out = self._io(u0)
+        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
+        _check(lib().or_start(self.ref, P, _p(c), _p(u0), _p(out)))
+        return out
+
+    def run(self, u_prev, u_curr, nsteps, P, beta):
+        """Returns (u^{n+nsteps-1}, u^{n+nsteps})."""
+        a = np.array(u_prev, dtype=np.float64, order="C", copy=True)
+        b = np.array(u_curr, dtype=np.float64, order="C", copy=True)
+        assert a.shape == self.shape and b.shape == self.shape
+        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
+        _check(lib().or_run(self.ref, P, _p(c), _p(a), _p(b), int(nsteps)))
+        return a, b
+
+
+def linv_line(x, v, alpha, bnd=None):
+    """O1 on one bounded line object (nodes x, values v); bnd = (ta, tb, ka, kb)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty_like(v)
+    b = np.ascontiguousarray(bnd if bnd is not None else (0.0, 0.0, 0.0, 0.0), dtype=np.float64)
+    _check(lib().or_linv_line(len(x) - 1, _p(x), _p(v), float(alpha), _p(b), _p(w)))
+    return w
+
+
+def linv_periodic_line(v, h, alpha):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    w = np.empty_like(v)
+    _check(lib().or_linv_periodic_line(len(v), float(h), _p(v), float(alpha), _p(w)))
+    return w
+
+
+def count_reset() -> None:
+    """Reset the count of C/D operator applications (Table 2 pin)."""
+    lib().or_count_reset()
+
+
+def count_get() -> int:
+    return int(lib().or_count_get())
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
