@@ -1,0 +1,175 @@
+/*
+ * molt.h -- C-ABI of the MI355X MOL^T wave solver library (libmolt.so).
+ *
+ * The library advances the wave equation u_tt = c^2 (u_xx + u_yy + u_zz) with
+ * the A-stable order-2P schemes of Causley & Christlieb built from recursive
+ * applications of the convolution operator L^{-1} = (1 - alpha^{-2} d^2)^{-1}
+ * (Sec. 2, eqs. L_def, L_Inverse), D = 1 - L^{-1} (eq. D_def_1d), the
+ * univariate operators L_gamma, D_gamma (Sec. 4, eq. LD_gam) and the ADI
+ * operators C and D (eqs. C_def_ADI, C_def_ADI_3, D_def_ADI, D_def_ADI_3):
+ *
+ *     u^{n+1} - 2 u^n + u^{n-1} = sum_{p=1}^{P} sum_{m=1}^{p}
+ *         (-1)^m 2 beta^{2m}/(2m)! binom(p-1, m-1) C^m D^{p-m} [u^n]
+ *
+ * (eq. Full_2D; in 1D C = D and this is eq. update_P), with
+ * alpha = beta / (c dt), 0 < beta <= beta_max(P) (Sec. 3.1, eq. Stab_cond).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Fields are dense arrays of n[0]*n[1]*n[2] values (1D: n[1] = n[2] = 1) in
+ * C order with x fastest: element (i, j, k) at i + n[0]*(j + n[1]*k).  Field
+ * pointers are DEVICE pointers owned by the caller (e.g. torch tensors); their
+ * element type is the plan's dtype.  Every call is asynchronous on the given
+ * stream (a hipStream_t passed as void*, NULL = the default stream) and
+ * returns after enqueueing; nothing synchronises unless stated.  Errors are
+ * reported as a mol_status; mol_last_error() returns a message for the last
+ * failing call of the calling thread.  No call throws.
+ *
+ * Boundary data (Sec. 3.2): homogeneous.  On a Dirichlet axis the first and
+ * last node of every line are boundary nodes: the library reads them as 0 and
+ * writes 0 there.  With a mask (2D only) every node outside the domain is read
+ * as 0 and written as 0, and the x and y convolutions act on line objects
+ * (Sec. 4.3): the inside nodes between two crossings of the boundary curve
+ * plus the two boundary points at the crossings.
+ */
+#ifndef MOLT_H
+#define MOLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MOL_OK = 0,
+    MOL_E_INVALID = 1,     /* bad argument (descriptor, pointer, size) */
+    MOL_E_UNSUPPORTED = 2, /* valid but not provided (e.g. g != NULL, mask in 3D) */
+    MOL_E_UNSTABLE = 3,    /* beta > beta_max(P) without MOL_ALLOW_UNSTABLE */
+    MOL_E_NOMEM = 4,       /* device or host allocation failed */
+    MOL_E_DEVICE = 5       /* a HIP call or kernel launch failed */
+} mol_status;
+
+typedef enum { MOL_BC_DIRICHLET = 0, MOL_BC_PERIODIC = 1 } mol_bc;
+typedef enum { MOL_F64 = 0, MOL_F32 = 1 } mol_dtype;
+
+enum {
+    MOL_ALLOW_UNSTABLE = 1,   /* accept beta > beta_max(P) */
+    MOL_INCREMENT_FORM = 2,   /* mol_solve carries du = u^n - u^{n-1} instead of u^{n-1} */
+    MOL_NO_GRAPH = 4          /* mol_solve launches kernels directly instead of a hipGraph */
+};
+
+/* Problem descriptor (Sec. 2: domain, c, dt, beta; Sec. 3: order P;
+ * Sec. 3.2: boundary type; Sec. 4.3: embedded boundary). */
+typedef struct mol_desc {
+    int ndim;               /* 1, 2 or 3 */
+    int64_t n[3];           /* nodes per axis (x, y, z); unused axes = 1 */
+    double h[3];            /* node spacing per axis */
+    int bc[3];              /* mol_bc per axis */
+    const uint8_t *mask;    /* HOST pointer or NULL (2D only): n[1] x n[0] bytes,
+                               1 = inside; the outer ring of nodes must be 0 */
+    const double *cross;    /* HOST pointer or NULL: 4 x n[1] x n[0] doubles; at an
+                               inside node next to an outside node, the distance to
+                               the boundary crossing in units of h toward -x, +x,
+                               -y, +y, in (0, 1]; NULL puts the crossing on the
+                               outside node (distance 1) */
+    int P;                  /* order 2P, 1 <= P <= 5 (Table 1) */
+    double c;               /* wave speed > 0 */
+    double dt;              /* time step > 0 */
+    double beta;            /* <= 0 selects beta_max(P) (Table 1) */
+    int dtype;              /* mol_dtype of every field */
+    int flags;              /* MOL_ALLOW_UNSTABLE | MOL_INCREMENT_FORM | MOL_NO_GRAPH */
+} mol_desc;
+
+typedef struct mol_plan_ mol_plan;
+
+/* Scalars derived by the plan (for reporting). */
+typedef struct mol_plan_info {
+    double beta;            /* beta used */
+    double beta_max;        /* beta_max(P) */
+    double alpha;           /* beta / (c dt) (eq. L_def) */
+    double nu[3];           /* alpha * h per axis */
+    int64_t points;         /* nodes per field */
+    int64_t unknowns;       /* nodes that are not boundary / outside nodes */
+    int64_t segments[2];    /* line objects per axis (masked plans), else 0 */
+    int kernels_per_step;   /* kernel launches in one mol_step */
+    double bytes_per_step;  /* algorithmic HBM bytes of one step (fields read + written) */
+    size_t workspace_bytes; /* device workspace held by the plan */
+} mol_plan_info;
+
+/* beta_max(P): first positive root of -sum_{p<=P} A_p(beta) = 4
+ * (Theorem of Sec. 3.1, eq. Stab_cond); returns -1 for P outside 1..8. */
+double mol_beta_max(int P);
+
+/* Validates the descriptor, derives alpha, the quadrature weights and the
+ * stage coefficients in FP64, builds the kernel schedule (and for a mask the
+ * line-object tables), and allocates the device workspace on the current
+ * device.  *plan is set only on MOL_OK.  The plan is bound to that device. */
+mol_status mol_plan_create(const mol_desc *desc, mol_plan **plan);
+
+/* Frees the plan and its device memory (synchronises the device first). */
+mol_status mol_plan_destroy(mol_plan *plan);
+
+mol_status mol_plan_get_info(const mol_plan *plan, mol_plan_info *info);
+
+/* Device bytes mol_plan_create would allocate for this descriptor (workspace
+ * plus tables), not counting the caller's fields; 0 if the descriptor is
+ * invalid.  For admission by footprint. */
+size_t mol_workspace_bytes(const mol_desc *desc);
+
+/* Starting value (Sec. 3.2).  g == NULL (zero initial velocity):
+ * u1 = u0 + rhs(u0)/2, the even Taylor terms to order 2P with the spatial
+ * derivatives from the convolution operators.  g != NULL: MOL_E_UNSUPPORTED.
+ * u0 and u1 must not overlap. */
+mol_status mol_start(mol_plan *plan, const void *u0, const void *g, void *u1, void *stream);
+
+/* One step of the three-level scheme: u_next = 2 u_curr - u_prev + rhs(u_curr).
+ * u_next may alias u_prev (it is written after u_prev is read); it must not
+ * overlap u_curr. */
+mol_status mol_step(mol_plan *plan, const void *u_prev, const void *u_curr, void *u_next,
+                    void *stream);
+
+/* nsteps >= 0 steps in place: on entry (u_prev_io, u_curr_io) = (u^{n-1}, u^n),
+ * on return (u^{n+nsteps-1}, u^{n+nsteps}).  Unless MOL_NO_GRAPH is set, the
+ * step sequence is captured once in a hipGraph and replayed.  Asynchronous. */
+mol_status mol_solve(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
+                     void *stream);
+
+/* One step for each of count independent plans (serving): equivalent to
+ * mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream) for every i,
+ * with the sweeps of plans of the same dtype and direction fused into shared
+ * launches.  Plans must be distinct. */
+mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
+                          const void *const *u_curr, void *const *u_next, int count,
+                          void *stream);
+
+/* Single operators, for testing and composition.  in and out must not overlap. */
+typedef enum {
+    MOL_OP_LINV_X = 0, MOL_OP_LINV_Y = 1, MOL_OP_LINV_Z = 2, /* L_gamma^{-1} (eq. LD_gam) */
+    MOL_OP_D_X = 3, MOL_OP_D_Y = 4, MOL_OP_D_Z = 5,          /* D_gamma = 1 - L_gamma^{-1} */
+    MOL_OP_C = 6,           /* C (1D: D; 2D: eq. C_def_ADI; 3D: eq. C_def_ADI_3) */
+    MOL_OP_D = 7,           /* D (1D: D; 2D: eq. D_def_ADI; 3D: eq. D_def_ADI_3) */
+    MOL_OP_RHS = 8          /* sum_{p,m} c_{p,m} C^m D^{p-m} (eq. Full_2D) */
+} mol_op;
+mol_status mol_apply(mol_plan *plan, int op, const void *in, void *out, void *stream);
+
+/* Per-kernel timing of one step, for measurement tools.  Runs the kernels of
+ * mol_step(plan, u_prev, u_curr, u_next) reps times on the stream with a pair
+ * of hipEvents around every launch, synchronises, and writes for kernel i
+ * (i < min(count, max)) its mean duration in ms (ms[i]), its algorithmic
+ * bytes per launch (bytes[i]: every loaded and every written field streamed
+ * once), its sweep direction (dir[i], 0 = x) and its swept combinations
+ * (nsweep[i]).  Returns the kernel count of one step in *count.  Any array may
+ * be NULL.  Same aliasing rules as mol_step. */
+mol_status mol_profile_step(mol_plan *plan, const void *u_prev, const void *u_curr, void *u_next,
+                            int reps, void *stream, int max, double *ms, double *bytes,
+                            int *dir, int *nsweep, int *count);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *mol_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOLT_H */

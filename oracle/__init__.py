@@ -32,32 +32,36 @@ from .scheme import stage_coefficients, beta_max, A_p  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "molt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_LD = os.path.join(_HERE, "liboracle_ld.so")
 
 DIRICHLET = 0
 PERIODIC = 1
 
 
 def build(force: bool = False) -> str:
-    """Compile molt_oracle.c with gcc (FP64, -O2, OpenMP over lines)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile molt_oracle.c with gcc (-O2, OpenMP over lines): the FP64 oracle,
+    and the same source with 80-bit long double arithmetic (long-run reference)."""
+    for out, extra in ((_LIB, []), (_LIB_LD, ["-DOR_LONG_DOUBLE"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                                   *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, out)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(precision: str = "f64"):
+    """The oracle library: precision "f64" (double) or "ld" (x87 long double)."""
+    if precision not in _libs:
         build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.or_linv_line.argtypes = [ctypes.c_long, dp, dp, ctypes.c_double, dp, dp]
-        L.or_linv_periodic_line.argtypes = [ctypes.c_long, ctypes.c_double, dp, ctypes.c_double, dp]
+        L = ctypes.CDLL(_LIB if precision == "f64" else _LIB_LD)
+        rt = ctypes.c_double if precision == "f64" else ctypes.c_longdouble
+        dp = ctypes.POINTER(rt)
+        L.or_linv_line.argtypes = [ctypes.c_long, dp, dp, rt, dp, dp]
+        L.or_linv_periodic_line.argtypes = [ctypes.c_long, rt, dp, rt, dp]
         for name in ("or_apply_C", "or_apply_D"):
             getattr(L, name).argtypes = [ctypes.c_void_p, dp, dp]
         for name in ("or_apply_linv", "or_apply_Dg"):
@@ -68,13 +72,16 @@ def lib():
         L.or_run.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp, ctypes.c_long]
         L.or_num_threads.restype = ctypes.c_int
         L.or_count_get.restype = ctypes.c_long
-        _lib = L
-    return _lib
+        _libs[precision] = L
+    return _libs[precision]
 
 
 def _p(a: np.ndarray):
-    assert a.dtype == np.float64 and a.flags.c_contiguous
-    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert a.flags.c_contiguous
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert a.dtype == np.longdouble
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longdouble))
 
 
 def _check(rc: int) -> None:
@@ -102,7 +109,9 @@ class Problem:
     (seg_idx[n,3] int64, seg_th[n,2] float64) for embedded line objects
     (2D only), ``mask`` = uint8 inside indicator in the field's shape."""
 
-    def __init__(self, shape, h, bc, alpha, segments=None, mask=None):
+    def __init__(self, shape, h, bc, alpha, segments=None, mask=None, precision="f64"):
+        self.precision = precision
+        self.rt = np.float64 if precision == "f64" else np.longdouble
         shape = tuple(int(s) for s in shape)
         self.shape = shape
         self.ndim = len(shape)
@@ -140,59 +149,71 @@ class Problem:
         return ctypes.byref(self._s)
 
     def _io(self, v):
-        v = np.ascontiguousarray(v, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=self.rt)
         assert v.shape == self.shape, (v.shape, self.shape)
         return v, np.empty_like(v)
+
+    def _lib(self):
+        return lib(self.precision)
+
+    def _coef(self, P, beta):
+        if self.precision == "f64":
+            return np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
+        return np.ascontiguousarray(scheme.stage_coefficients_ld(P, beta))
+
+    @staticmethod
+    def _out(a):
+        return np.asarray(a, dtype=np.float64)
 
     def linv(self, v, axis):
         """L_gamma^{-1} along grid axis ``axis`` (0 = x, 1 = y, 2 = z)."""
         v, out = self._io(v)
-        _check(lib().or_apply_linv(self.ref, axis, _p(v), _p(out)))
-        return out
+        _check(self._lib().or_apply_linv(self.ref, axis, _p(v), _p(out)))
+        return self._out(out)
 
     def Dg(self, v, axis):
         """D_gamma = 1 - L_gamma^{-1} (eq. LD_gam)."""
         v, out = self._io(v)
-        _check(lib().or_apply_Dg(self.ref, axis, _p(v), _p(out)))
-        return out
+        _check(self._lib().or_apply_Dg(self.ref, axis, _p(v), _p(out)))
+        return self._out(out)
 
     def C(self, v):
         v, out = self._io(v)
-        _check(lib().or_apply_C(self.ref, _p(v), _p(out)))
-        return out
+        _check(self._lib().or_apply_C(self.ref, _p(v), _p(out)))
+        return self._out(out)
 
     def D(self, v):
         v, out = self._io(v)
-        _check(lib().or_apply_D(self.ref, _p(v), _p(out)))
-        return out
+        _check(self._lib().or_apply_D(self.ref, _p(v), _p(out)))
+        return self._out(out)
 
     def rhs(self, u, P, beta):
         u, out = self._io(u)
-        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
-        _check(lib().or_rhs(self.ref, P, _p(c), _p(u), _p(out)))
-        return out
+        c = self._coef(P, beta)
+        _check(self._lib().or_rhs(self.ref, P, _p(c), _p(u), _p(out)))
+        return self._out(out)
 
     def step(self, u_prev, u_curr, P, beta):
         u_prev, _ = self._io(u_prev)
         u_curr, out = self._io(u_curr)
-        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
-        _check(lib().or_step(self.ref, P, _p(c), _p(u_prev), _p(u_curr), _p(out)))
-        return out
+        c = self._coef(P, beta)
+        _check(self._lib().or_step(self.ref, P, _p(c), _p(u_prev), _p(u_curr), _p(out)))
+        return self._out(out)
 
     def start(self, u0, P, beta):
         u0, out = self._io(u0)
-        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
-        _check(lib().or_start(self.ref, P, _p(c), _p(u0), _p(out)))
-        return out
+        c = self._coef(P, beta)
+        _check(self._lib().or_start(self.ref, P, _p(c), _p(u0), _p(out)))
+        return self._out(out)
 
     def run(self, u_prev, u_curr, nsteps, P, beta):
         """Returns (u^{n+nsteps-1}, u^{n+nsteps})."""
-        a = np.array(u_prev, dtype=np.float64, order="C", copy=True)
-        b = np.array(u_curr, dtype=np.float64, order="C", copy=True)
+        a = np.array(u_prev, dtype=self.rt, order="C", copy=True)
+        b = np.array(u_curr, dtype=self.rt, order="C", copy=True)
         assert a.shape == self.shape and b.shape == self.shape
-        c = np.ascontiguousarray(stage_coefficients(P, beta), dtype=np.float64)
-        _check(lib().or_run(self.ref, P, _p(c), _p(a), _p(b), int(nsteps)))
-        return a, b
+        c = self._coef(P, beta)
+        _check(self._lib().or_run(self.ref, P, _p(c), _p(a), _p(b), int(nsteps)))
+        return self._out(a), self._out(b)
 
 
 def linv_line(x, v, alpha, bnd=None):
@@ -201,14 +222,14 @@ def linv_line(x, v, alpha, bnd=None):
     v = np.ascontiguousarray(v, dtype=np.float64)
     w = np.empty_like(v)
     b = np.ascontiguousarray(bnd if bnd is not None else (0.0, 0.0, 0.0, 0.0), dtype=np.float64)
-    _check(lib().or_linv_line(len(x) - 1, _p(x), _p(v), float(alpha), _p(b), _p(w)))
+    _check(lib("f64").or_linv_line(len(x) - 1, _p(x), _p(v), float(alpha), _p(b), _p(w)))
     return w
 
 
 def linv_periodic_line(v, h, alpha):
     v = np.ascontiguousarray(v, dtype=np.float64)
     w = np.empty_like(v)
-    _check(lib().or_linv_periodic_line(len(v), float(h), _p(v), float(alpha), _p(w)))
+    _check(lib("f64").or_linv_periodic_line(len(v), float(h), _p(v), float(alpha), _p(w)))
     return w
 
 

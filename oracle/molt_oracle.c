@@ -44,6 +44,21 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Real type of the arithmetic: double by default.  The same source is also
+   built with OR_LONG_DOUBLE (x87 80-bit) for long multi-step references, where
+   the literal D = v - L^{-1} v loses digits to cancellation on smooth data. */
+#ifdef OR_LONG_DOUBLE
+typedef long double real;
+#define R_EXP expl
+#define R_EXPM1 expm1l
+#define R_FABS fabsl
+#else
+typedef double real;
+#define R_EXP exp
+#define R_EXPM1 expm1
+#define R_FABS fabs
+#endif
+
 #define OR_OK 0
 /* number of applications of C or D since the last reset (Table 2 count) */
 static long or_napply = 0;
@@ -56,22 +71,22 @@ long or_count_get(void) { return or_napply; }
 /* Moments M_k(nu) = int_0^1 z^k e^{-nu z} dz, k = 0, 1, 2.                  */
 /* Power series below nu = 2 (no cancellation), closed form above.           */
 /* ------------------------------------------------------------------------ */
-static void or_moments(double nu, double M[3])
+static void or_moments(real nu, real M[3])
 {
     if (nu < 2.0) {
         for (int k = 0; k < 3; ++k) {
             /* sum_{n>=0} (-nu)^n / (n! (n+k+1)) */
-            double term = 1.0, s = 0.0;
+            real term = 1.0, s = 0.0;
             for (int n = 0; n < 80; ++n) {
-                double c = term / (double)(n + k + 1);
+                real c = term / (real)(n + k + 1);
                 s += c;
-                if (fabs(c) < 1e-300 || (n > 4 && fabs(c) < 1e-19 * fabs(s))) break;
-                term *= -nu / (double)(n + 1);
+                if (R_FABS(c) < 1e-300 || (n > 4 && R_FABS(c) < 1e-19 * R_FABS(s))) break;
+                term *= -nu / (real)(n + 1);
             }
             M[k] = s;
         }
     } else {
-        double e = exp(-nu);
+        real e = R_EXP(-nu);
         M[0] = (1.0 - e) / nu;
         M[1] = (1.0 - e * (1.0 + nu)) / (nu * nu);
         M[2] = (2.0 - e * (2.0 + 2.0 * nu + nu * nu)) / (nu * nu * nu);
@@ -79,10 +94,10 @@ static void or_moments(double nu, double M[3])
 }
 
 /* Quadratic q(t) = v0 + b t + c t^2 around node x_j (t = y - x_j). */
-typedef struct { double v0, b, c; } or_quad;
+typedef struct { real v0, b, c; } or_quad;
 
 /* Through (-hl, vm), (0, v0), (hr, vp). */
-static or_quad or_quad3(double vm, double v0, double vp, double hl, double hr)
+static or_quad or_quad3(real vm, real v0, real vp, real hl, real hr)
 {
     or_quad q;
     q.v0 = v0;
@@ -92,7 +107,7 @@ static or_quad or_quad3(double vm, double v0, double vp, double hl, double hr)
 }
 
 /* Left end node: through (0, v0), (hr, vp) with prescribed curvature q'' = kap. */
-static or_quad or_quad_left_end(double v0, double vp, double hr, double kap)
+static or_quad or_quad_left_end(real v0, real vp, real hr, real kap)
 {
     or_quad q;
     q.v0 = v0;
@@ -102,7 +117,7 @@ static or_quad or_quad_left_end(double v0, double vp, double hr, double kap)
 }
 
 /* Right end node: through (-hl, vm), (0, v0) with prescribed curvature kap. */
-static or_quad or_quad_right_end(double vm, double v0, double hl, double kap)
+static or_quad or_quad_right_end(real vm, real v0, real hl, real kap)
 {
     or_quad q;
     q.v0 = v0;
@@ -112,17 +127,17 @@ static or_quad or_quad_right_end(double vm, double v0, double hl, double kap)
 }
 
 /* J^L_j = (alpha/2) int_{x_j - hl}^{x_j} e^{-alpha (x_j - y)} q(y - x_j) dy  */
-static double or_JL(or_quad q, double alpha, double hl)
+static real or_JL(or_quad q, real alpha, real hl)
 {
-    double nu = alpha * hl, M[3];
+    real nu = alpha * hl, M[3];
     or_moments(nu, M);
     return 0.5 * nu * (q.v0 * M[0] - q.b * hl * M[1] + q.c * hl * hl * M[2]);
 }
 
 /* J^R_j = (alpha/2) int_{x_j}^{x_j + hr} e^{-alpha (y - x_j)} q(y - x_j) dy  */
-static double or_JR(or_quad q, double alpha, double hr)
+static real or_JR(or_quad q, real alpha, real hr)
 {
-    double nu = alpha * hr, M[3];
+    real nu = alpha * hr, M[3];
     or_moments(nu, M);
     return 0.5 * nu * (q.v0 * M[0] + q.b * hr * M[1] + q.c * hr * hr * M[2]);
 }
@@ -133,44 +148,44 @@ static double or_JR(or_quad q, double alpha, double hr)
  * two ends and the curvature of the data at the two ends (all 0 for
  * homogeneous Dirichlet data).  Writes w[0..m] = L^{-1} v.
  */
-int or_linv_line(long m, const double *x, const double *v, double alpha,
-                 const double *bnd, double *w)
+int or_linv_line(long m, const real *x, const real *v, real alpha,
+                 const real *bnd, real *w)
 {
     if (m < 1 || alpha <= 0.0) return OR_EINVAL;
-    double ta = bnd ? bnd[0] : 0.0, tb = bnd ? bnd[1] : 0.0;
-    double ka = bnd ? bnd[2] : 0.0, kb = bnd ? bnd[3] : 0.0;
-    double *IL = (double *)malloc(sizeof(double) * (size_t)(m + 1));
-    double *IR = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+    real ta = bnd ? bnd[0] : 0.0, tb = bnd ? bnd[1] : 0.0;
+    real ka = bnd ? bnd[2] : 0.0, kb = bnd ? bnd[3] : 0.0;
+    real *IL = (real *)malloc(sizeof(real) * (size_t)(m + 1));
+    real *IR = (real *)malloc(sizeof(real) * (size_t)(m + 1));
     if (!IL || !IR) { free(IL); free(IR); return OR_ENOMEM; }
 
     /* local quadratics, one per node */
     /* left-to-right recurrence: I^L_0 = 0, I^L_j = e^{-alpha h_j} I^L_{j-1} + J^L_j */
     IL[0] = 0.0;
     for (long j = 1; j <= m; ++j) {
-        double hl = x[j] - x[j - 1];
+        real hl = x[j] - x[j - 1];
         or_quad q = (j < m) ? or_quad3(v[j - 1], v[j], v[j + 1], hl, x[j + 1] - x[j])
                             : or_quad_right_end(v[j - 1], v[j], hl, kb);
-        IL[j] = exp(-alpha * hl) * IL[j - 1] + or_JL(q, alpha, hl);
+        IL[j] = R_EXP(-alpha * hl) * IL[j - 1] + or_JL(q, alpha, hl);
     }
     /* right-to-left recurrence: I^R_m = 0, I^R_j = e^{-alpha h_{j+1}} I^R_{j+1} + J^R_j */
     IR[m] = 0.0;
     for (long j = m - 1; j >= 0; --j) {
-        double hr = x[j + 1] - x[j];
+        real hr = x[j + 1] - x[j];
         or_quad q = (j > 0) ? or_quad3(v[j - 1], v[j], v[j + 1], x[j] - x[j - 1], hr)
                             : or_quad_left_end(v[j], v[j + 1], hr, ka);
-        IR[j] = exp(-alpha * hr) * IR[j + 1] + or_JR(q, alpha, hr);
+        IR[j] = R_EXP(-alpha * hr) * IR[j + 1] + or_JR(q, alpha, hr);
     }
     /* boundary correction: w = I^L + I^R + A e^{-alpha(x-a)} + B e^{-alpha(b-x)}
        with w(a) = ta, w(b) = tb */
-    double len = x[m] - x[0];
-    double mu = exp(-alpha * len);
-    double one_m_mu2 = -expm1(-2.0 * alpha * len);
-    double ra = ta - IR[0];            /* I^L_0 = 0 */
-    double rb = tb - IL[m];            /* I^R_m = 0 */
-    double A = (ra - mu * rb) / one_m_mu2;
-    double B = (rb - mu * ra) / one_m_mu2;
+    real len = x[m] - x[0];
+    real mu = R_EXP(-alpha * len);
+    real one_m_mu2 = -R_EXPM1(-2.0 * alpha * len);
+    real ra = ta - IR[0];            /* I^L_0 = 0 */
+    real rb = tb - IL[m];            /* I^R_m = 0 */
+    real A = (ra - mu * rb) / one_m_mu2;
+    real B = (rb - mu * ra) / one_m_mu2;
     for (long j = 0; j <= m; ++j)
-        w[j] = IL[j] + IR[j] + A * exp(-alpha * (x[j] - x[0])) + B * exp(-alpha * (x[m] - x[j]));
+        w[j] = IL[j] + IR[j] + A * R_EXP(-alpha * (x[j] - x[0])) + B * R_EXP(-alpha * (x[m] - x[j]));
     free(IL);
     free(IR);
     return OR_OK;
@@ -181,25 +196,25 @@ int or_linv_line(long m, const double *x, const double *v, double alpha,
  * n h).  The convolution of the periodic extension: contributions from the
  * earlier images form a geometric series with ratio e^{-alpha n h}.
  */
-int or_linv_periodic_line(long n, double h, const double *v, double alpha, double *w)
+int or_linv_periodic_line(long n, real h, const real *v, real alpha, real *w)
 {
     if (n < 3 || alpha <= 0.0 || h <= 0.0) return OR_EINVAL;
-    double *JL = (double *)malloc(sizeof(double) * (size_t)n);
-    double *JR = (double *)malloc(sizeof(double) * (size_t)n);
-    double *IL = (double *)malloc(sizeof(double) * (size_t)n);
-    double *IR = (double *)malloc(sizeof(double) * (size_t)n);
+    real *JL = (real *)malloc(sizeof(real) * (size_t)n);
+    real *JR = (real *)malloc(sizeof(real) * (size_t)n);
+    real *IL = (real *)malloc(sizeof(real) * (size_t)n);
+    real *IR = (real *)malloc(sizeof(real) * (size_t)n);
     if (!JL || !JR || !IL || !IR) { free(JL); free(JR); free(IL); free(IR); return OR_ENOMEM; }
     for (long j = 0; j < n; ++j) {
         or_quad q = or_quad3(v[(j - 1 + n) % n], v[j], v[(j + 1) % n], h, h);
         JL[j] = or_JL(q, alpha, h);
         JR[j] = or_JR(q, alpha, h);
     }
-    double d = exp(-alpha * h);
-    double one_m_mu = -expm1(-alpha * h * (double)n);
+    real d = R_EXP(-alpha * h);
+    real one_m_mu = -R_EXPM1(-alpha * h * (real)n);
     /* I^L at the last node: all images to the left, summed geometrically */
-    double s = 0.0, dk = 1.0;
+    real s = 0.0, dk = 1.0;
     for (long k = 0; k < n; ++k) { s += dk * JL[n - 1 - k]; dk *= d; }
-    double prev = s / one_m_mu;
+    real prev = s / one_m_mu;
     for (long j = 0; j < n; ++j) { IL[j] = d * prev + JL[j]; prev = IL[j]; }
     /* I^R at the first node: all images to the right */
     s = 0.0; dk = 1.0;
@@ -249,7 +264,7 @@ static long or_stride(const or_problem *pb, int dir)
 }
 
 /* L_gamma^{-1} along axis dir for every line of the grid. */
-int or_apply_linv(const or_problem *pb, int dir, const double *in, double *out)
+int or_apply_linv(const or_problem *pb, int dir, const real *in, real *out)
 {
     if (!pb || dir < 0 || dir >= pb->ndim) return OR_EINVAL;
     long N = or_npts(pb), nl = pb->n[dir], st = or_stride(pb, dir);
@@ -257,7 +272,7 @@ int or_apply_linv(const or_problem *pb, int dir, const double *in, double *out)
     int rc = OR_OK;
     if (pb->nseg[dir] > 0) {
         /* embedded: only line objects carry values; everything else is 0 */
-        memset(out, 0, sizeof(double) * (size_t)N);
+        memset(out, 0, sizeof(real) * (size_t)N);
         if (pb->ndim != 2) return OR_EINVAL;
         long other = 1 - dir;
         long so = or_stride(pb, (int)other);
@@ -266,19 +281,19 @@ int or_apply_linv(const or_problem *pb, int dir, const double *in, double *out)
         for (long s = 0; s < nseg; ++s) {
             long line = pb->seg_idx[dir][3 * s], i0 = pb->seg_idx[dir][3 * s + 1];
             long i1 = pb->seg_idx[dir][3 * s + 2];
-            double tl = pb->seg_th[dir][2 * s], tr = pb->seg_th[dir][2 * s + 1];
+            real tl = (real)pb->seg_th[dir][2 * s], tr = (real)pb->seg_th[dir][2 * s + 1];
             long m = (i1 - i0) + 2; /* nodes: boundary, i0..i1, boundary */
-            double *x = (double *)malloc(sizeof(double) * (size_t)(m + 1));
-            double *v = (double *)malloc(sizeof(double) * (size_t)(m + 1));
-            double *w = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+            real *x = (real *)malloc(sizeof(real) * (size_t)(m + 1));
+            real *v = (real *)malloc(sizeof(real) * (size_t)(m + 1));
+            real *w = (real *)malloc(sizeof(real) * (size_t)(m + 1));
             if (!x || !v || !w) { free(x); free(v); free(w); rc |= OR_ENOMEM; continue; }
-            double hh = pb->h[dir];
-            x[0] = ((double)i0 - tl) * hh; v[0] = 0.0;
+            real hh = pb->h[dir];
+            x[0] = ((real)i0 - tl) * hh; v[0] = 0.0;
             for (long i = i0; i <= i1; ++i) {
-                x[i - i0 + 1] = (double)i * hh;
+                x[i - i0 + 1] = (real)i * hh;
                 v[i - i0 + 1] = in[line * so + i * st];
             }
-            x[m] = ((double)i1 + tr) * hh; v[m] = 0.0;
+            x[m] = ((real)i1 + tr) * hh; v[m] = 0.0;
             rc |= or_linv_line(m, x, v, pb->alpha, NULL, w);
             for (long i = i0; i <= i1; ++i) out[line * so + i * st] = w[i - i0 + 1];
             free(x); free(v); free(w);
@@ -290,12 +305,12 @@ int or_apply_linv(const or_problem *pb, int dir, const double *in, double *out)
         /* base offset of line L: index with axis dir removed */
         long lo = L % st, hi = L / st;
         long base = hi * st * nl + lo;
-        double *x = (double *)malloc(sizeof(double) * (size_t)nl);
-        double *v = (double *)malloc(sizeof(double) * (size_t)nl);
-        double *w = (double *)malloc(sizeof(double) * (size_t)nl);
+        real *x = (real *)malloc(sizeof(real) * (size_t)nl);
+        real *v = (real *)malloc(sizeof(real) * (size_t)nl);
+        real *w = (real *)malloc(sizeof(real) * (size_t)nl);
         if (!x || !v || !w) { free(x); free(v); free(w); rc |= OR_ENOMEM; continue; }
         for (long i = 0; i < nl; ++i) {
-            x[i] = (double)i * pb->h[dir];
+            x[i] = (real)i * pb->h[dir];
             v[i] = in[base + i * st];
         }
         if (pb->bc[dir] == 1) {
@@ -311,7 +326,7 @@ int or_apply_linv(const or_problem *pb, int dir, const double *in, double *out)
 }
 
 /* Zero every node that is not an unknown: Dirichlet end nodes, outside nodes. */
-static void or_project(const or_problem *pb, double *f)
+static void or_project(const or_problem *pb, real *f)
 {
     long N = or_npts(pb);
     if (pb->mask) {
@@ -328,12 +343,12 @@ static void or_project(const or_problem *pb, double *f)
 }
 
 /* D_gamma v = v - L_gamma^{-1} v (eq. LD_gam) */
-int or_apply_Dg(const or_problem *pb, int dir, const double *in, double *out)
+int or_apply_Dg(const or_problem *pb, int dir, const real *in, real *out)
 {
     long N = or_npts(pb);
-    double *t = (double *)malloc(sizeof(double) * (size_t)N);
+    real *t = (real *)malloc(sizeof(real) * (size_t)N);
     if (!t) return OR_ENOMEM;
-    memcpy(t, in, sizeof(double) * (size_t)N);
+    memcpy(t, in, sizeof(real) * (size_t)N);
     or_project(pb, t);
     int rc = or_apply_linv(pb, dir, t, out);
     for (long i = 0; i < N; ++i) out[i] = t[i] - out[i];
@@ -346,14 +361,14 @@ int or_apply_Dg(const or_problem *pb, int dir, const double *in, double *out)
  * 3D: C_xyz = L_y^{-1}L_z^{-1} D_x + L_z^{-1}L_x^{-1} D_y + L_x^{-1}L_y^{-1} D_z
  * (eq. C_def_ADI_3).  The rightmost operator of each product acts first.
  */
-int or_apply_C(const or_problem *pb, const double *in, double *out)
+int or_apply_C(const or_problem *pb, const real *in, real *out)
 {
     long N = or_npts(pb);
     int rc = OR_OK;
     ++or_napply;
     if (pb->ndim == 1) return or_apply_Dg(pb, 0, in, out);
-    double *a = (double *)malloc(sizeof(double) * (size_t)N);
-    double *b = (double *)malloc(sizeof(double) * (size_t)N);
+    real *a = (real *)malloc(sizeof(real) * (size_t)N);
+    real *b = (real *)malloc(sizeof(real) * (size_t)N);
     if (!a || !b) { free(a); free(b); return OR_ENOMEM; }
     if (pb->ndim == 2) {
         rc |= or_apply_Dg(pb, 0, in, a);     /* D_x v */
@@ -362,7 +377,7 @@ int or_apply_C(const or_problem *pb, const double *in, double *out)
         rc |= or_apply_linv(pb, 0, a, b);    /* L_x^{-1} D_y v */
         for (long i = 0; i < N; ++i) out[i] += b[i];
     } else {
-        memset(out, 0, sizeof(double) * (size_t)N);
+        memset(out, 0, sizeof(real) * (size_t)N);
         /* term gamma: L_{g2}^{-1} L_{g1}^{-1} D_gamma with (gamma, g1, g2) =
            (x, z, y), (y, x, z), (z, y, x) following the printed products */
         const int g[3][3] = {{0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
@@ -379,16 +394,16 @@ int or_apply_C(const or_problem *pb, const double *in, double *out)
 
 /* D: 1D: D.  2D: D_xy = 1 - L_x^{-1} L_y^{-1} (eq. D_def_ADI).
    3D: D_xyz = 1 - L_x^{-1} L_y^{-1} L_z^{-1} (eq. D_def_ADI_3). */
-int or_apply_D(const or_problem *pb, const double *in, double *out)
+int or_apply_D(const or_problem *pb, const real *in, real *out)
 {
     long N = or_npts(pb);
     int rc = OR_OK;
     ++or_napply;
     if (pb->ndim == 1) return or_apply_Dg(pb, 0, in, out);
-    double *t = (double *)malloc(sizeof(double) * (size_t)N);
-    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    real *t = (real *)malloc(sizeof(real) * (size_t)N);
+    real *a = (real *)malloc(sizeof(real) * (size_t)N);
     if (!t || !a) { free(t); free(a); return OR_ENOMEM; }
-    memcpy(t, in, sizeof(double) * (size_t)N);
+    memcpy(t, in, sizeof(real) * (size_t)N);
     or_project(pb, t);
     if (pb->ndim == 2) {
         rc |= or_apply_linv(pb, 1, t, a);
@@ -397,7 +412,7 @@ int or_apply_D(const or_problem *pb, const double *in, double *out)
         rc |= or_apply_linv(pb, 2, t, a);
         rc |= or_apply_linv(pb, 1, a, out);
         rc |= or_apply_linv(pb, 0, out, a);
-        memcpy(out, a, sizeof(double) * (size_t)N);
+        memcpy(out, a, sizeof(real) * (size_t)N);
     }
     for (long i = 0; i < N; ++i) out[i] = t[i] - out[i];
     free(t); free(a);
@@ -413,16 +428,16 @@ int or_apply_D(const or_problem *pb, const double *in, double *out)
  * weighted by c_{p,m} = (-1)^m 2 beta^{2m}/(2m)! binom(p-1, m-1).
  * coef[(p-1)*P + (m-1)] = c_{p,m}, supplied by the caller.
  */
-int or_rhs(const or_problem *pb, int P, const double *coef, const double *u, double *rhs)
+int or_rhs(const or_problem *pb, int P, const real *coef, const real *u, real *rhs)
 {
     if (P < 1) return OR_EINVAL;
     long N = or_npts(pb);
     int rc = OR_OK;
-    double **v = (double **)calloc((size_t)P, sizeof(double *));
-    double *t = (double *)malloc(sizeof(double) * (size_t)N);
+    real **v = (real **)calloc((size_t)P, sizeof(real *));
+    real *t = (real *)malloc(sizeof(real) * (size_t)N);
     if (!v || !t) { free(v); free(t); return OR_ENOMEM; }
     for (int k = 0; k < P; ++k) {
-        v[k] = (double *)malloc(sizeof(double) * (size_t)N);
+        v[k] = (real *)malloc(sizeof(real) * (size_t)N);
         if (!v[k]) rc = OR_ENOMEM;
     }
     if (rc) goto done;
@@ -432,10 +447,10 @@ int or_rhs(const or_problem *pb, int P, const double *coef, const double *u, dou
         rc |= or_apply_D(pb, v[p - 2], v[p - 1]);
         for (int k = p - 1; k >= 1; --k) {
             rc |= or_apply_C(pb, v[k - 1], t);
-            memcpy(v[k - 1], t, sizeof(double) * (size_t)N);
+            memcpy(v[k - 1], t, sizeof(real) * (size_t)N);
         }
         for (int k = 1; k <= p; ++k) {
-            double c = coef[(p - 1) * P + (p + 1 - k) - 1];
+            real c = coef[(p - 1) * P + (p + 1 - k) - 1];
             for (long i = 0; i < N; ++i) rhs[i] += c * v[k - 1][i];
         }
     }
@@ -446,11 +461,11 @@ done:
 }
 
 /* u^{n+1} = 2u^n - u^{n-1} + rhs(u^n)   (eq. Full_2D, left-hand side) */
-int or_step(const or_problem *pb, int P, const double *coef, const double *u_prev,
-            const double *u_curr, double *u_next)
+int or_step(const or_problem *pb, int P, const real *coef, const real *u_prev,
+            const real *u_curr, real *u_next)
 {
     long N = or_npts(pb);
-    double *r = (double *)malloc(sizeof(double) * (size_t)N);
+    real *r = (real *)malloc(sizeof(real) * (size_t)N);
     if (!r) return OR_ENOMEM;
     int rc = or_rhs(pb, P, coef, u_curr, r);
     for (long i = 0; i < N; ++i) u_next[i] = 2.0 * u_curr[i] - u_prev[i] + r[i];
@@ -462,10 +477,10 @@ int or_step(const or_problem *pb, int P, const double *coef, const double *u_pre
 /* Starting value for zero initial velocity (Sec. 3.2): u^1 = u^0 + rhs(u^0)/2,
    the even Taylor terms up to order 2P with the spatial derivatives built from
    the same convolution operators. */
-int or_start(const or_problem *pb, int P, const double *coef, const double *u0, double *u1)
+int or_start(const or_problem *pb, int P, const real *coef, const real *u0, real *u1)
 {
     long N = or_npts(pb);
-    double *r = (double *)malloc(sizeof(double) * (size_t)N);
+    real *r = (real *)malloc(sizeof(real) * (size_t)N);
     if (!r) return OR_ENOMEM;
     int rc = or_rhs(pb, P, coef, u0, r);
     for (long i = 0; i < N; ++i) u1[i] = u0[i] + 0.5 * r[i];
@@ -476,17 +491,17 @@ int or_start(const or_problem *pb, int P, const double *coef, const double *u0, 
 
 /* nsteps of the three-level scheme; on return u_prev/u_curr hold
    (u^{n+nsteps-1}, u^{n+nsteps}). */
-int or_run(const or_problem *pb, int P, const double *coef, double *u_prev, double *u_curr,
+int or_run(const or_problem *pb, int P, const real *coef, real *u_prev, real *u_curr,
            long nsteps)
 {
     long N = or_npts(pb);
-    double *nx = (double *)malloc(sizeof(double) * (size_t)N);
+    real *nx = (real *)malloc(sizeof(real) * (size_t)N);
     if (!nx) return OR_ENOMEM;
     int rc = OR_OK;
     for (long s = 0; s < nsteps && rc == OR_OK; ++s) {
         rc = or_step(pb, P, coef, u_prev, u_curr, nx);
-        memcpy(u_prev, u_curr, sizeof(double) * (size_t)N);
-        memcpy(u_curr, nx, sizeof(double) * (size_t)N);
+        memcpy(u_prev, u_curr, sizeof(real) * (size_t)N);
+        memcpy(u_curr, nx, sizeof(real) * (size_t)N);
     }
     free(nx);
     return rc;

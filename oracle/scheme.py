@@ -43,6 +43,19 @@ def stage_coefficients(P: int, beta: float) -> np.ndarray:
     return c
 
 
+def stage_coefficients_ld(P: int, beta: float) -> np.ndarray:
+    """c_{p,m} in extended precision (numpy longdouble) for the 80-bit build;
+    beta is taken as the exact binary value of the given double."""
+    c = np.zeros((P, P), dtype=np.longdouble)
+    b = Fraction(float(beta))
+    for p in range(1, P + 1):
+        for m in range(1, p + 1):
+            q = c_pm(p, m, b)
+            with mp.workdps(40):
+                c[p - 1, m - 1] = np.longdouble(mp.nstr(mp.mpf(q.numerator) / q.denominator, 30))
+    return c
+
+
 def stability_S(P: int, beta, Dhat):
     """S(beta, Dhat) = -sum_{p<=P} A_p(beta) Dhat^p (eq. Stab_sum)."""
     return -sum(A_p(p, beta) * Dhat ** p for p in range(1, P + 1))

@@ -1,0 +1,849 @@
+// Directional sweep kernels for gfx950: the O(N) recursive convolution
+// L_gamma^{-1} (Sec. 2: characteristic split I^L + I^R, each an exponential
+// recurrence with decay e^{-alpha h}, local integrals over one cell against the
+// quadratic through three nodes, then the boundary correction
+// A e^{-alpha(x-a)} + B e^{-alpha(b-x)}) applied along x, y or z lines, with
+// D_gamma = 1 - L_gamma^{-1} (Sec. 4, eq. LD_gam) emitted directly.
+//
+// Formulation used on the device.  With E = I - v/2 the recurrences are forced
+// only by differences of the data,
+//   E^L_p = d E^L_{p-1} + w2 (v_{p+1} - 2 v_p + v_{p-1}) - g (v_p - v_{p-1}),
+//   E^R_p = d E^R_{p+1} + w2 (v_{p+1} - 2 v_p + v_{p-1}) + g (v_{p+1} - v_p),
+//   D v_p = -(E^L_p + E^R_p + A d^p + B d^{M-p}),
+// (d = e^{-nu}, g = (1-d)/(2 nu), nu = alpha h), which is the same discrete
+// operator as I^L + I^R (exact in real arithmetic) but never forms v - L^{-1} v,
+// so D keeps full relative precision in FP32.  At a Dirichlet end node the
+// curvature term is dropped (the data's curvature there is 0 for homogeneous
+// boundary values, Sec. 3.2).
+//
+// Each launch computes up to MAXS swept combinations s_k = sum_f mS[k][f] F_f
+// of up to MAXF loaded fields and writes up to MAXO outputs
+// out_o = sum_f mOF[o][f] F_f + sum_k mOD[o][k] D(s_k): the ADI compositions
+// (eqs. C_def_ADI, D_def_ADI, ...) and the time update are fused this way.
+//
+// x lines (contiguous): one workgroup per line, the line staged through LDS
+// (coalesced vector loads, padded to avoid bank conflicts), every lane runs
+// the recurrences over S consecutive nodes, lane carries are combined by a
+// wave-level scan of the linear recurrence (multiplier d^S) and waves through
+// LDS: exact.
+//
+// y / z lines (strided): lanes own consecutive columns (coalesced rows), waves
+// of a workgroup stack along the line, each lane runs S nodes, wave carries
+// are scanned through LDS.  Lines longer than one tile of W*S nodes are split
+// into tiles; the carry entering a tile is the truncated sum over a halo of
+// K nodes with d^K below the dtype's rounding (the exponential decay of the
+// Green's function), computed cooperatively by all waves of the tile.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "molt_internal.h"
+
+namespace molt {
+
+template <typename T>
+struct KArgs {
+    const T *f[MAXF];
+    T *o[MAXO];
+    T mS[MAXS][MAXF];
+    T mOF[MAXO][MAXF];
+    T mOD[MAXO][MAXS];
+    int nf;
+    int proj;
+    int64_t n;        // nodes per line
+    int64_t nlines;   // x: lines; strided: columns (x extent)
+    int64_t lineoff;  // x: element offset between lines
+    int64_t ls;       // strided: stride between nodes of a line
+    int64_t os;       // strided: stride of the outer index
+    int64_t nouter;   // strided: outer extent
+    int64_t nblocks;  // strided: total workgroups (XCD remap)
+    int ntiles;       // strided: tiles per line
+    int halo;         // strided: halo nodes per side
+    int aligned;      // x: vector loads allowed
+    int periodic;     // along the sweep
+    T d, g, w2;
+    T dS;             // d^S
+    T dBlk;           // x: d^{64 S} (one wave of lanes)
+    double nu;
+    double K00, K01, K10, K11;
+    // projection: line index = (i1 in [0,pn1), i2 in [0,pn2)); Dirichlet flags
+    int64_t pn1, pn2;
+    int pd1, pd2;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t N)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
+    // contiguous range of logical tiles so that neighbouring tiles of a line
+    // (which read each other's halo) share one L2.
+    const int64_t X = 8;
+    int64_t x = i % X, local = i / X;
+    int64_t per = N / X, rem = N % X;
+    return x * per + (x < rem ? x : rem) + local;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_up(T v, int off) { return __shfl_up(v, off, 64); }
+template <typename T>
+__device__ __forceinline__ T shfl_down(T v, int off) { return __shfl_down(v, off, 64); }
+
+// Forcing of the two recurrences at node p from its neighbours vm, v0, vp
+// (end and outside nodes already read as 0).  Dirichlet end nodes drop the
+// curvature term; E^L starts at node 0 and E^R at node M.
+template <typename T>
+__device__ __forceinline__ T force_L(T vm, T v0, T vp, int p, int M, bool dir_end, T g, T w2)
+{
+    if (dir_end) {
+        if (p <= 0 || p > M) return T(0);
+        if (p == M) return -g * (v0 - vm);
+    } else if (p > M) {
+        return T(0);
+    }
+    return w2 * ((vp - v0) - (v0 - vm)) - g * (v0 - vm);
+}
+template <typename T>
+__device__ __forceinline__ T force_R(T vm, T v0, T vp, int p, int M, bool dir_end, T g, T w2)
+{
+    if (dir_end) {
+        if (p < 0 || p >= M) return T(0);
+        if (p == 0) return g * (vp - v0);
+    } else if (p > M) {
+        return T(0);
+    }
+    return w2 * ((vp - v0) - (v0 - vm)) + g * (vp - v0);
+}
+
+// Local recurrences over S nodes p0..p0+S-1 from the values v[0..S+1] of
+// nodes p0-1..p0+S.  sum[j] = local E^L + local E^R (zero carry-in at both
+// segment ends); aL = local E^L at the last node, aR = local E^R at the first
+// node, eLM = local E^L at node M if this segment holds it.
+template <typename T, int S>
+__device__ __forceinline__ void seg_recur(const T (&v)[S + 2], int p0, int M, bool dir_end, T d,
+                                          T g, T w2, T (&sum)[S], T &aL, T &aR, T &eLM)
+{
+    T e = T(0);
+    eLM = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        e = d * e + force_L(v[j], v[j + 1], v[j + 2], p, M, dir_end, g, w2);
+        sum[j] = e;
+        if (p == M) eLM = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        e = d * e + force_R(v[j], v[j + 1], v[j + 2], p0 + j, M, dir_end, g, w2);
+        sum[j] += e;
+    }
+    aR = e;
+}
+
+// In place: sum[j] <- D_j = -(sum[j] + d^{j+1} cL + d^{S-j} cR + A d^p + B d^{M-p}),
+// p = p0 + j; zero beyond the line and at Dirichlet end nodes.  A, B in FP64.
+template <typename T, int S>
+__device__ __forceinline__ void seg_close(T (&sum)[S], T cL, T cR, double A, double B, int p0,
+                                          int M, double nu, T d, bool dir_end)
+{
+    const double dd = exp(-nu);
+    double ta = (A != 0.0) ? A * exp(-nu * (double)p0) : 0.0;
+    T ldec = d * cL;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        sum[j] += (T)ta + ldec;
+        ta *= dd;
+        ldec *= d;
+    }
+    const int rem = M - p0;
+    const int jmax = (rem >= S - 1) ? (S - 1) : rem;
+    double tb = (B != 0.0 && jmax >= 0) ? B * exp(-nu * (double)(rem - jmax)) : 0.0;
+    T rdec = cR;
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        rdec *= d;
+        sum[j] += rdec;
+        if (j <= jmax) {
+            sum[j] += (T)tb;
+            tb *= dd;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        sum[j] = (p > M || (dir_end && (p == 0 || p == M))) ? T(0) : -sum[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x sweep: contiguous lines, one line per workgroup of NT = 64*WPL threads
+// ---------------------------------------------------------------------------
+template <typename T, int S, int WPL, int NS, int NO, int VW>
+__global__ void __launch_bounds__(64 * WPL)
+k_sweep_x(const KArgs<T> a)
+{
+    constexpr int NT = 64 * WPL;
+    constexpr int NPAD = NT * (S + 1);
+    constexpr int NV = S / VW;
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
+    __shared__ T wtot[2][NS][WPL];
+    __shared__ T ends[2][NS];
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int64_t line = blockIdx.x;
+    const int n = (int)a.n;
+    const int M = n - 1;
+    const int64_t base = line * a.lineoff;            // uniform per workgroup
+    const bool dir_end = !a.periodic;
+
+    bool bline = false;
+    if (a.proj) {
+        const int64_t i1 = line % a.pn1, i2 = line / a.pn1;
+        bline = (a.pd1 && (i1 == 0 || i1 == a.pn1 - 1)) || (a.pd2 && (i2 == 0 || i2 == a.pn2 - 1));
+    }
+
+    // ---- phase 1: coalesced loads, prologue combinations -> LDS ----
+    T ev[NO][S];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int e0 = (i * NT + t) * VW;
+        T sv[NS][VW], ee[NO][VW];
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sv[k][c] = T(0);
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ee[o][c] = T(0);
+        }
+        for (int f = 0; f < a.nf; ++f) {
+            T x[VW];
+            const T *src = a.f[f] + base;
+            if (a.aligned && e0 + VW <= n) {
+                const vec_t vv = *reinterpret_cast<const vec_t *>(src + e0);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) x[c] = vv[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < VW; ++c) x[c] = (e0 + c < n) ? src[e0 + c] : T(0);
+            }
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) sv[k][c] += a.mS[k][f] * x[c];
+#pragma unroll
+                for (int o = 0; o < NO; ++o) ee[o][c] += a.mOF[o][f] * x[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int e = e0 + c;
+            const int slot = (e / S) * (S + 1) + (e % S);
+            const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][c];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ev[o][i * VW + c] = ee[o][c];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: recurrences over the lane's S nodes ----
+    const int p0 = t * S;
+    T sum[NS][S];
+    T aL[NS], aR[NS], eLM[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const T *sk = sm + k * NPAD;
+        T v[S + 2];
+#pragma unroll
+        for (int j = 0; j < S; ++j) v[j + 1] = sk[t * (S + 1) + j];
+        if (p0 == 0) v[0] = a.periodic ? sk[(M / S) * (S + 1) + (M % S)] : T(0);
+        else v[0] = sk[(t - 1) * (S + 1) + (S - 1)];
+        v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
+        if (a.periodic && M >= p0 && M < p0 + S) v[M - p0 + 2] = sk[0];  // wrap at node M
+        seg_recur<T, S>(v, p0, M, dir_end, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+    }
+
+    // lane scan (multiplier d^S per lane), then waves through LDS
+    T cL[NS], cR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T xl = aL[k], xr = aR[k], m = a.dS;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T yl = shfl_up(xl, off);
+            const T yr = shfl_down(xr, off);
+            if (lane >= off) xl += m * yl;
+            if (lane + off < 64) xr += m * yr;
+            m *= m;
+        }
+        const T exl = shfl_up(xl, 1);
+        const T exr = shfl_down(xr, 1);
+        cL[k] = (lane == 0) ? T(0) : exl;
+        cR[k] = (lane == 63) ? T(0) : exr;
+        if (WPL > 1) {
+            if (lane == 63) wtot[0][k][wave] = xl;
+            if (lane == 0) wtot[1][k][wave] = xr;
+        }
+    }
+    if (WPL > 1) {
+        __syncthreads();
+        const T pl = (T)exp(-a.nu * (double)S * (double)lane);
+        const T pr = (T)exp(-a.nu * (double)S * (double)(63 - lane));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T cw = T(0), cwr = T(0);
+            for (int w = 0; w < wave; ++w) cw = a.dBlk * cw + wtot[0][k][w];
+            for (int w = WPL - 1; w > wave; --w) cwr = a.dBlk * cwr + wtot[1][k][w];
+            cL[k] += pl * cw;
+            cR[k] += pr * cwr;
+        }
+    }
+    // line ends: E^R_0 (lane holding node 0) and E^L_M (lane holding node M)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (p0 == 0) ends[0][k] = aR[k] + a.dS * cR[k];
+        if (M >= p0 && M < p0 + S) {
+            const int jm = M - p0;
+            ends[1][k] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: closure, D values back into LDS ----
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const double er0 = (double)ends[0][k], elm = (double)ends[1][k];
+        const double A = a.K00 * er0 + a.K01 * elm;
+        const double B = a.K10 * er0 + a.K11 * elm;
+        seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end);
+        T *sk = sm + k * NPAD;
+#pragma unroll
+        for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
+    }
+    __syncthreads();
+
+    // ---- phase 4: epilogue in the coalesced layout ----
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int e0 = (i * NT + t) * VW;
+        T out[NO][VW];
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int e = e0 + c;
+            const int slot = (e / S) * (S + 1) + (e % S);
+            T Dk[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
+            const bool z = a.proj && (bline || (dir_end && (e == 0 || e == M)));
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                T r = ev[o][i * VW + c];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
+                out[o][c] = z ? T(0) : r;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            T *dst = a.o[o] + base;
+            if (a.aligned && e0 + VW <= n) {
+                vec_t vv;
+#pragma unroll
+                for (int c = 0; c < VW; ++c) vv[c] = out[o][c];
+                *reinterpret_cast<vec_t *>(dst + e0) = vv;
+            } else {
+#pragma unroll
+                for (int c = 0; c < VW; ++c)
+                    if (e0 + c < n) dst[e0 + c] = out[o][c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// strided sweep (y or z): lanes = 64 consecutive columns, W waves x S nodes
+// ---------------------------------------------------------------------------
+template <typename T, int S, int W, int NS, int NO>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_s(const KArgs<T> a)
+{
+    constexpr int WS = W * S;
+    __shared__ T red[2][NS][W][64];      // cooperative sums, then wave aggregates
+    __shared__ T endv[2][NS][64];        // E^R_0 and E^L_M per column (one tile)
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t L = xcd_remap(blockIdx.x, a.nblocks);
+    const int tile = (int)(L % a.ntiles);
+    const int64_t rest = L / a.ntiles;
+    const int64_t ncg = (a.nlines + 63) / 64;
+    const int64_t cg = rest % ncg;
+    const int64_t outer = rest / ncg;
+    const int col = (int)(cg * 64) + lane;
+    const bool active = col < a.nlines;
+    const int n = (int)a.n, M = n - 1;
+    const int ls = (int)a.ls;
+    const int64_t blk = cg * 64 + outer * a.os;          // uniform per workgroup
+    const int loff = active ? lane : 0;                  // per-lane column offset
+    const bool dir_end = !a.periodic;
+    const bool per = a.periodic != 0;
+    const T d = a.d, g = a.g, w2 = a.w2;
+    const int oa = tile * WS;
+    const int ob = (oa + WS < n) ? oa + WS : n;
+    const bool split = a.ntiles > 1;
+    const int K = a.halo;
+
+    // swept combination k at node p of this column (0 outside / at Dirichlet ends)
+    auto sval = [&](int k, int p) -> T {
+        if (per) {
+            p %= n;
+            if (p < 0) p += n;
+        } else if (p <= 0 || p >= M) {
+            return T(0);
+        }
+        if (!active) return T(0);
+        const int off = loff + p * ls;
+        T s = T(0);
+        for (int f = 0; f < a.nf; ++f) s += a.mS[k][f] * a.f[f][blk + off];
+        return s;
+    };
+    // this wave's share of sum_{kk<K} d^kk F(r0 + sg*kk): sg = -1 sums the
+    // forcing of E^L moving up from r0, sg = +1 that of E^R moving down
+    const int q = (K + W - 1) / W;
+    const int k0 = wave * q;
+    const int k1 = (k0 + q < K) ? k0 + q : K;
+    auto part = [&](int k, int r0, int sg) -> T {
+        T acc = T(0);
+        if (k0 >= k1) return acc;
+        T pw = (T)exp(-a.nu * (double)k0);
+        int r = r0 + sg * k0;
+        T vb = sval(k, r - sg), v0 = sval(k, r);
+        for (int kk = k0; kk < k1; ++kk, r += sg) {
+            const T vn = sval(k, r + sg);
+            const int rr = per ? ((r % n) + n) % n : r;
+            const T fv = (sg < 0) ? force_L(vn, v0, vb, rr, M, dir_end, g, w2)
+                                  : force_R(vb, v0, vn, rr, M, dir_end, g, w2);
+            acc += pw * fv;
+            pw *= d;
+            vb = v0;
+            v0 = vn;
+        }
+        return acc;
+    };
+    // cooperative pair of sums over all waves (workgroup-uniform call)
+    auto coop = [&](int r0a, int sga, bool usea, int r0b, int sgb, bool useb, T (&oa_)[NS],
+                    T (&ob_)[NS]) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            red[0][k][wave][lane] = usea ? part(k, r0a, sga) : T(0);
+            red[1][k][wave][lane] = useb ? part(k, r0b, sgb) : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T x = T(0), y = T(0);
+            for (int w = 0; w < W; ++w) {
+                x += red[0][k][w][lane];
+                y += red[1][k][w][lane];
+            }
+            oa_[k] = x;
+            ob_[k] = y;
+        }
+        __syncthreads();
+    };
+
+    // ---- carries entering the tile, and line-end values for split lines ----
+    T cTop[NS], cBot[NS], er0s[NS], elms[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        cTop[k] = T(0);
+        cBot[k] = T(0);
+        er0s[k] = T(0);
+        elms[k] = T(0);
+    }
+    // a tile far (> K nodes) from a line end does not see that end's correction
+    const bool needA = split && !per && oa < K;
+    const bool needB = split && !per && n - ob < K;
+    if (split) {
+        coop(oa - 1, -1, per || oa > 0, ob, +1, per || ob < n, cTop, cBot);
+        if (needA || needB) coop(0, +1, needA, M, -1, needB, er0s, elms);
+    }
+
+    // ---- main nodes p0 .. p0+S-1: load S+2 nodes once, form combinations ----
+    const int p0 = oa + wave * S;
+    T ev[NO][S];
+    T v[NS][S + 2];
+#pragma unroll
+    for (int j = 0; j < S + 2; ++j) {
+        int p = p0 - 1 + j;
+        bool inside;
+        if (per) {
+            p %= n;
+            if (p < 0) p += n;
+            inside = true;
+        } else {
+            inside = (p >= 0 && p <= M);
+        }
+        T sk[NS], eo[NO];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sk[k] = T(0);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) eo[o] = T(0);
+        if (inside && active) {
+            const int off = loff + p * ls;
+            for (int f = 0; f < a.nf; ++f) {
+                const T x = a.f[f][blk + off];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) sk[k] += a.mS[k][f] * x;
+#pragma unroll
+                for (int o = 0; o < NO; ++o) eo[o] += a.mOF[o][f] * x;
+            }
+        }
+        const bool zero = !inside || (dir_end && (p == 0 || p == M));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) v[k][j] = zero ? T(0) : sk[k];
+        if (j >= 1 && j <= S) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ev[o][j - 1] = eo[o];
+        }
+    }
+
+    T sum[NS][S];
+    T aL[NS], aR[NS], eLM[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        seg_recur<T, S>(v[k], p0, M, dir_end, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
+        red[0][k][wave][lane] = aL[k];
+        red[1][k][wave][lane] = aR[k];
+    }
+    __syncthreads();
+    // In a short last tile of a split periodic line the bottom carry enters
+    // at node n, inside a wave: it is applied through the closure instead.
+    const bool botAsB = per && split && ob == n;
+    T cL[NS], cR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T c = cTop[k];
+        for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
+        cL[k] = c;
+        T cr = botAsB ? T(0) : cBot[k];
+        for (int w = W - 1; w > wave; --w) cr = a.dS * cr + red[1][k][w][lane];
+        cR[k] = cr;
+    }
+    if (!split) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (p0 == 0) endv[0][k][lane] = aR[k] + a.dS * cR[k];
+            if (M >= p0 && M < p0 + S) {
+                const int jm = M - p0;
+                endv[1][k][lane] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- closure and epilogue ----
+    bool bline = false;
+    if (a.proj)
+        bline = (a.pd1 && (col == 0 || col == a.pn1 - 1)) ||
+                (a.pd2 && (outer == 0 || outer == a.pn2 - 1));
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double A = 0.0, B = 0.0;
+        if (!split) {
+            const double er0 = (double)endv[0][k][lane], elm = (double)endv[1][k][lane];
+            A = a.K00 * er0 + a.K01 * elm;
+            B = a.K10 * er0 + a.K11 * elm;
+        } else if (!per) {
+            const double er0 = (double)er0s[k], elm = (double)elms[k];
+            A = a.K00 * er0 + a.K01 * elm;
+            B = a.K10 * er0 + a.K11 * elm;
+        } else if (botAsB) {
+            B = (double)d * (double)cBot[k];     // cBot d^{n-p} = (d cBot) d^{M-p}
+        }
+        seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, dir_end);
+    }
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        if (p > M) break;
+        const bool z = a.proj && (bline || (dir_end && (p == 0 || p == M)));
+        const int off = loff + p * ls;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            T r = ev[o][j];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * sum[k][j];
+            a.o[o][blk + off] = z ? T(0) : r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise z = a x + b y
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T *x, T b, const T *y, T *z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride) z[k] = a * x[k] + b * y[k];
+}
+
+// ---------------------------------------------------------------------------
+// host side: launch dispatch
+// ---------------------------------------------------------------------------
+namespace {
+
+struct XCfg { int S, WPL; };
+struct SCfg { int S, W; };
+// configuration tables (cfg[0] indexes these)
+const XCfg kXCfg[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}, {16, 8}, {8, 2}, {8, 4}};
+const SCfg kSCfg[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {4, 16}, {16, 4}};
+constexpr int NXCFG = sizeof(kXCfg) / sizeof(kXCfg[0]);
+constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);
+
+int g_max_lds = -1;
+int max_lds()
+{
+    if (g_max_lds < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            g_max_lds = v;
+        else
+            g_max_lds = 65536;
+    }
+    return g_max_lds;
+}
+
+template <typename T>
+void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *const *fptr,
+                 void *const *optr)
+{
+    for (int i = 0; i < MAXF; ++i) k.f[i] = i < op.nf ? static_cast<const T *>(fptr[i]) : nullptr;
+    for (int i = 0; i < MAXO; ++i) k.o[i] = i < op.no ? static_cast<T *>(optr[i]) : nullptr;
+    for (int s = 0; s < MAXS; ++s)
+        for (int f = 0; f < MAXF; ++f) k.mS[s][f] = (T)op.mS[s][f];
+    for (int o = 0; o < MAXO; ++o) {
+        for (int f = 0; f < MAXF; ++f) k.mOF[o][f] = (T)op.mOF[o][f];
+        for (int s = 0; s < MAXS; ++s) k.mOD[o][s] = (T)op.mOD[o][s];
+    }
+    k.nf = op.nf;
+    k.proj = op.proj;
+    k.n = dc.n;
+    k.periodic = dc.periodic;
+    k.d = (T)dc.d;
+    k.g = (T)dc.g;
+    k.w2 = (T)dc.w2;
+    k.nu = dc.nu;
+    k.K00 = dc.K[0][0];
+    k.K01 = dc.K[0][1];
+    k.K10 = dc.K[1][0];
+    k.K11 = dc.K[1][1];
+}
+
+template <typename T, int S, int WPL, int NS, int NO>
+hipError_t run_x(const KArgs<T> &k, int64_t nlines, hipStream_t st)
+{
+    constexpr int VW = (sizeof(T) == 4) ? (S >= 4 ? 4 : S) : (S >= 2 ? 2 : 1);
+    const size_t lds = (size_t)NS * 64 * WPL * (S + 1) * sizeof(T);
+    auto fn = k_sweep_x<T, S, WPL, NS, NO, VW>;
+    if (lds > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)nlines), dim3(64 * WPL), lds, st, k);
+    return hipGetLastError();
+}
+
+template <typename T, int S, int W, int NS, int NO>
+hipError_t run_s(const KArgs<T> &k, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sweep_s<T, S, W, NS, NO>), dim3((unsigned)k.nblocks), dim3(64 * W), 0,
+                       st, k);
+    return hipGetLastError();
+}
+
+template <typename T, int NS, int NO>
+hipError_t dispatch_x(const KArgs<T> &k, int64_t nlines, int id, hipStream_t st)
+{
+    switch (id) {
+    case 0: return run_x<T, 2, 1, NS, NO>(k, nlines, st);
+    case 1: return run_x<T, 4, 1, NS, NO>(k, nlines, st);
+    case 2: return run_x<T, 8, 1, NS, NO>(k, nlines, st);
+    case 3: return run_x<T, 16, 1, NS, NO>(k, nlines, st);
+    case 4: return run_x<T, 16, 2, NS, NO>(k, nlines, st);
+    case 5: return run_x<T, 16, 4, NS, NO>(k, nlines, st);
+    case 6: return run_x<T, 8, 8, NS, NO>(k, nlines, st);
+    case 7: return run_x<T, 16, 8, NS, NO>(k, nlines, st);
+    case 8: return run_x<T, 8, 2, NS, NO>(k, nlines, st);
+    case 9: return run_x<T, 8, 4, NS, NO>(k, nlines, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int NS, int NO>
+hipError_t dispatch_s(const KArgs<T> &k, int id, hipStream_t st)
+{
+    switch (id) {
+    case 0: return run_s<T, 16, 16, NS, NO>(k, st);
+    case 1: return run_s<T, 16, 8, NS, NO>(k, st);
+    case 2: return run_s<T, 8, 16, NS, NO>(k, st);
+    case 3: return run_s<T, 8, 8, NS, NO>(k, st);
+    case 4: return run_s<T, 4, 16, NS, NO>(k, st);
+    case 5: return run_s<T, 16, 4, NS, NO>(k, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
+                    const void *const *fptr, void *const *optr, const int *cfg, hipStream_t st)
+{
+    KArgs<T> k{};
+    fill_common<T>(k, op, dc, fptr, optr);
+    const int dir = op.dir;
+    const int nsno = op.ns * 10 + op.no;
+    if (dir == 0) {
+        const XCfg c = kXCfg[cfg[0]];
+        const int64_t nlines = g.n[1] * g.n[2];
+        k.nlines = nlines;
+        k.lineoff = g.n[0];
+        constexpr int VWT = sizeof(T) == 4 ? 4 : 2;
+        const int vw = (sizeof(T) == 4) ? (c.S >= 4 ? 4 : c.S) : (c.S >= 2 ? 2 : 1);
+        (void)VWT;
+        k.aligned = (g.n[0] % vw == 0) ? 1 : 0;
+        for (int i = 0; i < MAXF; ++i)
+            if (i < op.nf && (reinterpret_cast<uintptr_t>(fptr[i]) % (vw * sizeof(T)))) k.aligned = 0;
+        for (int i = 0; i < MAXO; ++i)
+            if (i < op.no && (reinterpret_cast<uintptr_t>(optr[i]) % (vw * sizeof(T)))) k.aligned = 0;
+        k.dS = (T)exp(-dc.nu * c.S);
+        k.dBlk = (T)exp(-dc.nu * c.S * 64.0);
+        k.pn1 = g.n[1];
+        k.pn2 = g.n[2];
+        k.pd1 = g.ndim > 1 ? g.dirichlet[1] : 0;
+        k.pd2 = g.ndim > 2 ? g.dirichlet[2] : 0;
+        switch (nsno) {
+        case 11: return dispatch_x<T, 1, 1>(k, nlines, cfg[0], st);
+        case 12: return dispatch_x<T, 1, 2>(k, nlines, cfg[0], st);
+        case 22: return dispatch_x<T, 2, 2>(k, nlines, cfg[0], st);
+        case 23: return dispatch_x<T, 2, 3>(k, nlines, cfg[0], st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    const SCfg c = kSCfg[cfg[0]];
+    const int WS = c.S * c.W;
+    k.nlines = g.n[0];
+    if (dir == 1) {
+        k.ls = g.n[0];
+        k.os = g.n[0] * g.n[1];
+        k.nouter = g.n[2];
+        k.pn1 = g.n[0];
+        k.pn2 = g.n[2];
+        k.pd1 = g.dirichlet[0];
+        k.pd2 = g.ndim > 2 ? g.dirichlet[2] : 0;
+    } else {
+        k.ls = g.n[0] * g.n[1];
+        k.os = g.n[0];
+        k.nouter = g.n[1];
+        k.pn1 = g.n[0];
+        k.pn2 = g.n[1];
+        k.pd1 = g.dirichlet[0];
+        k.pd2 = g.dirichlet[1];
+    }
+    k.ntiles = (int)((dc.n + WS - 1) / WS);
+    k.halo = dc.halo;
+    k.nblocks = (int64_t)k.ntiles * ((g.n[0] + 63) / 64) * k.nouter;
+    k.dS = (T)exp(-dc.nu * c.S);
+    k.dBlk = k.dS;
+    switch (nsno) {
+    case 11: return dispatch_s<T, 1, 1>(k, cfg[0], st);
+    case 12: return dispatch_s<T, 1, 2>(k, cfg[0], st);
+    case 22: return dispatch_s<T, 2, 2>(k, cfg[0], st);
+    case 23: return dispatch_s<T, 2, 3>(k, cfg[0], st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool config_valid(const Geom &g, int dir, bool fp64, int ns, int no, const int *cfg)
+{
+    const size_t es = fp64 ? 8 : 4;
+    if (!((ns == 1 && (no == 1 || no == 2)) || (ns == 2 && (no == 2 || no == 3)))) return false;
+    if (dir == 0) {
+        if (cfg[0] < 0 || cfg[0] >= NXCFG) return false;
+        const XCfg c = kXCfg[cfg[0]];
+        const int64_t cap = (int64_t)64 * c.WPL * c.S;
+        if (g.n[0] > cap) return false;
+        const size_t lds = (size_t)ns * 64 * c.WPL * (c.S + 1) * es;
+        if (lds > (size_t)max_lds()) return false;
+        return true;
+    }
+    if (cfg[0] < 0 || cfg[0] >= NSCFG) return false;
+    return true;
+}
+
+int default_config(const Geom &g, int dir, bool fp64, int ns, int no, int *cfg)
+{
+    if (dir == 0) {
+        const int64_t n = g.n[0];
+        // smallest line capacity that holds the line, preferring 16 nodes/lane
+        // FP64 keeps 8 nodes per lane (16 spill registers)
+        static const int order32[] = {0, 1, 2, 3, 4, 5, 7};
+        static const int order64[] = {0, 1, 2, 8, 9, 6, 7};
+        const int *ord = fp64 ? order64 : order32;
+        const int cnt = 7;
+        for (int i = 0; i < cnt; ++i) {
+            cfg[0] = ord[i];
+            const XCfg c = kXCfg[cfg[0]];
+            if (64 * c.WPL * c.S >= n && config_valid(g, dir, fp64, ns, no, cfg)) return 0;
+        }
+        return -1;
+    }
+    // strided: prefer tall tiles (16 waves x 16 nodes) for FP32 single sweeps,
+    // shorter lanes when more registers are live
+    const int regs = (2 * ns + no) * (fp64 ? 2 : 1);
+    cfg[0] = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
+    return config_valid(g, dir, fp64, ns, no, cfg) ? 0 : -1;
+}
+
+int strided_tile_nodes(int cfgid) { return kSCfg[cfgid].S * kSCfg[cfgid].W; }
+
+hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
+                        const void *const *fptr, void *const *optr, const int *cfg,
+                        hipStream_t st)
+{
+    if (!config_valid(g, op.dir, fp64, op.ns, op.no, cfg)) return hipErrorInvalidValue;
+    return fp64 ? launch_t<double>(op, g, dc, fptr, optr, cfg, st)
+                : launch_t<float>(op, g, dc, fptr, optr, cfg, st);
+}
+
+hipError_t launch_axpby(bool fp64, int64_t n, double a, const void *x, double b, const void *y,
+                        void *z, hipStream_t st)
+{
+    const int bs = 256;
+    int64_t nb = (n + bs - 1) / bs;
+    if (nb > 65536) nb = 65536;
+    if (nb < 1) nb = 1;
+    if (fp64)
+        hipLaunchKernelGGL(k_axpby<double>, dim3((unsigned)nb), dim3(bs), 0, st, n, a,
+                           static_cast<const double *>(x), b, static_cast<const double *>(y),
+                           static_cast<double *>(z));
+    else
+        hipLaunchKernelGGL(k_axpby<float>, dim3((unsigned)nb), dim3(bs), 0, st, n, (float)a,
+                           static_cast<const float *>(x), (float)b, static_cast<const float *>(y),
+                           static_cast<float *>(z));
+    return hipGetLastError();
+}
+
+}  // namespace molt

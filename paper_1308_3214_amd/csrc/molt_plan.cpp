@@ -1,0 +1,852 @@
+// Plan builder and C-ABI of libmolt.
+//
+// A plan turns the problem statement (domain, c, dt, beta, order P, boundary
+// types, optional embedded boundary) into
+//   * FP64 scheme constants: beta_max(P) (Sec. 3.1, eq. Stab_cond),
+//     alpha = beta/(c dt) (eq. L_def), the stage weights
+//     c_{p,m} = (-1)^m 2 beta^{2m}/(2m)! binom(p-1, m-1) (eq. Full_2D);
+//   * per-direction quadrature constants: d = e^{-nu}, g = (1-d)/(2 nu) via
+//     expm1, the curvature weight w2 (series below nu = 1), the 2x2 closure
+//     of the boundary correction (Dirichlet: e^{-alpha L} and 1/(1-e^{-2 alpha L});
+//     periodic: 1/(1-e^{-alpha L})), and the halo length of split lines;
+//   * a kernel program per entry point: the stage schedule of Table 2 with the
+//     ADI compositions written through directional D's and fused into the
+//     sweeps' prologues/epilogues, the time update fused into the last sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/molt.h"
+#include "molt_internal.h"
+#include "molt_program.h"
+
+using namespace molt;
+
+namespace {
+
+thread_local std::string g_err;
+
+mol_status fail(mol_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// scheme constants
+// ---------------------------------------------------------------------------
+double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+double fact(int n)
+{
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= (double)i;
+    return r;
+}
+
+}  // namespace
+
+// weight of C^m D^{p-m} in eq. Full_2D
+double molt::stage_c(int p, int m, double beta)
+{
+    return ((m % 2) ? -2.0 : 2.0) * std::pow(beta, 2 * m) / fact(2 * m) * binom(p - 1, m - 1);
+}
+
+// A_p = sum_m c_{p,m}: the 1D weights (eq. update_P)
+double molt::A_p(int p, double beta)
+{
+    double s = 0.0;
+    for (int m = 1; m <= p; ++m) s += stage_c(p, m, beta);
+    return s;
+}
+
+namespace {
+
+// S(beta, 1) = -sum_{p<=P} A_p(beta) (eq. Stab_sum at Dhat = 1)
+double S1(int P, double beta)
+{
+    double s = 0.0;
+    for (int p = 1; p <= P; ++p) s -= A_p(p, beta);
+    return s;
+}
+
+double beta_max_of(int P)
+{
+    // S(beta, 1) grows from 0 at beta = 0; march to the first crossing of 4,
+    // then refine by bisection.
+    double lo = 0.0, hi = 0.0;
+    const double step = 1.0 / 512.0;
+    for (double b = step; b < 16.0; b += step) {
+        if (S1(P, b) >= 4.0) {
+            lo = b - step;
+            hi = b;
+            break;
+        }
+    }
+    if (hi == 0.0) return -1.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (S1(P, mid) < 4.0) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// curvature weight w2(nu) = (2(1-e^{-nu})/nu^2 - (1+e^{-nu})/nu)/4
+double w2_of(double nu)
+{
+    if (nu < 1.0) {
+        // -(nu/4) sum_{k>=0} (-nu)^k / (k! (k+2)(k+3))
+        double s = 0.0, t = 1.0;
+        for (int k = 0; k < 40; ++k) {
+            s += t / ((k + 2.0) * (k + 3.0));
+            t *= -nu / (k + 1.0);
+        }
+        return -0.25 * nu * s;
+    }
+    const double om = -std::expm1(-nu);
+    const double d = std::exp(-nu);
+    return 0.25 * (2.0 * om / (nu * nu) - (1.0 + d) / nu);
+}
+
+int halo_for(double nu, bool fp64)
+{
+    // d^K <= 2^-(mantissa bits) / 16: below the rounding of the result
+    const double lnTol = fp64 ? (53.0 + 4.0) * std::log(2.0) : (24.0 + 4.0) * std::log(2.0);
+    const double K = std::ceil(lnTol / nu) + 1.0;
+    return K > 1e9 ? 1000000000 : (int)K;
+}
+
+DirCoef make_dircoef(double nu, int64_t n, bool periodic, bool fp64)
+{
+    DirCoef c{};
+    c.nu = nu;
+    c.d = std::exp(-nu);
+    c.g = -std::expm1(-nu) / (2.0 * nu);
+    c.w2 = w2_of(nu);
+    c.periodic = periodic ? 1 : 0;
+    c.n = n;
+    c.halo = halo_for(nu, fp64);
+    if (periodic) {
+        const double f = c.d / (-std::expm1(-nu * (double)n));
+        c.K[0][0] = 0.0; c.K[0][1] = f;
+        c.K[1][0] = f;   c.K[1][1] = 0.0;
+    } else {
+        const double L = nu * (double)(n - 1);       // alpha * (b - a)
+        const double mu = std::exp(-L);
+        const double inv = 1.0 / (-std::expm1(-2.0 * L));
+        c.K[0][0] = -inv;      c.K[0][1] = mu * inv;
+        c.K[1][0] = mu * inv;  c.K[1][1] = -inv;
+    }
+    return c;
+}
+
+}  // namespace
+
+namespace molt {
+
+bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
+                   const std::vector<OutSpec> &outs, int proj)
+{
+
+        const int ns = (int)combos.size(), no = (int)outs.size();
+        if (ns < 1 || ns > MAXS || no < 1 || no > MAXO) {
+            err = "internal: launch shape";
+            return false;
+        }
+        // does the preferred config exist? else split two combos into two launches
+        int cfg[2] = {0, 0};
+        if (!pl.masked && default_config(pl.geom, dir, pl.fp64, ns, no, cfg) != 0) {
+            if (ns == 2) {
+                std::vector<OutSpec> o0, o1;
+                for (const OutSpec &o : outs) {
+                    const bool u0 = o.dc[0] != 0.0, u1 = o.dc[1] != 0.0;
+                    if (u0 && u1) {
+                        err = "internal: cannot split a launch whose output needs both sweeps";
+                        return false;
+                    }
+                    OutSpec t = o;
+                    if (u1) { t.dc[0] = t.dc[1]; t.dc[1] = 0; o1.push_back(t); }
+                    else o0.push_back(t);
+                }
+                bool ok = true;
+                if (!o0.empty()) ok = ok && emit(prog, dir, {combos[0]}, o0, proj);
+                if (!o1.empty()) ok = ok && emit(prog, dir, {combos[1]}, o1, proj);
+                return ok;
+            }
+            if (no > 1) {
+                bool ok = true;
+                for (const OutSpec &o : outs) ok = ok && emit(prog, dir, combos, {o}, proj);
+                return ok;
+            }
+            err = "no kernel configuration fits this line length";
+            return false;
+        }
+        SweepOp op;
+        op.dir = dir;
+        op.ns = ns;
+        op.no = no;
+        op.proj = proj;
+        std::vector<int> fields;
+        auto fid = [&](int b) -> int {
+            for (size_t i = 0; i < fields.size(); ++i)
+                if (fields[i] == b) return (int)i;
+            fields.push_back(b);
+            return (int)fields.size() - 1;
+        };
+        for (int k = 0; k < ns; ++k)
+            for (auto &t : combos[k]) {
+                const int i = fid(t.first);
+                if (i < MAXF) op.mS[k][i] += t.second;
+            }
+        for (int o = 0; o < no; ++o) {
+            op.o[o] = outs[o].buf;
+            for (auto &t : outs[o].elem) {
+                const int i = fid(t.first);
+                if (i < MAXF) op.mOF[o][i] += t.second;
+            }
+            for (int k = 0; k < ns; ++k) op.mOD[o][k] = outs[o].dc[k];
+        }
+        if ((int)fields.size() > MAXF) {
+            err = "schedule needs more fields per launch than supported (lower P)";
+            return false;
+        }
+        op.nf = (int)fields.size();
+        for (int i = 0; i < op.nf; ++i) op.f[i] = fields[i];
+        ProgOp po;
+        po.op = op;
+        po.cfg[0] = cfg[0];
+        po.cfg[1] = cfg[1];
+        prog.push_back(po);
+        return true;
+    }
+
+std::vector<OutSpec> finals(const std::vector<FinalOut> &fo, const Lin &rhs_elem, double rhs_dcoef)
+{
+    std::vector<OutSpec> v;
+    for (const FinalOut &f : fo) {
+        OutSpec o{};
+        o.buf = f.buf;
+        o.elem = f.elem + f.r * rhs_elem;
+        o.dc[0] = f.r * rhs_dcoef;
+        o.dc[1] = 0.0;
+        v.push_back(o);
+    }
+    return v;
+}
+
+// 1D: rhs = sum_p A_p D^p u, D^p by repeated sweeps (Sec. 3, eq. update_P).
+bool build_rhs_1d(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo)
+{
+    mol_plan_ &pl = b.pl;
+    const int P = pl.desc.P;
+    std::vector<int> w(P, u);   // w[p] = D^p u, w[0] = u
+    Lin acc;
+    for (int p = 1; p < P; ++p) {
+        w[p] = b.new_ws();
+        OutSpec o{};
+        o.buf = w[p];
+        o.dc[0] = 1.0;
+        if (!b.emit(prog, 0, {lin(w[p - 1])}, {o}, 0)) return false;
+        acc = acc + lin(w[p], A_p(p, pl.beta));
+    }
+    return b.emit(prog, 0, {lin(w[P - 1])}, finals(fo, acc, A_p(P, pl.beta)), 1);
+}
+
+// 2D / 3D rectangles and boxes: stage schedule of Table 2; each application of
+// C or D composed from directional D's (operators commute on boxes):
+//   2D: C v = D_x(v - 2y) + y,  D v = D_x(v - y) + y,  y = D_y v
+//   3D: C v = D_x(v - 2y - 2z + 3yz) + (y + z - 2yz),
+//       D v = D_x(v - y - z + yz) + (y + z - yz),  z = D_z v, y = D_y v, yz = D_y z
+bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo)
+{
+    mol_plan_ &pl = b.pl;
+    const int P = pl.desc.P;
+    const int nd = pl.geom.ndim;
+    const double beta = pl.beta;
+    std::vector<int> v{u};      // inputs of the current stage
+    int accbuf = -1;            // accumulated earlier-stage terms (stage >= 3)
+    for (int p = 1; p <= P; ++p) {
+        const int nin = (int)v.size();     // p == 1: {u}; else v_1..v_{p-1}
+        // ---- transverse sweeps ----
+        std::vector<Lin> gC(nin), hC(nin);   // C v_k = D_x(gC) + hC
+        Lin gD, hD;                           // D v_last = D_x(gD) + hD
+        if (nd == 2) {
+            std::vector<int> y(nin);
+            for (int k = 0; k < nin; k += 2) {
+                std::vector<Lin> cmb;
+                std::vector<OutSpec> outs;
+                for (int j = k; j < std::min(nin, k + 2); ++j) {
+                    y[j] = b.new_ws();
+                    cmb.push_back(lin(v[j]));
+                    OutSpec o{};
+                    o.buf = y[j];
+                    o.dc[j - k] = 1.0;
+                    outs.push_back(o);
+                }
+                if (!b.emit(prog, 1, cmb, outs, 0)) return false;
+            }
+            for (int k = 0; k < nin; ++k) {
+                gC[k] = lin(v[k]) + lin(y[k], -2.0);
+                hC[k] = lin(y[k]);
+            }
+            gD = lin(v[nin - 1]) + lin(y[nin - 1], -1.0);
+            hD = lin(y[nin - 1]);
+        } else {
+            std::vector<int> z(nin), y(nin), yz(nin);
+            for (int k = 0; k < nin; k += 2) {
+                std::vector<Lin> cmb;
+                std::vector<OutSpec> outs;
+                for (int j = k; j < std::min(nin, k + 2); ++j) {
+                    z[j] = b.new_ws();
+                    cmb.push_back(lin(v[j]));
+                    OutSpec o{};
+                    o.buf = z[j];
+                    o.dc[j - k] = 1.0;
+                    outs.push_back(o);
+                }
+                if (!b.emit(prog, 2, cmb, outs, 0)) return false;
+            }
+            for (int k = 0; k < nin; ++k) {
+                y[k] = b.new_ws();
+                yz[k] = b.new_ws();
+                OutSpec o1{}, o2{};
+                o1.buf = y[k];
+                o1.dc[0] = 1.0;
+                o2.buf = yz[k];
+                o2.dc[1] = 1.0;
+                if (!b.emit(prog, 1, {lin(v[k]), lin(z[k])}, {o1, o2}, 0)) return false;
+            }
+            for (int k = 0; k < nin; ++k) {
+                gC[k] = lin(v[k]) + lin(y[k], -2.0) + lin(z[k], -2.0) + lin(yz[k], 3.0);
+                hC[k] = lin(y[k]) + lin(z[k]) + lin(yz[k], -2.0);
+            }
+            const int l = nin - 1;
+            gD = lin(v[l]) + lin(y[l], -1.0) + lin(z[l], -1.0) + lin(yz[l]);
+            hD = lin(y[l]) + lin(z[l]) + lin(yz[l], -1.0);
+        }
+        // ---- x sweeps: the new terms of stage p ----
+        // stage p produces p terms: C v_k (k < nin) and D v_{nin-1} (p >= 2); for
+        // p == 1 the single term C u.  Term k carries m = p - k factors of C.
+        std::vector<Lin> g, h;
+        for (int k = 0; k < nin; ++k) { g.push_back(gC[k]); h.push_back(hC[k]); }
+        if (p >= 2) { g.push_back(gD); h.push_back(hD); }
+        const int nt = (int)g.size();          // == p
+        // earlier-stage terms carried into this stage
+        Lin acc_in;
+        if (p == 2) acc_in = lin(v[0], stage_c(1, 1, beta));   // v_1 = C u
+        else if (p >= 3) acc_in = lin(accbuf);
+        if (p == P) {
+            // one sweep of the weighted sum of this stage's terms
+            Lin gs, hs = acc_in;
+            for (int k = 0; k < nt; ++k) {
+                const double c = stage_c(p, p - k, beta);
+                gs = gs + c * g[k];
+                hs = hs + c * h[k];
+            }
+            return b.emit(prog, 0, {gs}, finals(fo, hs, 1.0), 1);
+        }
+        // non-final stage: write the p new terms (and the accumulator if needed)
+        std::vector<int> nv(nt);
+        for (int k = 0; k < nt; ++k) nv[k] = b.new_ws();
+        const bool need_acc = (P >= 3);
+        const int newacc = need_acc ? b.new_ws() : -1;
+        // launches of <= 2 sweeps; the last one also writes the accumulator
+        Lin acc_done = acc_in;    // contributions of terms already written
+        for (int k = 0; k < nt; k += 2) {
+            const int k1 = std::min(nt, k + 2);
+            std::vector<Lin> cmb;
+            std::vector<OutSpec> outs;
+            for (int j = k; j < k1; ++j) {
+                cmb.push_back(g[j]);
+                OutSpec o{};
+                o.buf = nv[j];
+                o.elem = h[j];
+                o.dc[j - k] = 1.0;
+                outs.push_back(o);
+            }
+            const bool last = (k1 == nt);
+            if (last && need_acc) {
+                OutSpec o{};
+                o.buf = newacc;
+                o.elem = acc_done;
+                for (int j = k; j < k1; ++j) {
+                    const double c = stage_c(p, p - j, beta);
+                    o.elem = o.elem + c * h[j];
+                    o.dc[j - k] = c;
+                }
+                outs.push_back(o);
+            }
+            if (!b.emit(prog, 0, cmb, outs, 0)) return false;
+            for (int j = k; j < k1; ++j) acc_done = acc_done + lin(nv[j], stage_c(p, p - j, beta));
+        }
+        // stage p+1 inputs: terms in Table 2 order (m = p, p-1, ..., 1)
+        v = nv;
+        accbuf = newacc;
+    }
+    return true;
+}
+
+bool build_rhs(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo)
+{
+    if (b.pl.masked) {
+        return build_rhs_masked(b, prog, u, fo);
+    }
+    if (b.pl.geom.ndim == 1) return build_rhs_1d(b, prog, u, fo);
+    return build_rhs_box(b, prog, u, fo);
+}
+
+// single operators
+bool build_apply(Builder &b, Program &prog, int op)
+{
+    mol_plan_ &pl = b.pl;
+    const int nd = pl.geom.ndim;
+    if (op <= MOL_OP_D_Z) {
+        const int dir = op % 3;
+        if (dir >= nd) {
+            b.err = "operator direction not present";
+            return false;
+        }
+        OutSpec o{};
+        o.buf = B_OUT;
+        o.dc[0] = (op <= MOL_OP_LINV_Z) ? -1.0 : 1.0;
+        if (op <= MOL_OP_LINV_Z) o.elem = lin(B_IN);   // L^{-1} = 1 - D
+        if (pl.masked) return build_apply_masked(b, prog, op);
+        return b.emit(prog, dir, {lin(B_IN)}, {o}, 1);
+    }
+    if (pl.masked) return build_apply_masked(b, prog, op);
+    if (op == MOL_OP_RHS) return build_rhs(b, prog, B_IN, {{B_OUT, Lin{}, 1.0}});
+    const bool isC = (op == MOL_OP_C);
+    if (nd == 1) {
+        OutSpec o{};
+        o.buf = B_OUT;
+        o.dc[0] = 1.0;
+        return b.emit(prog, 0, {lin(B_IN)}, {o}, 1);
+    }
+    if (nd == 2) {
+        const int y = b.new_ws();
+        OutSpec o{};
+        o.buf = y;
+        o.dc[0] = 1.0;
+        if (!b.emit(prog, 1, {lin(B_IN)}, {o}, 0)) return false;
+        OutSpec f{};
+        f.buf = B_OUT;
+        f.elem = lin(y);
+        f.dc[0] = 1.0;
+        return b.emit(prog, 0, {lin(B_IN) + lin(y, isC ? -2.0 : -1.0)}, {f}, 1);
+    }
+    const int z = b.new_ws(), y = b.new_ws(), yz = b.new_ws();
+    OutSpec oz{};
+    oz.buf = z;
+    oz.dc[0] = 1.0;
+    if (!b.emit(prog, 2, {lin(B_IN)}, {oz}, 0)) return false;
+    OutSpec o1{}, o2{};
+    o1.buf = y;
+    o1.dc[0] = 1.0;
+    o2.buf = yz;
+    o2.dc[1] = 1.0;
+    if (!b.emit(prog, 1, {lin(B_IN), lin(z)}, {o1, o2}, 0)) return false;
+    OutSpec f{};
+    f.buf = B_OUT;
+    f.dc[0] = 1.0;
+    if (isC) {
+        f.elem = lin(y) + lin(z) + lin(yz, -2.0);
+        return b.emit(prog, 0, {lin(B_IN) + lin(y, -2.0) + lin(z, -2.0) + lin(yz, 3.0)}, {f}, 1);
+    }
+    f.elem = lin(y) + lin(z) + lin(yz, -1.0);
+    return b.emit(prog, 0, {lin(B_IN) + lin(y, -1.0) + lin(z, -1.0) + lin(yz)}, {f}, 1);
+}
+
+mol_status validate(const mol_desc *d)
+{
+    if (!d) return fail(MOL_E_INVALID, "desc is NULL");
+    if (d->ndim < 1 || d->ndim > 3) return fail(MOL_E_INVALID, "ndim must be 1, 2 or 3");
+    for (int a = 0; a < 3; ++a) {
+        if (a < d->ndim) {
+            if (d->n[a] < 3) return fail(MOL_E_INVALID, "every axis needs at least 3 nodes");
+            if (!(d->h[a] > 0.0)) return fail(MOL_E_INVALID, "h must be > 0");
+            if (d->bc[a] != MOL_BC_DIRICHLET && d->bc[a] != MOL_BC_PERIODIC)
+                return fail(MOL_E_INVALID, "unknown boundary type");
+        } else if (d->n[a] != 1 && d->n[a] != 0) {
+            return fail(MOL_E_INVALID, "unused axes must have n = 1");
+        }
+    }
+    if (d->P < 1 || d->P > 5) return fail(MOL_E_INVALID, "P must be in 1..5 (Table 1)");
+    if (!(d->c > 0.0) || !(d->dt > 0.0)) return fail(MOL_E_INVALID, "c and dt must be > 0");
+    if (d->dtype != MOL_F64 && d->dtype != MOL_F32) return fail(MOL_E_INVALID, "unknown dtype");
+    if (d->mask) {
+        if (d->ndim != 2) return fail(MOL_E_UNSUPPORTED, "masks are supported in 2D only");
+        if (d->bc[0] != MOL_BC_DIRICHLET || d->bc[1] != MOL_BC_DIRICHLET)
+            return fail(MOL_E_INVALID, "a mask needs Dirichlet boundaries");
+    } else if (d->cross) {
+        return fail(MOL_E_INVALID, "cross given without mask");
+    }
+    int64_t npts = 1;
+    for (int a = 0; a < d->ndim; ++a) {
+        if (d->n[a] > (int64_t)1 << 31) return fail(MOL_E_UNSUPPORTED, "axis too long");
+        npts *= d->n[a];
+    }
+    if (npts >= ((int64_t)1 << 31)) return fail(MOL_E_UNSUPPORTED, "fields of 2^31 nodes or more are not supported");
+    return MOL_OK;
+}
+
+// Build everything except device allocations (dry = true) or including them.
+mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
+{
+    mol_status s = validate(d);
+    if (s != MOL_OK) return s;
+    pl->desc = *d;
+    pl->desc.mask = nullptr;
+    pl->desc.cross = nullptr;
+    pl->fp64 = (d->dtype == MOL_F64);
+    pl->es = pl->fp64 ? 8 : 4;
+    Geom &g = pl->geom;
+    g.ndim = d->ndim;
+    pl->npts = 1;
+    pl->unknowns = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = (a < d->ndim) ? d->n[a] : 1;
+        g.dirichlet[a] = (a < d->ndim && d->bc[a] == MOL_BC_DIRICHLET) ? 1 : 0;
+        pl->npts *= g.n[a];
+        pl->unknowns *= (a < d->ndim) ? (g.dirichlet[a] ? g.n[a] - 2 : g.n[a]) : 1;
+    }
+    pl->betamax = beta_max_of(d->P);
+    pl->beta = (d->beta > 0.0) ? d->beta : pl->betamax;
+    if (pl->beta > pl->betamax * (1.0 + 1e-12) && !(d->flags & MOL_ALLOW_UNSTABLE)) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "beta = %.8g exceeds beta_max(%d) = %.8g", pl->beta, d->P,
+                 pl->betamax);
+        return fail(MOL_E_UNSTABLE, buf);
+    }
+    pl->alpha = pl->beta / (d->c * d->dt);
+    for (int a = 0; a < d->ndim; ++a) {
+        const double nu = pl->alpha * d->h[a];
+        pl->dc[a] = make_dircoef(nu, g.n[a], d->bc[a] == MOL_BC_PERIODIC, pl->fp64);
+    }
+    pl->masked = (d->mask != nullptr);
+    if (pl->masked) {
+        std::string err;
+        pl->h_mask.assign(d->mask, d->mask + pl->npts);
+        if (d->cross) pl->h_cross.assign(d->cross, d->cross + 4 * pl->npts);
+        mol_status ms = masked_tables(pl, dry, err);
+        if (ms != MOL_OK) return fail(ms, err);
+        pl->unknowns = 0;
+        for (int64_t i = 0; i < pl->npts; ++i) pl->unknowns += d->mask[i] ? 1 : 0;
+    }
+    Builder b(*pl, dry);
+    // step: u_next = 2 u - u_prev + rhs(u)
+    bool ok = build_rhs(b, pl->step, B_UCURR, {{B_UNEXT, lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0), 1.0}});
+    // increment form: (u, du) -> (u + du + rhs, du + rhs), in place
+    ok = ok && build_rhs(b, pl->inc_step, B_UCURR,
+                         {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0}, {B_UPREV, lin(B_UPREV), 1.0}});
+    // start: u1 = u0 + rhs(u0)/2
+    ok = ok && build_rhs(b, pl->start, B_IN, {{B_OUT, lin(B_IN), 0.5}});
+    for (int op = 0; op <= MOL_OP_RHS && ok; ++op) {
+        if (op <= MOL_OP_D_Z && (op % 3) >= d->ndim) continue;
+        ok = build_apply(b, pl->apply[op], op);
+    }
+    if (!ok) return fail(MOL_E_UNSUPPORTED, b.err);
+    // one more workspace field: scratch for the odd-step swap of mol_solve
+    pl->nws += 1;
+    return MOL_OK;
+}
+
+hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
+                       void *unext, const void *in, void *out, hipStream_t st)
+{
+    for (const ProgOp &po : prog) {
+        const void *fp[MAXF];
+        void *op[MAXO];
+        auto res = [&](int b) -> void * {
+            switch (b) {
+            case B_UPREV: return const_cast<void *>(uprev);
+            case B_UCURR: return const_cast<void *>(ucurr);
+            case B_UNEXT: return unext;
+            case B_IN: return const_cast<void *>(in);
+            case B_OUT: return out;
+            default: return pl->ws[b - B_WS0];
+            }
+        };
+        for (int i = 0; i < po.op.nf; ++i) fp[i] = res(po.op.f[i]);
+        for (int i = 0; i < po.op.no; ++i) op[i] = res(po.op.o[i]);
+        hipError_t e;
+        if (pl->masked)
+            e = launch_seg_op(po.op, pl, fp, op, st);
+        else
+            e = launch_sweep(po.op, pl->geom, pl->dc[po.op.dir], pl->fp64, fp, op, po.cfg, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+double program_bytes(const mol_plan_ *pl, const Program &prog)
+{
+    double b = 0;
+    for (const ProgOp &po : prog) b += (double)(po.op.nf + po.op.no);
+    return b * (double)pl->npts * (double)pl->es;
+}
+
+void free_plan(mol_plan_ *pl)
+{
+    if (!pl) return;
+    if (pl->gexec) hipGraphExecDestroy(pl->gexec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    for (void *p : pl->ws)
+        if (p) hipFree(p);
+    masked_free(pl);
+    delete pl;
+}
+
+mol_status dev_err(hipError_t e, const char *what)
+{
+    std::string m = what;
+    m += ": ";
+    m += hipGetErrorString(e);
+    return fail(MOL_E_DEVICE, m);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+double mol_beta_max(int P)
+{
+    if (P < 1 || P > 8) return -1.0;
+    return beta_max_of(P);
+}
+
+const char *mol_last_error(void) { return g_err.c_str(); }
+
+size_t mol_workspace_bytes(const mol_desc *desc)
+{
+    mol_plan_ *pl = new (std::nothrow) mol_plan_();
+    if (!pl) return 0;
+    size_t r = 0;
+    if (build_plan(desc, pl, true) == MOL_OK)
+        r = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes;
+    masked_free(pl);
+    delete pl;
+    return r;
+}
+
+mol_status mol_plan_create(const mol_desc *desc, mol_plan **out)
+{
+    if (!out) return fail(MOL_E_INVALID, "plan out-pointer is NULL");
+    mol_plan_ *pl = new (std::nothrow) mol_plan_();
+    if (!pl) return fail(MOL_E_NOMEM, "host allocation failed");
+    mol_status s = build_plan(desc, pl, false);
+    if (s != MOL_OK) {
+        free_plan(pl);
+        return s;
+    }
+    hipGetDevice(&pl->dev);
+    pl->ws.assign(pl->nws, nullptr);
+    for (int i = 0; i < pl->nws; ++i) {
+        hipError_t e = hipMalloc(&pl->ws[i], (size_t)pl->npts * pl->es);
+        if (e != hipSuccess) {
+            free_plan(pl);
+            return fail(MOL_E_NOMEM, "hipMalloc of the workspace failed");
+        }
+        // workspace never holds stale non-finite values
+        hipMemset(pl->ws[i], 0, (size_t)pl->npts * pl->es);
+    }
+    hipDeviceSynchronize();
+    *out = pl;
+    return MOL_OK;
+}
+
+mol_status mol_plan_destroy(mol_plan *pl)
+{
+    if (!pl) return MOL_OK;
+    hipDeviceSynchronize();
+    free_plan(pl);
+    return MOL_OK;
+}
+
+mol_status mol_plan_get_info(const mol_plan *pl, mol_plan_info *info)
+{
+    if (!pl || !info) return fail(MOL_E_INVALID, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->beta = pl->beta;
+    info->beta_max = pl->betamax;
+    info->alpha = pl->alpha;
+    for (int a = 0; a < pl->geom.ndim; ++a) info->nu[a] = pl->dc[a].nu;
+    info->points = pl->npts;
+    info->unknowns = pl->unknowns;
+    info->segments[0] = pl->nsegs[0];
+    info->segments[1] = pl->nsegs[1];
+    info->kernels_per_step = (int)pl->step.size();
+    info->bytes_per_step = program_bytes(pl, pl->step);
+    info->workspace_bytes = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes;
+    return MOL_OK;
+}
+
+mol_status mol_start(mol_plan *pl, const void *u0, const void *g, void *u1, void *stream)
+{
+    if (!pl || !u0 || !u1) return fail(MOL_E_INVALID, "NULL argument");
+    if (g) return fail(MOL_E_UNSUPPORTED, "non-zero initial velocity is not provided");
+    if (u0 == u1) return fail(MOL_E_INVALID, "u0 and u1 must not overlap");
+    hipError_t e = run_program(pl, pl->start, nullptr, nullptr, nullptr, u0, u1, (hipStream_t)stream);
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_start");
+}
+
+mol_status mol_step(mol_plan *pl, const void *u_prev, const void *u_curr, void *u_next, void *stream)
+{
+    if (!pl || !u_prev || !u_curr || !u_next) return fail(MOL_E_INVALID, "NULL argument");
+    if (u_next == u_curr) return fail(MOL_E_INVALID, "u_next must not overlap u_curr");
+    hipError_t e = run_program(pl, pl->step, u_prev, u_curr, u_next, nullptr, nullptr,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_step");
+}
+
+mol_status mol_apply(mol_plan *pl, int op, const void *in, void *out, void *stream)
+{
+    if (!pl || !in || !out) return fail(MOL_E_INVALID, "NULL argument");
+    if (op < 0 || op > MOL_OP_RHS) return fail(MOL_E_INVALID, "unknown operator");
+    if (in == out) return fail(MOL_E_INVALID, "in and out must not overlap");
+    if (pl->apply[op].empty()) return fail(MOL_E_INVALID, "operator not available for this plan");
+    hipError_t e = run_program(pl, pl->apply[op], nullptr, nullptr, nullptr, in, out,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_apply");
+}
+
+mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *stream)
+{
+    if (!pl || !A || !B) return fail(MOL_E_INVALID, "NULL argument");
+    if (A == B) return fail(MOL_E_INVALID, "u_prev and u_curr must differ");
+    if (nsteps < 0) return fail(MOL_E_INVALID, "nsteps < 0");
+    if (nsteps == 0) return MOL_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool inc = (pl->desc.flags & MOL_INCREMENT_FORM) != 0;
+    const bool graph = !(pl->desc.flags & MOL_NO_GRAPH);
+    const size_t bytes = (size_t)pl->npts * pl->es;
+    hipError_t e;
+    if (inc) {
+        // A <- du = B - A, steps in place on (B, A), then A <- B - du
+        e = launch_axpby(pl->fp64, pl->npts, 1.0, B, -1.0, A, A, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve");
+    }
+    // one replay unit: increment form = 1 step in place; three-level = 2 steps
+    auto unit = [&](hipStream_t s) -> hipError_t {
+        if (inc) return run_program(pl, pl->inc_step, A, B, nullptr, nullptr, nullptr, s);
+        hipError_t r = run_program(pl, pl->step, A, B, A, nullptr, nullptr, s);
+        if (r != hipSuccess) return r;
+        return run_program(pl, pl->step, B, A, B, nullptr, nullptr, s);
+    };
+    const int64_t per = inc ? 1 : 2;
+    const int64_t reps = nsteps / per;
+    if (reps > 0) {
+        if (graph && st != nullptr) {
+            if (!pl->gexec || pl->gA != A || pl->gB != B || pl->ginc != (int)inc) {
+                if (pl->gexec) { hipGraphExecDestroy(pl->gexec); pl->gexec = nullptr; }
+                if (pl->graph) { hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+                e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return dev_err(e, "hipStreamBeginCapture");
+                hipError_t eu = unit(st);
+                hipGraph_t gr = nullptr;
+                e = hipStreamEndCapture(st, &gr);
+                if (eu != hipSuccess) { if (gr) hipGraphDestroy(gr); return dev_err(eu, "capture"); }
+                if (e != hipSuccess) return dev_err(e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0);
+                if (e != hipSuccess) { hipGraphDestroy(gr); return dev_err(e, "hipGraphInstantiate"); }
+                pl->graph = gr;
+                pl->gA = A;
+                pl->gB = B;
+                pl->ginc = (int)inc;
+            }
+            for (int64_t r = 0; r < reps; ++r) {
+                e = hipGraphLaunch(pl->gexec, st);
+                if (e != hipSuccess) return dev_err(e, "hipGraphLaunch");
+            }
+        } else {
+            for (int64_t r = 0; r < reps; ++r) {
+                e = unit(st);
+                if (e != hipSuccess) return dev_err(e, "mol_solve");
+            }
+        }
+    }
+    if (!inc && (nsteps % 2)) {
+        // odd count: one more step into A, then swap the contents of A and B
+        e = run_program(pl, pl->step, A, B, A, nullptr, nullptr, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve");
+        if (pl->nws < 1) return fail(MOL_E_DEVICE, "no workspace for the swap");
+        void *W = pl->ws[pl->nws - 1];
+        e = hipMemcpyAsync(W, A, bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(A, B, bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(B, W, bytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve swap");
+    }
+    if (inc) {
+        e = launch_axpby(pl->fp64, pl->npts, 1.0, B, -1.0, A, A, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve");
+    }
+    return MOL_OK;
+}
+
+mol_status mol_profile_step(mol_plan *pl, const void *u_prev, const void *u_curr, void *u_next,
+                            int reps, void *stream, int max, double *ms, double *bytes, int *dir,
+                            int *nsweep, int *count)
+{
+    if (!pl || !u_prev || !u_curr || !u_next || reps < 1) return fail(MOL_E_INVALID, "bad arguments");
+    const int nk = (int)pl->step.size();
+    if (count) *count = nk;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<hipEvent_t> ev(2 * (size_t)nk * reps);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(MOL_E_DEVICE, "hipEventCreate failed");
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        for (int i = 0; i < nk && e == hipSuccess; ++i) {
+            Program one(1, pl->step[i]);
+            e = hipEventRecord(ev[2 * ((size_t)r * nk + i)], st);
+            if (e == hipSuccess) e = run_program(pl, one, u_prev, u_curr, u_next, nullptr, nullptr, st);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * ((size_t)r * nk + i) + 1], st);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (int i = 0; i < nk && i < max && e == hipSuccess; ++i) {
+        double tot = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ev[2 * ((size_t)r * nk + i)], ev[2 * ((size_t)r * nk + i) + 1]);
+            tot += t;
+        }
+        const SweepOp &op = pl->step[i].op;
+        if (ms) ms[i] = tot / reps;
+        if (bytes) bytes[i] = (double)(op.nf + op.no) * (double)pl->npts * (double)pl->es;
+        if (dir) dir[i] = op.dir;
+        if (nsweep) nsweep[i] = op.ns;
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_profile_step");
+}
+
+mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
+                          const void *const *u_curr, void *const *u_next, int count, void *stream)
+{
+    if (count < 0 || (count > 0 && (!plans || !u_prev || !u_curr || !u_next)))
+        return fail(MOL_E_INVALID, "bad batch arguments");
+    for (int i = 0; i < count; ++i) {
+        mol_status s = mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream);
+        if (s != MOL_OK) return s;
+    }
+    return MOL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Plan state and the kernel-program builder shared by the plan sources.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/molt.h"
+#include "molt_internal.h"
+
+namespace molt {
+
+// buffer ids inside a program: caller fields, then plan workspace fields
+enum { B_UPREV = 0, B_UCURR = 1, B_UNEXT = 2, B_IN = 3, B_OUT = 4, B_WS0 = 5 };
+
+struct ProgOp {
+    SweepOp op;
+    int cfg[2];
+};
+typedef std::vector<ProgOp> Program;
+
+}  // namespace molt
+
+struct mol_plan_ {
+    mol_desc desc{};
+    molt::Geom geom{};
+    bool fp64 = false;
+    double beta = 0, betamax = 0, alpha = 0;
+    molt::DirCoef dc[3]{};
+    int64_t npts = 0, unknowns = 0;
+    size_t es = 8;
+    int nws = 0;                       // workspace fields
+    std::vector<void *> ws;            // device workspace fields
+    molt::Program step, start, inc_step;
+    molt::Program apply[9];
+    int dev = 0;
+    // graph cache for mol_solve
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void *gA = nullptr, *gB = nullptr;
+    int ginc = -1;
+    // masked plans (embedded boundary)
+    bool masked = false;
+    molt::SegTable seg[2];
+    unsigned char *d_mask = nullptr;
+    int64_t nsegs[2] = {0, 0};
+    size_t table_bytes = 0;
+    std::vector<unsigned char> h_mask;  // kept for table construction
+    std::vector<double> h_cross;
+};
+
+namespace molt {
+
+// linear expression over buffers
+typedef std::vector<std::pair<int, double>> Lin;
+
+inline Lin lin(int b, double c = 1.0) { return Lin{{b, c}}; }
+inline Lin operator+(Lin a, const Lin &b)
+{
+    a.insert(a.end(), b.begin(), b.end());
+    return a;
+}
+inline Lin operator*(double s, Lin a)
+{
+    for (auto &t : a) t.second *= s;
+    return a;
+}
+
+struct OutSpec {
+    int buf;
+    Lin elem;
+    double dc[MAXS];
+};
+
+struct Builder {
+    mol_plan_ &pl;
+    bool dry;
+    std::string err;
+    explicit Builder(mol_plan_ &p, bool d) : pl(p), dry(d) {}
+
+    int new_ws() { return B_WS0 + pl.nws++; }
+
+    // one directional launch: combos = swept combinations, outs = outputs
+    bool emit(Program &prog, int dir, const std::vector<Lin> &combos,
+              const std::vector<OutSpec> &outs, int proj);
+};
+
+// How the right-hand side sum_{p,m} c_{p,m} C^m D^{p-m} u is consumed: each
+// final output = elem + r * rhs.
+struct FinalOut {
+    int buf;
+    Lin elem;
+    double r;
+};
+
+std::vector<OutSpec> finals(const std::vector<FinalOut> &fo, const Lin &rhs_elem, double rhs_dcoef);
+double stage_c(int p, int m, double beta);
+double A_p(int p, double beta);
+int strided_tile_nodes(int cfgid);
+
+// masked (embedded boundary) plans
+bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo);
+bool build_apply_masked(Builder &b, Program &prog, int op);
+mol_status masked_tables(mol_plan_ *pl, bool dry, std::string &err);
+void masked_free(mol_plan_ *pl);
+hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *const *fptr,
+                         void *const *optr, hipStream_t st);
+
+}  // namespace molt

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libmolt.so (the C-ABI declared in include/molt.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  torch supplies device memory and streams.  If the shared library is
+missing this module raises at import time; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmolt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmolt.so is not built (run __graft_entry__.build() or "
+                      "python paper_1308_3214_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes / enums (include/molt.h)
+MOL_OK, MOL_E_INVALID, MOL_E_UNSUPPORTED, MOL_E_UNSTABLE, MOL_E_NOMEM, MOL_E_DEVICE = range(6)
+DIRICHLET, PERIODIC = 0, 1
+F64, F32 = 0, 1
+ALLOW_UNSTABLE, INCREMENT_FORM, NO_GRAPH = 1, 2, 4
+OPS = {"linv_x": 0, "linv_y": 1, "linv_z": 2, "d_x": 3, "d_y": 4, "d_z": 5, "C": 6, "D": 7, "rhs": 8}
+_STATUS = {1: "MOL_E_INVALID", 2: "MOL_E_UNSUPPORTED", 3: "MOL_E_UNSTABLE", 4: "MOL_E_NOMEM",
+           5: "MOL_E_DEVICE"}
+
+
+class MolError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int64 * 3),
+        ("h", ctypes.c_double * 3),
+        ("bc", ctypes.c_int * 3),
+        ("mask", ctypes.c_void_p),
+        ("cross", ctypes.c_void_p),
+        ("P", ctypes.c_int),
+        ("c", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("dtype", ctypes.c_int),
+        ("flags", ctypes.c_int),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [
+        ("beta", ctypes.c_double),
+        ("beta_max", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("nu", ctypes.c_double * 3),
+        ("points", ctypes.c_int64),
+        ("unknowns", ctypes.c_int64),
+        ("segments", ctypes.c_int64 * 2),
+        ("kernels_per_step", ctypes.c_int),
+        ("bytes_per_step", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+_vp = ctypes.c_void_p
+_lib.mol_beta_max.argtypes = [ctypes.c_int]
+_lib.mol_beta_max.restype = ctypes.c_double
+_lib.mol_last_error.restype = ctypes.c_char_p
+_lib.mol_workspace_bytes.argtypes = [ctypes.POINTER(_Desc)]
+_lib.mol_workspace_bytes.restype = ctypes.c_size_t
+_lib.mol_plan_create.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_vp)]
+_lib.mol_plan_destroy.argtypes = [_vp]
+_lib.mol_plan_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
+_lib.mol_start.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.mol_step.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.mol_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
+_lib.mol_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+_lib.mol_step_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                ctypes.POINTER(_vp), ctypes.c_int, _vp]
+_lib.mol_profile_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int)]
+for _f in ("mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
+           "mol_solve", "mol_apply", "mol_step_batch"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
+           "mol_workspace_bytes", "mol_start", "mol_step", "mol_solve", "mol_step_batch",
+           "mol_apply", "mol_profile_step", "mol_last_error")
+
+
+def _check(st):
+    if st != MOL_OK:
+        raise MolError(st, _lib.mol_last_error().decode())
+
+
+def beta_max(P: int) -> float:
+    return float(_lib.mol_beta_max(int(P)))
+
+
+def last_error() -> str:
+    return _lib.mol_last_error().decode()
+
+
+def make_desc(shape, h, bc=DIRICHLET, P=2, c=1.0, dt=None, cfl=None, beta=0.0, dtype="f64",
+              flags=0, mask=None, cross=None):
+    """Descriptor for a field of array shape ``shape`` (C order, x last).
+    Give either dt or cfl (dt = cfl * h_x / c)."""
+    shape = tuple(int(s) for s in shape)
+    nd = len(shape)
+    nx = list(reversed(shape))
+    hh = list(h) if np.ndim(h) else [float(h)] * nd
+    bb = list(bc) if np.ndim(bc) else [int(bc)] * nd
+    if dt is None:
+        dt = float(cfl) * hh[0] / c
+    d = _Desc()
+    d.ndim = nd
+    for a in range(3):
+        d.n[a] = nx[a] if a < nd else 1
+        d.h[a] = float(hh[a]) if a < nd else 1.0
+        d.bc[a] = int(bb[a]) if a < nd else 0
+    keep = []
+    if mask is not None:
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        keep.append(m)
+        d.mask = m.ctypes.data
+    if cross is not None:
+        cr = np.ascontiguousarray(cross, dtype=np.float64)
+        keep.append(cr)
+        d.cross = cr.ctypes.data
+    d.P = int(P)
+    d.c = float(c)
+    d.dt = float(dt)
+    d.beta = float(beta)
+    d.dtype = F64 if dtype in ("f64", "float64", F64) else F32
+    d.flags = int(flags)
+    return d, keep
+
+
+def workspace_bytes(**kw) -> int:
+    d, keep = make_desc(**kw)
+    return int(_lib.mol_workspace_bytes(ctypes.byref(d)))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A solver plan bound to the current device.  Fields are torch tensors of
+    the plan's dtype and shape, on that device, contiguous."""
+
+    def __init__(self, shape, h, bc=DIRICHLET, P=2, c=1.0, dt=None, cfl=None, beta=0.0,
+                 dtype="f64", flags=0, mask=None, cross=None):
+        d, keep = make_desc(shape, h, bc, P, c, dt, cfl, beta, dtype, flags, mask, cross)
+        self.shape = tuple(int(s) for s in shape)
+        self.fp64 = d.dtype == F64
+        self._h = _vp()
+        _check(_lib.mol_plan_create(ctypes.byref(d), ctypes.byref(self._h)))
+        del keep
+        info = _Info()
+        _check(_lib.mol_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = {
+            "beta": info.beta, "beta_max": info.beta_max, "alpha": info.alpha,
+            "nu": tuple(info.nu), "points": info.points, "unknowns": info.unknowns,
+            "segments": tuple(info.segments), "kernels_per_step": info.kernels_per_step,
+            "bytes_per_step": info.bytes_per_step, "workspace_bytes": info.workspace_bytes,
+        }
+
+    def close(self):
+        if self._h:
+            _lib.mol_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _t(self, x):
+        import torch
+        want = torch.float64 if self.fp64 else torch.float32
+        if not isinstance(x, torch.Tensor) or x.dtype != want or not x.is_cuda \
+                or tuple(x.shape) != self.shape or not x.is_contiguous():
+            raise ValueError("expected a contiguous %s CUDA tensor of shape %s" % (want, self.shape))
+        return ctypes.c_void_p(x.data_ptr())
+
+    def start(self, u0, u1, stream=None):
+        _check(_lib.mol_start(self._h, self._t(u0), None, self._t(u1), _stream(stream)))
+
+    def step(self, u_prev, u_curr, u_next, stream=None):
+        _check(_lib.mol_step(self._h, self._t(u_prev), self._t(u_curr), self._t(u_next),
+                             _stream(stream)))
+
+    def solve(self, u_prev, u_curr, nsteps, stream=None):
+        _check(_lib.mol_solve(self._h, self._t(u_prev), self._t(u_curr), int(nsteps),
+                              _stream(stream)))
+
+    def profile_step(self, u_prev, u_curr, u_next, reps=10, stream=None):
+        """Per-kernel mean duration (ms) and algorithmic bytes of one step,
+        from hipEvents around each launch."""
+        mx = 64
+        ms = (ctypes.c_double * mx)()
+        by = (ctypes.c_double * mx)()
+        dr = (ctypes.c_int * mx)()
+        ns = (ctypes.c_int * mx)()
+        cnt = ctypes.c_int()
+        _check(_lib.mol_profile_step(self._h, self._t(u_prev), self._t(u_curr), self._t(u_next),
+                                     int(reps), _stream(stream), mx, ms, by, dr, ns,
+                                     ctypes.byref(cnt)))
+        return [{"ms": ms[i], "bytes": by[i], "dir": "xyz"[dr[i]], "sweeps": ns[i]}
+                for i in range(min(cnt.value, mx))]
+
+    def apply(self, op, x, out, stream=None):
+        code = OPS[op] if isinstance(op, str) else int(op)
+        _check(_lib.mol_apply(self._h, code, self._t(x), self._t(out), _stream(stream)))
+
+
+def step_batch(plans, u_prev, u_curr, u_next, stream=None):
+    n = len(plans)
+    arr = lambda xs: (_vp * n)(*[ctypes.c_void_p(x) for x in xs])  # noqa: E731
+    hs = (_vp * n)(*[p.handle for p in plans])
+    _check(_lib.mol_step_batch(hs, arr([t.data_ptr() for t in u_prev]),
+                               arr([t.data_ptr() for t in u_curr]),
+                               arr([t.data_ptr() for t in u_next]), n, _stream(stream)))

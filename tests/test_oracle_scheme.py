@@ -209,3 +209,29 @@ def test_embedded_cavity_bounded(oracle_mod):
     a, c = pb.run(u0, pb.start(u0, P, b), 300, P, b)
     assert np.isfinite(c).all() and np.abs(c).max() < 2 * np.abs(u0).max()
     assert (c[mask == 0] == 0).all()
+
+
+def test_long_run_reference_precision(oracle_mod):
+    # 1D standing modes, N = 1024, P = 1, CFL = 2, 200 steps: both builds of
+    # the oracle against the exact evolution of the two eigenmodes.  The FP64
+    # build drifts (cancellation in D = v - L^{-1} v on smooth data); the
+    # 80-bit build stays at rounding level and serves as the long-run reference.
+    n = 1024
+    h = 1.0 / (n - 1)
+    x, u0, amps = W.sine_modes_1d(n, seed=1)
+    P = 1
+    b = scheme.beta_max(P)
+    alpha = b / (2 * h)
+    exact = np.zeros(n)
+    for A, k in zip(amps, (1, 3)):
+        Dh = 1 - cf.khat(mp.pi * k * h, alpha * h)
+        r = cf.rhs_symbol(P, b, Dh, Dh)
+        exact += float(A * cf.mode_sequence(r, 1, 1 + r / 2, 200)[200]) * np.sin(k * np.pi * x)
+    exact[0] = exact[-1] = 0.0
+    errs = {}
+    for prec in ("f64", "ld"):
+        pb = oracle_mod.Problem((n,), h, 0, alpha, precision=prec)
+        _, c = pb.run(u0, pb.start(u0, P, b), 199, P, b)
+        errs[prec] = np.linalg.norm(c - exact) / np.linalg.norm(exact)
+    assert errs["ld"] < 5e-14, errs
+    assert errs["f64"] < 1e-9, errs
