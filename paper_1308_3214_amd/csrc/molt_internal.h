@@ -37,6 +37,8 @@ struct SweepOp {
     double mOF[MAXO][MAXF] = {};
     double mOD[MAXO][MAXS] = {};
     int proj = 0;        // write 0 on every Dirichlet boundary node of the outputs
+    int chain = 0;       // x sweeps: also write D_x(out_0) to buffer ochain
+    int ochain = -1;
 };
 
 // Geometry of a full box grid (x fastest).
@@ -46,7 +48,8 @@ struct Geom {
     int dirichlet[3];
 };
 
-// Launch one sweep.  ptrs: resolved device pointers for op.f / op.o.
+// Launch one sweep.  ptrs: resolved device pointers for op.f / op.o (followed
+// by the chained output when op.chain is set).
 // Returns hipSuccess or the launch error.
 hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
                         const void *const *fptr, void *const *optr, const int *cfg,

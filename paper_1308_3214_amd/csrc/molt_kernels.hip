@@ -37,6 +37,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "molt_internal.h"
 
 namespace molt {
@@ -50,6 +52,8 @@ struct KArgs {
     T mOD[MAXO][MAXS];
     int nf;
     int proj;
+    int chain;        // x: also write D_x(out_0) to ochain (next sweep of out_0)
+    T *ochain;
     int64_t n;        // nodes per line
     int64_t nlines;   // x: lines; strided: columns (x extent)
     int64_t lineoff;  // x: element offset between lines
@@ -62,6 +66,8 @@ struct KArgs {
     int aligned;      // x: vector loads allowed
     int periodic;     // along the sweep
     T d, g, w2;
+    T gw;             // g + w2
+    T dpow[33];       // d^0 .. d^32
     T dS;             // d^S
     T dBlk;           // x: d^{64 S} (one wave of lanes)
     double nu;
@@ -178,87 +184,134 @@ __device__ __forceinline__ void seg_close(T (&sum)[S], T cL, T cR, double A, dou
     }
 }
 
+// Branch-free recurrences for a segment whose nodes are all interior nodes of
+// a Dirichlet line or of a periodic line (values outside the line read as 0).
+// With dl_j = v_j - v_{j-1}:  F^L_j = w2 dl_{j+1} - (g + w2) dl_j,
+// F^R_j = (g + w2) dl_{j+1} - w2 dl_j.
+template <typename T, int S>
+__device__ __forceinline__ void seg_recur_fast(const T (&v)[S + 2], T d, T gw, T w2, T (&sum)[S],
+                                               T &aL, T &aR)
+{
+    T dl[S + 1];
+#pragma unroll
+    for (int j = 0; j <= S; ++j) dl[j] = v[j + 1] - v[j];
+    T e = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        e = d * e + (w2 * dl[j + 1] - gw * dl[j]);
+        sum[j] = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        e = d * e + (gw * dl[j + 1] - w2 * dl[j]);
+        sum[j] += e;
+    }
+    aR = e;
+}
+
+// Dirichlet end nodes inside a segment handled by seg_recur_fast: at node 0 the
+// forcing must be F^L = 0, F^R = g v_1 and at node M F^L = g v_{M-1}, F^R = 0
+// (no curvature at a boundary node); the branch-free forcing is off by
+// -w2 v_1 (node 0) and -w2 v_{M-1} (node M) in both directions.  The linear
+// recurrences carry these corrections with powers of d.  v1 = value at node 1,
+// vM1 = value at node M-1 (read by the caller).  Returns E^L_M (local) in eLM.
+template <typename T, int S>
+__device__ __forceinline__ void seg_fix_dirichlet(int p0, int M, T v1, T vM1, T d, T w2,
+                                                  T (&sum)[S], T &aL, T &aR, T &eLM)
+{
+    if (p0 == 0) {
+        const T c = -w2 * v1;
+        T pw = c, last = c;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            sum[j] += pw;                 // forward: c d^j
+            last = pw;
+            pw *= d;
+        }
+        aL += last;                       // c d^{S-1}
+        sum[0] += c;                      // backward: node 0 only
+        aR += c;
+    }
+    const int jm = M - p0;
+    if (jm >= 0 && jm < S) {
+        const T c = -w2 * vM1;
+        T pf = c, pb = c, lf = T(0), lb = T(0);
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (j >= jm) { sum[j] += pf; lf = pf; pf *= d; }
+        }
+#pragma unroll
+        for (int j = S - 1; j >= 0; --j) {
+            if (j <= jm) { sum[j] += pb; lb = pb; pb *= d; }
+        }
+        aL += lf;                         // c d^{S-1-jm}
+        aR += lb;                         // c d^{jm}
+        T em = T(0);
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            if (j == jm) em = sum[j];     // E^R_M = 0 locally: sum = E^L_M
+        eLM = em;
+    }
+}
+
+// Closure for a segment: D_j = -(sum_j + d^{j+1} cL + d^{S-j} cR + A d^p + B d^{M-p}).
+// Interior segments use two decaying terms with d^j from the kernel
+// arguments; a segment holding node M (or nodes beyond it) adds the B term
+// node by node and zeroes what lies beyond M; Dirichlet end nodes get D = 0.
+template <typename T, int S>
+__device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A, double B, int p0,
+                                               int M, double nu, T d, const T *dpow, bool dir_end)
+{
+    const int jm = M - p0;
+    const bool holdsM = jm < S;
+    const T lt = d * cL + (T)((A != 0.0) ? A * exp(-nu * (double)p0) : 0.0);
+    const T rt = d * cR + (T)((!holdsM && B != 0.0) ? B * exp(-nu * (double)(jm - (S - 1))) : 0.0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) sum[j] = -(sum[j] + lt * dpow[j] + rt * dpow[S - 1 - j]);
+    if (holdsM) {
+        double pw = B;
+        const double dd = exp(-nu);
+#pragma unroll
+        for (int j = S - 1; j >= 0; --j) {
+            if (j > jm) {
+                sum[j] = T(0);
+            } else {
+                sum[j] -= (T)pw;
+                pw *= dd;
+            }
+        }
+        if (dir_end) {
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                if (j == jm) sum[j] = T(0);
+        }
+    }
+    if (dir_end && p0 == 0) sum[0] = T(0);
+}
+
 // ---------------------------------------------------------------------------
 // x sweep: contiguous lines, one line per workgroup of NT = 64*WPL threads
 // ---------------------------------------------------------------------------
-template <typename T, int S, int WPL, int NS, int NO, int VW>
-__global__ void __launch_bounds__(64 * WPL)
-k_sweep_x(const KArgs<T> a)
+// D_x of NSW combinations staged in LDS (sm + k*NPAD, padded slots); the D
+// values replace the inputs in place.  Ends with a __syncthreads.
+template <typename T, int S, int WPL, int NSW>
+__device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)[MAXS][WPL],
+                                             T (*ends)[MAXS], int t, int n)
 {
     constexpr int NT = 64 * WPL;
     constexpr int NPAD = NT * (S + 1);
-    constexpr int NV = S / VW;
-    typedef T vec_t __attribute__((ext_vector_type(VW)));
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
-    __shared__ T wtot[2][NS][WPL];
-    __shared__ T ends[2][NS];
-
-    const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int64_t line = blockIdx.x;
-    const int n = (int)a.n;
     const int M = n - 1;
-    const int64_t base = line * a.lineoff;            // uniform per workgroup
-    const bool dir_end = !a.periodic;
-
-    bool bline = false;
-    if (a.proj) {
-        const int64_t i1 = line % a.pn1, i2 = line / a.pn1;
-        bline = (a.pd1 && (i1 == 0 || i1 == a.pn1 - 1)) || (a.pd2 && (i2 == 0 || i2 == a.pn2 - 1));
-    }
-
-    // ---- phase 1: coalesced loads, prologue combinations -> LDS ----
-    T ev[NO][S];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const int e0 = (i * NT + t) * VW;
-        T sv[NS][VW], ee[NO][VW];
-#pragma unroll
-        for (int c = 0; c < VW; ++c) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) sv[k][c] = T(0);
-#pragma unroll
-            for (int o = 0; o < NO; ++o) ee[o][c] = T(0);
-        }
-        for (int f = 0; f < a.nf; ++f) {
-            T x[VW];
-            const T *src = a.f[f] + base;
-            if (a.aligned && e0 + VW <= n) {
-                const vec_t vv = *reinterpret_cast<const vec_t *>(src + e0);
-#pragma unroll
-                for (int c = 0; c < VW; ++c) x[c] = vv[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < VW; ++c) x[c] = (e0 + c < n) ? src[e0 + c] : T(0);
-            }
-#pragma unroll
-            for (int c = 0; c < VW; ++c) {
-#pragma unroll
-                for (int k = 0; k < NS; ++k) sv[k][c] += a.mS[k][f] * x[c];
-#pragma unroll
-                for (int o = 0; o < NO; ++o) ee[o][c] += a.mOF[o][f] * x[c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < VW; ++c) {
-            const int e = e0 + c;
-            const int slot = (e / S) * (S + 1) + (e % S);
-            const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
-#pragma unroll
-            for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][c];
-#pragma unroll
-            for (int o = 0; o < NO; ++o) ev[o][i * VW + c] = ee[o][c];
-        }
-    }
-    __syncthreads();
-
-    // ---- phase 2: recurrences over the lane's S nodes ----
     const int p0 = t * S;
-    T sum[NS][S];
-    T aL[NS], aR[NS], eLM[NS];
+    const int jm = M - p0;
+    const bool dir_end = !a.periodic;
+    const bool slow = a.periodic && (p0 + S - 1 > M);   // periodic lane crossing the end
+    T sum[NSW][S];
+    T aL[NSW], aR[NSW], eLM[NSW];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
+    for (int k = 0; k < NSW; ++k) {
         const T *sk = sm + k * NPAD;
         T v[S + 2];
 #pragma unroll
@@ -266,14 +319,24 @@ k_sweep_x(const KArgs<T> a)
         if (p0 == 0) v[0] = a.periodic ? sk[(M / S) * (S + 1) + (M % S)] : T(0);
         else v[0] = sk[(t - 1) * (S + 1) + (S - 1)];
         v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
-        if (a.periodic && M >= p0 && M < p0 + S) v[M - p0 + 2] = sk[0];  // wrap at node M
-        seg_recur<T, S>(v, p0, M, dir_end, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+        if (a.periodic && jm >= 0 && jm < S) v[jm + 2] = sk[0];   // wrap at node M
+        if (slow) {
+            seg_recur<T, S>(v, p0, M, false, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+        } else {
+            seg_recur_fast<T, S>(v, a.d, a.gw, a.w2, sum[k], aL[k], aR[k]);
+            eLM[k] = aL[k];                            // periodic: node M ends its lane
+            if (dir_end) {
+                const T v1 = (p0 == 0 && n > 1) ? sk[1] : T(0);
+                const int q = M - 1;
+                const T vM1 = (jm >= 0 && jm < S && q >= 0) ? sk[(q / S) * (S + 1) + (q % S)] : T(0);
+                seg_fix_dirichlet<T, S>(p0, M, v1, vM1, a.d, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+            }
+        }
     }
-
     // lane scan (multiplier d^S per lane), then waves through LDS
-    T cL[NS], cR[NS];
+    T cL[NSW], cR[NSW];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
+    for (int k = 0; k < NSW; ++k) {
         T xl = aL[k], xr = aR[k], m = a.dS;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -297,7 +360,7 @@ k_sweep_x(const KArgs<T> a)
         const T pl = (T)exp(-a.nu * (double)S * (double)lane);
         const T pr = (T)exp(-a.nu * (double)S * (double)(63 - lane));
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
+        for (int k = 0; k < NSW; ++k) {
             T cw = T(0), cwr = T(0);
             for (int w = 0; w < wave; ++w) cw = a.dBlk * cw + wtot[0][k][w];
             for (int w = WPL - 1; w > wave; --w) cwr = a.dBlk * cwr + wtot[1][k][w];
@@ -307,27 +370,98 @@ k_sweep_x(const KArgs<T> a)
     }
     // line ends: E^R_0 (lane holding node 0) and E^L_M (lane holding node M)
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
+    for (int k = 0; k < NSW; ++k) {
         if (p0 == 0) ends[0][k] = aR[k] + a.dS * cR[k];
-        if (M >= p0 && M < p0 + S) {
-            const int jm = M - p0;
-            ends[1][k] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
-        }
+        if (jm >= 0 && jm < S) ends[1][k] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
     }
     __syncthreads();
-
-    // ---- phase 3: closure, D values back into LDS ----
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
+    for (int k = 0; k < NSW; ++k) {
         const double er0 = (double)ends[0][k], elm = (double)ends[1][k];
         const double A = a.K00 * er0 + a.K01 * elm;
         const double B = a.K10 * er0 + a.K11 * elm;
-        seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end);
+        if (slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, false);
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, a.dpow, dir_end);
         T *sk = sm + k * NPAD;
 #pragma unroll
         for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
     }
     __syncthreads();
+}
+
+template <typename T, int S, int WPL, int NS, int NO, int VW>
+__global__ void __launch_bounds__(64 * WPL)
+k_sweep_x(const KArgs<T> a)
+{
+    constexpr int NT = 64 * WPL;
+    constexpr int NPAD = NT * (S + 1);
+    constexpr int NV = S / VW;
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
+    __shared__ T wtot[2][MAXS][WPL];
+    __shared__ T ends[2][MAXS];
+
+    const int t = threadIdx.x;
+    const int64_t line = blockIdx.x;
+    const int n = (int)a.n;
+    const int M = n - 1;
+    const int64_t base = line * a.lineoff;            // uniform per workgroup
+    const bool dir_end = !a.periodic;
+
+    bool bline = false;
+    if (a.proj) {
+        const int64_t i1 = line % a.pn1, i2 = line / a.pn1;
+        bline = (a.pd1 && (i1 == 0 || i1 == a.pn1 - 1)) || (a.pd2 && (i2 == 0 || i2 == a.pn2 - 1));
+    }
+
+    // ---- phase 1: coalesced loads (all of one field at once), prologue ----
+    T sv[NS][S], ev[NO][S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sv[k][j] = T(0);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) ev[o][j] = T(0);
+    }
+    for (int f = 0; f < a.nf; ++f) {
+        const T *src = a.f[f] + base;
+        T x[S];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int e0 = (i * NT + t) * VW;
+            if (a.aligned && e0 + VW <= n) {
+                const vec_t vv = *reinterpret_cast<const vec_t *>(src + e0);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) x[i * VW + c] = vv[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < VW; ++c) x[i * VW + c] = (e0 + c < n) ? src[e0 + c] : T(0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sv[k][j] += a.mS[k][f] * x[j];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ev[o][j] += a.mOF[o][f] * x[j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int e = (i * NT + t) * VW + c;
+            const int slot = (e / S) * (S + 1) + (e % S);
+            const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][i * VW + c];
+        }
+    }
+    __syncthreads();
+
+    // ---- phases 2-3: recurrences, scans, closure (D in LDS) ----
+    x_line_sweep<T, S, WPL, NS>(a, sm, wtot, ends, t, n);
 
     // ---- phase 4: epilogue in the coalesced layout ----
 #pragma unroll
@@ -364,6 +498,42 @@ k_sweep_x(const KArgs<T> a)
                     if (e0 + c < n) dst[e0 + c] = out[o][c];
             }
         }
+        if (a.chain) {
+            // the next x sweep of output 0 starts from these values (each
+            // slot is read and rewritten by the same thread only)
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+                const int e = e0 + c;
+                const int slot = (e / S) * (S + 1) + (e % S);
+                const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
+                sm[slot] = zero ? T(0) : out[0][c];
+            }
+        }
+    }
+    if (a.chain) {
+        __syncthreads();
+        x_line_sweep<T, S, WPL, 1>(a, sm, wtot, ends, t, n);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int e0 = (i * NT + t) * VW;
+            T out[VW];
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+                const int e = e0 + c;
+                out[c] = sm[(e / S) * (S + 1) + (e % S)];
+            }
+            T *dst = a.ochain + base;
+            if (a.aligned && e0 + VW <= n) {
+                vec_t vv;
+#pragma unroll
+                for (int c = 0; c < VW; ++c) vv[c] = out[c];
+                *reinterpret_cast<vec_t *>(dst + e0) = vv;
+            } else {
+#pragma unroll
+                for (int c = 0; c < VW; ++c)
+                    if (e0 + c < n) dst[e0 + c] = out[c];
+            }
+        }
     }
 }
 
@@ -398,6 +568,57 @@ k_sweep_s(const KArgs<T> a)
     const int ob = (oa + WS < n) ? oa + WS : n;
     const bool split = a.ntiles > 1;
     const int K = a.halo;
+    const int p0 = oa + wave * S;
+
+    // ---- main nodes p0-1 .. p0+S: all rows of one field issued together ----
+    T ev[NO][S];
+    T v[NS][S + 2];
+#pragma unroll
+    for (int j = 0; j < S + 2; ++j) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) v[k][j] = T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) ev[o][j] = T(0);
+    }
+    for (int f = 0; f < a.nf; ++f) {
+        const T *src = a.f[f] + blk;
+        T x[S + 2];
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            int p = p0 - 1 + j;
+            bool inside;
+            if (per) {
+                p %= n;
+                if (p < 0) p += n;
+                inside = true;
+            } else {
+                inside = (p >= 0 && p <= M);
+            }
+            x[j] = (inside && active) ? src[loff + p * ls] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) v[k][j] += a.mS[k][f] * x[j];
+            if (j >= 1 && j <= S) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) ev[o][j - 1] += a.mOF[o][f] * x[j];
+            }
+        }
+    }
+    if (dir_end) {
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            const int p = p0 - 1 + j;
+            if (p == 0 || p == M) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) v[k][j] = T(0);
+            }
+        }
+    }
 
     // swept combination k at node p of this column (0 outside / at Dirichlet ends)
     auto sval = [&](int k, int p) -> T {
@@ -458,6 +679,28 @@ k_sweep_s(const KArgs<T> a)
         __syncthreads();
     };
 
+    // ---- local recurrences of this wave's S nodes ----
+    const int jm = M - p0;
+    const bool slow = per && (p0 + S - 1 > M);          // periodic wave crossing the end
+    T sum[NS][S];
+    T aL[NS], aR[NS], eLM[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (slow) {
+            seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
+        } else {
+            seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
+            eLM[k] = aL[k];
+            if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
+                T vM1 = T(0);
+#pragma unroll
+                for (int j = 0; j < S + 2; ++j)
+                    if (j == jm) vM1 = v[k][j];            // node M-1
+                seg_fix_dirichlet<T, S>(p0, M, v[k][2], vM1, d, w2, sum[k], aL[k], aR[k], eLM[k]);
+            }
+        }
+    }
+
     // ---- carries entering the tile, and line-end values for split lines ----
     T cTop[NS], cBot[NS], er0s[NS], elms[NS];
 #pragma unroll
@@ -475,50 +718,8 @@ k_sweep_s(const KArgs<T> a)
         if (needA || needB) coop(0, +1, needA, M, -1, needB, er0s, elms);
     }
 
-    // ---- main nodes p0 .. p0+S-1: load S+2 nodes once, form combinations ----
-    const int p0 = oa + wave * S;
-    T ev[NO][S];
-    T v[NS][S + 2];
-#pragma unroll
-    for (int j = 0; j < S + 2; ++j) {
-        int p = p0 - 1 + j;
-        bool inside;
-        if (per) {
-            p %= n;
-            if (p < 0) p += n;
-            inside = true;
-        } else {
-            inside = (p >= 0 && p <= M);
-        }
-        T sk[NS], eo[NO];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) sk[k] = T(0);
-#pragma unroll
-        for (int o = 0; o < NO; ++o) eo[o] = T(0);
-        if (inside && active) {
-            const int off = loff + p * ls;
-            for (int f = 0; f < a.nf; ++f) {
-                const T x = a.f[f][blk + off];
-#pragma unroll
-                for (int k = 0; k < NS; ++k) sk[k] += a.mS[k][f] * x;
-#pragma unroll
-                for (int o = 0; o < NO; ++o) eo[o] += a.mOF[o][f] * x;
-            }
-        }
-        const bool zero = !inside || (dir_end && (p == 0 || p == M));
-#pragma unroll
-        for (int k = 0; k < NS; ++k) v[k][j] = zero ? T(0) : sk[k];
-        if (j >= 1 && j <= S) {
-#pragma unroll
-            for (int o = 0; o < NO; ++o) ev[o][j - 1] = eo[o];
-        }
-    }
-
-    T sum[NS][S];
-    T aL[NS], aR[NS], eLM[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        seg_recur<T, S>(v[k], p0, M, dir_end, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
         red[0][k][wave][lane] = aL[k];
         red[1][k][wave][lane] = aR[k];
     }
@@ -540,10 +741,7 @@ k_sweep_s(const KArgs<T> a)
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             if (p0 == 0) endv[0][k][lane] = aR[k] + a.dS * cR[k];
-            if (M >= p0 && M < p0 + S) {
-                const int jm = M - p0;
-                endv[1][k][lane] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
-            }
+            if (jm >= 0 && jm < S) endv[1][k][lane] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
         }
         __syncthreads();
     }
@@ -567,9 +765,13 @@ k_sweep_s(const KArgs<T> a)
         } else if (botAsB) {
             B = (double)d * (double)cBot[k];     // cBot d^{n-p} = (d cBot) d^{M-p}
         }
-        seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, dir_end);
+        if (slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, false);
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, a.dpow, dir_end);
     }
     if (!active) return;
+    T *dst[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) dst[o] = a.o[o] + blk;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int p = p0 + j;
@@ -581,7 +783,7 @@ k_sweep_s(const KArgs<T> a)
             T r = ev[o][j];
 #pragma unroll
             for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * sum[k][j];
-            a.o[o][blk + off] = z ? T(0) : r;
+            dst[o][off] = z ? T(0) : r;
         }
     }
 }
@@ -643,6 +845,10 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
     k.d = (T)dc.d;
     k.g = (T)dc.g;
     k.w2 = (T)dc.w2;
+    k.gw = (T)(dc.g + dc.w2);
+    for (int j = 0; j < 33; ++j) k.dpow[j] = (T)std::exp(-dc.nu * (double)j);
+    k.chain = op.chain;
+    k.ochain = op.chain ? static_cast<T *>(optr[op.no]) : nullptr;
     k.nu = dc.nu;
     k.K00 = dc.K[0][0];
     k.K01 = dc.K[0][1];

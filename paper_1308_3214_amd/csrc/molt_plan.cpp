@@ -159,7 +159,7 @@ DirCoef make_dircoef(double nu, int64_t n, bool periodic, bool fp64)
 namespace molt {
 
 bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
-                   const std::vector<OutSpec> &outs, int proj)
+                   const std::vector<OutSpec> &outs, int proj, int chain_buf)
 {
 
         const int ns = (int)combos.size(), no = (int)outs.size();
@@ -195,11 +195,17 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
             err = "no kernel configuration fits this line length";
             return false;
         }
+        if (chain_buf >= 0 && dir != 0) {
+            err = "internal: chained sweeps are x sweeps";
+            return false;
+        }
         SweepOp op;
         op.dir = dir;
         op.ns = ns;
         op.no = no;
         op.proj = proj;
+        op.chain = chain_buf >= 0 ? 1 : 0;
+        op.ochain = chain_buf;
         std::vector<int> fields;
         auto fid = [&](int b) -> int {
             for (size_t i = 0; i < fields.size(); ++i)
@@ -271,7 +277,8 @@ bool build_rhs_1d(Builder &b, Program &prog, int u, const std::vector<FinalOut> 
 //   2D: C v = D_x(v - 2y) + y,  D v = D_x(v - y) + y,  y = D_y v
 //   3D: C v = D_x(v - 2y - 2z + 3yz) + (y + z - 2yz),
 //       D v = D_x(v - y - z + yz) + (y + z - yz),  z = D_z v, y = D_y v, yz = D_y z
-bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo)
+bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo,
+                   int chain_a = -1)
 {
     mol_plan_ &pl = b.pl;
     const int P = pl.desc.P;
@@ -279,7 +286,20 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
     const double beta = pl.beta;
     std::vector<int> v{u};      // inputs of the current stage
     int accbuf = -1;            // accumulated earlier-stage terms (stage >= 3)
-    for (int p = 1; p <= P; ++p) {
+    int pfirst = 1;
+    if (chain_a >= 0) {
+        // 2D, P >= 2: stage 1 in the order x then y, with a = D_x u written by
+        // the previous step's last sweep: C u = D_y(u - 2a) + a
+        const int v1 = b.new_ws();
+        OutSpec o{};
+        o.buf = v1;
+        o.elem = lin(chain_a);
+        o.dc[0] = 1.0;
+        if (!b.emit(prog, 1, {lin(u) + lin(chain_a, -2.0)}, {o}, 0)) return false;
+        v = {v1};
+        pfirst = 2;
+    }
+    for (int p = pfirst; p <= P; ++p) {
         const int nin = (int)v.size();     // p == 1: {u}; else v_1..v_{p-1}
         // ---- transverse sweeps ----
         std::vector<Lin> gC(nin), hC(nin);   // C v_k = D_x(gC) + hC
@@ -357,7 +377,7 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
                 gs = gs + c * g[k];
                 hs = hs + c * h[k];
             }
-            return b.emit(prog, 0, {gs}, finals(fo, hs, 1.0), 1);
+            return b.emit(prog, 0, {gs}, finals(fo, hs, 1.0), 1, chain_a);
         }
         // non-final stage: write the p new terms (and the accumulator if needed)
         std::vector<int> nv(nt);
@@ -552,6 +572,21 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
     // increment form: (u, du) -> (u + du + rhs, du + rhs), in place
     ok = ok && build_rhs(b, pl->inc_step, B_UCURR,
                          {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0}, {B_UPREV, lin(B_UPREV), 1.0}});
+    // fused solve programs (2D rectangles, P >= 2)
+    if (ok && !pl->masked && g.ndim == 2 && d->P >= 2) {
+        pl->chain_a = b.new_ws();
+        OutSpec o{};
+        o.buf = pl->chain_a;
+        o.dc[0] = 1.0;
+        ok = ok && b.emit(pl->solve_pro, 0, {lin(B_UCURR)}, {o}, 0);
+        ok = ok && build_rhs_box(b, pl->solve_step, B_UCURR,
+                                 {{B_UNEXT, lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0), 1.0}},
+                                 pl->chain_a);
+        ok = ok && build_rhs_box(b, pl->solve_inc_step, B_UCURR,
+                                 {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0},
+                                  {B_UPREV, lin(B_UPREV), 1.0}},
+                                 pl->chain_a);
+    }
     // start: u1 = u0 + rhs(u0)/2
     ok = ok && build_rhs(b, pl->start, B_IN, {{B_OUT, lin(B_IN), 0.5}});
     for (int op = 0; op <= MOL_OP_RHS && ok; ++op) {
@@ -569,7 +604,7 @@ hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, co
 {
     for (const ProgOp &po : prog) {
         const void *fp[MAXF];
-        void *op[MAXO];
+        void *op[MAXO + 1];
         auto res = [&](int b) -> void * {
             switch (b) {
             case B_UPREV: return const_cast<void *>(uprev);
@@ -582,6 +617,7 @@ hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, co
         };
         for (int i = 0; i < po.op.nf; ++i) fp[i] = res(po.op.f[i]);
         for (int i = 0; i < po.op.no; ++i) op[i] = res(po.op.o[i]);
+        if (po.op.chain) op[po.op.no] = res(po.op.ochain);
         hipError_t e;
         if (pl->masked)
             e = launch_seg_op(po.op, pl, fp, op, st);
@@ -595,7 +631,7 @@ hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, co
 double program_bytes(const mol_plan_ *pl, const Program &prog)
 {
     double b = 0;
-    for (const ProgOp &po : prog) b += (double)(po.op.nf + po.op.no);
+    for (const ProgOp &po : prog) b += (double)(po.op.nf + po.op.no + po.op.chain);
     return b * (double)pl->npts * (double)pl->es;
 }
 
@@ -691,8 +727,10 @@ mol_status mol_plan_get_info(const mol_plan *pl, mol_plan_info *info)
     info->unknowns = pl->unknowns;
     info->segments[0] = pl->nsegs[0];
     info->segments[1] = pl->nsegs[1];
-    info->kernels_per_step = (int)pl->step.size();
-    info->bytes_per_step = program_bytes(pl, pl->step);
+    // mol_solve runs the fused program when the plan has one
+    const Program &sp = pl->solve_step.empty() ? pl->step : pl->solve_step;
+    info->kernels_per_step = (int)sp.size();
+    info->bytes_per_step = program_bytes(pl, sp);
     info->workspace_bytes = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes;
     return MOL_OK;
 }
@@ -743,12 +781,20 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
         if (e != hipSuccess) return dev_err(e, "mol_solve");
     }
     // one replay unit: increment form = 1 step in place; three-level = 2 steps
+    const bool fused = !pl->solve_step.empty();
+    const Program &stepP = fused ? pl->solve_step : pl->step;
+    const Program &incP = fused ? pl->solve_inc_step : pl->inc_step;
     auto unit = [&](hipStream_t s) -> hipError_t {
-        if (inc) return run_program(pl, pl->inc_step, A, B, nullptr, nullptr, nullptr, s);
-        hipError_t r = run_program(pl, pl->step, A, B, A, nullptr, nullptr, s);
+        if (inc) return run_program(pl, incP, A, B, nullptr, nullptr, nullptr, s);
+        hipError_t r = run_program(pl, stepP, A, B, A, nullptr, nullptr, s);
         if (r != hipSuccess) return r;
-        return run_program(pl, pl->step, B, A, B, nullptr, nullptr, s);
+        return run_program(pl, stepP, B, A, B, nullptr, nullptr, s);
     };
+    if (fused) {
+        // D_x of the current field for the first stage of the first step
+        e = run_program(pl, pl->solve_pro, A, B, nullptr, nullptr, nullptr, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve");
+    }
     const int64_t per = inc ? 1 : 2;
     const int64_t reps = nsteps / per;
     if (reps > 0) {
@@ -783,7 +829,7 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
     }
     if (!inc && (nsteps % 2)) {
         // odd count: one more step into A, then swap the contents of A and B
-        e = run_program(pl, pl->step, A, B, A, nullptr, nullptr, st);
+        e = run_program(pl, stepP, A, B, A, nullptr, nullptr, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
         if (pl->nws < 1) return fail(MOL_E_DEVICE, "no workspace for the swap");
         void *W = pl->ws[pl->nws - 1];
@@ -804,16 +850,20 @@ mol_status mol_profile_step(mol_plan *pl, const void *u_prev, const void *u_curr
                             int *nsweep, int *count)
 {
     if (!pl || !u_prev || !u_curr || !u_next || reps < 1) return fail(MOL_E_INVALID, "bad arguments");
-    const int nk = (int)pl->step.size();
+    // the program mol_solve replays (fused when the plan has one)
+    const bool fused = !pl->solve_step.empty();
+    const Program &sp = fused ? pl->solve_step : pl->step;
+    const int nk = (int)sp.size();
     if (count) *count = nk;
     hipStream_t st = (hipStream_t)stream;
     std::vector<hipEvent_t> ev(2 * (size_t)nk * reps);
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) return fail(MOL_E_DEVICE, "hipEventCreate failed");
     hipError_t e = hipSuccess;
+    if (fused) e = run_program(pl, pl->solve_pro, u_prev, u_curr, u_next, nullptr, nullptr, st);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
         for (int i = 0; i < nk && e == hipSuccess; ++i) {
-            Program one(1, pl->step[i]);
+            Program one(1, sp[i]);
             e = hipEventRecord(ev[2 * ((size_t)r * nk + i)], st);
             if (e == hipSuccess) e = run_program(pl, one, u_prev, u_curr, u_next, nullptr, nullptr, st);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * ((size_t)r * nk + i) + 1], st);
@@ -827,9 +877,9 @@ mol_status mol_profile_step(mol_plan *pl, const void *u_prev, const void *u_curr
             e = hipEventElapsedTime(&t, ev[2 * ((size_t)r * nk + i)], ev[2 * ((size_t)r * nk + i) + 1]);
             tot += t;
         }
-        const SweepOp &op = pl->step[i].op;
+        const SweepOp &op = sp[i].op;
         if (ms) ms[i] = tot / reps;
-        if (bytes) bytes[i] = (double)(op.nf + op.no) * (double)pl->npts * (double)pl->es;
+        if (bytes) bytes[i] = (double)(op.nf + op.no + op.chain) * (double)pl->npts * (double)pl->es;
         if (dir) dir[i] = op.dir;
         if (nsweep) nsweep[i] = op.ns;
     }

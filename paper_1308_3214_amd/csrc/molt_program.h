@@ -32,6 +32,10 @@ struct mol_plan_ {
     int nws = 0;                       // workspace fields
     std::vector<void *> ws;            // device workspace fields
     molt::Program step, start, inc_step;
+    // fused solve (2D rectangles, P >= 2): the last x sweep of a step also
+    // writes D_x u^{n+1} into ws chain_a for the next step's first stage
+    molt::Program solve_pro, solve_step, solve_inc_step;
+    int chain_a = -1;
     molt::Program apply[9];
     int dev = 0;
     // graph cache for mol_solve
@@ -82,7 +86,7 @@ struct Builder {
 
     // one directional launch: combos = swept combinations, outs = outputs
     bool emit(Program &prog, int dir, const std::vector<Lin> &combos,
-              const std::vector<OutSpec> &outs, int proj);
+              const std::vector<OutSpec> &outs, int proj, int chain_buf = -1);
 };
 
 // How the right-hand side sum_{p,m} c_{p,m} C^m D^{p-m} u is consumed: each

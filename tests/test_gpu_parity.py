@@ -143,11 +143,10 @@ def test_step_and_start(torch_cuda, molt, oracle_mod, P, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nsteps", [1, 6, 25])
-def test_solve_graph(torch_cuda, molt, oracle_mod, dtype, nsteps):
+@pytest.mark.parametrize("nsteps,P", [(1, 2), (6, 2), (25, 2), (7, 3), (5, 1)])
+def test_solve_graph(torch_cuda, molt, oracle_mod, dtype, nsteps, P):
     torch = torch_cuda
     shape, h = (64, 96), (1.0 / 95, 1.0 / 63)
-    P = 2
     for flags in (0, molt.NO_GRAPH, molt.INCREMENT_FORM):
         plan = molt.Plan(shape, h, 0, P=P, cfl=2.0, dtype=dtype, flags=flags)
         pb = oracle_mod.Problem(shape, h, 0, plan.info["alpha"], precision="ld")
