@@ -166,6 +166,23 @@ mol_status mol_profile_step(mol_plan *plan, const void *u_prev, const void *u_cu
                             int reps, void *stream, int max, double *ms, double *bytes,
                             int *dir, int *nsweep, int *count);
 
+/* Launch configurations, for the autotuner.  Kernel indices refer to the step
+ * program mol_solve replays (as in mol_profile_step).  mol_plan_kernel_configs
+ * writes up to max valid configuration ids of kernel `kernel` into ids, their
+ * number into *count and the id in use into *current (pointers may be NULL).
+ * mol_plan_set_kernel_config selects one (MOL_E_INVALID if not valid for that
+ * kernel); it also applies to every other kernel of the plan with the same
+ * direction, field count and sweep shape.  At creation a plan takes its
+ * configurations from the tuning cache file named by the environment variable
+ * MOLT_TUNE_CACHE, else tune_cache.txt beside the library, when it holds an
+ * entry for the problem; otherwise built-in defaults. */
+mol_status mol_plan_kernel_configs(const mol_plan *plan, int kernel, int *ids, int max, int *count,
+                                   int *current);
+mol_status mol_plan_set_kernel_config(mol_plan *plan, int kernel, int config);
+/* The cache key of a plan's problem and of one of its kernels (for the tuner):
+ * writes a NUL-terminated string of at most len bytes. */
+mol_status mol_plan_tune_key(const mol_plan *plan, int kernel, char *buf, int len);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *mol_last_error(void);
 

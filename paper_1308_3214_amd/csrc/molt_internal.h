@@ -58,6 +58,7 @@ hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, boo
 // Per-direction launch configuration chosen by the plan: cfg[0] = variant id.
 int default_config(const Geom &g, int dir, bool fp64, int ns, int no, int *cfg);
 bool config_valid(const Geom &g, int dir, bool fp64, int ns, int no, const int *cfg);
+int config_count(int dir);
 
 // Elementwise a*x + b*y -> z on n values (state conversion for the increment form).
 hipError_t launch_axpby(bool fp64, int64_t n, double a, const void *x, double b, const void *y,

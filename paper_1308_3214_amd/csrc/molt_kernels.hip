@@ -1,816 +1,17 @@
-// Directional sweep kernels for gfx950: the O(N) recursive convolution
-// L_gamma^{-1} (Sec. 2: characteristic split I^L + I^R, each an exponential
-// recurrence with decay e^{-alpha h}, local integrals over one cell against the
-// quadratic through three nodes, then the boundary correction
-// A e^{-alpha(x-a)} + B e^{-alpha(b-x)}) applied along x, y or z lines, with
-// D_gamma = 1 - L_gamma^{-1} (Sec. 4, eq. LD_gam) emitted directly.
-//
-// Formulation used on the device.  With E = I - v/2 the recurrences are forced
-// only by differences of the data,
-//   E^L_p = d E^L_{p-1} + w2 (v_{p+1} - 2 v_p + v_{p-1}) - g (v_p - v_{p-1}),
-//   E^R_p = d E^R_{p+1} + w2 (v_{p+1} - 2 v_p + v_{p-1}) + g (v_{p+1} - v_p),
-//   D v_p = -(E^L_p + E^R_p + A d^p + B d^{M-p}),
-// (d = e^{-nu}, g = (1-d)/(2 nu), nu = alpha h), which is the same discrete
-// operator as I^L + I^R (exact in real arithmetic) but never forms v - L^{-1} v,
-// so D keeps full relative precision in FP32.  At a Dirichlet end node the
-// curvature term is dropped (the data's curvature there is 0 for homogeneous
-// boundary values, Sec. 3.2).
-//
-// Each launch computes up to MAXS swept combinations s_k = sum_f mS[k][f] F_f
-// of up to MAXF loaded fields and writes up to MAXO outputs
-// out_o = sum_f mOF[o][f] F_f + sum_k mOD[o][k] D(s_k): the ADI compositions
-// (eqs. C_def_ADI, D_def_ADI, ...) and the time update are fused this way.
-//
-// x lines (contiguous): one workgroup per line, the line staged through LDS
-// (coalesced vector loads, padded to avoid bank conflicts), every lane runs
-// the recurrences over S consecutive nodes, lane carries are combined by a
-// wave-level scan of the linear recurrence (multiplier d^S) and waves through
-// LDS: exact.
-//
-// y / z lines (strided): lanes own consecutive columns (coalesced rows), waves
-// of a workgroup stack along the line, each lane runs S nodes, wave carries
-// are scanned through LDS.  Lines longer than one tile of W*S nodes are split
-// into tiles; the carry entering a tile is the truncated sum over a halo of
-// K nodes with d^K below the dtype's rounding (the exponential decay of the
-// Green's function), computed cooperatively by all waves of the tile.
+// Host side of the directional sweeps: argument packing, launch-configuration
+// choice and validation, dispatch to the instantiation units.
 #include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdint.h>
 
 #include <cmath>
+#include <cstdint>
 
 #include "molt_internal.h"
+#include "molt_sweep.h"
 
 namespace molt {
 
-template <typename T>
-struct KArgs {
-    const T *f[MAXF];
-    T *o[MAXO];
-    T mS[MAXS][MAXF];
-    T mOF[MAXO][MAXF];
-    T mOD[MAXO][MAXS];
-    int nf;
-    int proj;
-    int chain;        // x: also write D_x(out_0) to ochain (next sweep of out_0)
-    T *ochain;
-    int64_t n;        // nodes per line
-    int64_t nlines;   // x: lines; strided: columns (x extent)
-    int64_t lineoff;  // x: element offset between lines
-    int64_t ls;       // strided: stride between nodes of a line
-    int64_t os;       // strided: stride of the outer index
-    int64_t nouter;   // strided: outer extent
-    int64_t nblocks;  // strided: total workgroups (XCD remap)
-    int ntiles;       // strided: tiles per line
-    int halo;         // strided: halo nodes per side
-    int aligned;      // x: vector loads allowed
-    int periodic;     // along the sweep
-    T d, g, w2;
-    T gw;             // g + w2
-    T dpow[33];       // d^0 .. d^32
-    T dS;             // d^S
-    T dBlk;           // x: d^{64 S} (one wave of lanes)
-    double nu;
-    double K00, K01, K10, K11;
-    // projection: line index = (i1 in [0,pn1), i2 in [0,pn2)); Dirichlet flags
-    int64_t pn1, pn2;
-    int pd1, pd2;
-};
-
-// ---------------------------------------------------------------------------
-// helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t N)
-{
-    // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-    // contiguous range of logical tiles so that neighbouring tiles of a line
-    // (which read each other's halo) share one L2.
-    const int64_t X = 8;
-    int64_t x = i % X, local = i / X;
-    int64_t per = N / X, rem = N % X;
-    return x * per + (x < rem ? x : rem) + local;
-}
-
-template <typename T>
-__device__ __forceinline__ T shfl_up(T v, int off) { return __shfl_up(v, off, 64); }
-template <typename T>
-__device__ __forceinline__ T shfl_down(T v, int off) { return __shfl_down(v, off, 64); }
-
-// Forcing of the two recurrences at node p from its neighbours vm, v0, vp
-// (end and outside nodes already read as 0).  Dirichlet end nodes drop the
-// curvature term; E^L starts at node 0 and E^R at node M.
-template <typename T>
-__device__ __forceinline__ T force_L(T vm, T v0, T vp, int p, int M, bool dir_end, T g, T w2)
-{
-    if (dir_end) {
-        if (p <= 0 || p > M) return T(0);
-        if (p == M) return -g * (v0 - vm);
-    } else if (p > M) {
-        return T(0);
-    }
-    return w2 * ((vp - v0) - (v0 - vm)) - g * (v0 - vm);
-}
-template <typename T>
-__device__ __forceinline__ T force_R(T vm, T v0, T vp, int p, int M, bool dir_end, T g, T w2)
-{
-    if (dir_end) {
-        if (p < 0 || p >= M) return T(0);
-        if (p == 0) return g * (vp - v0);
-    } else if (p > M) {
-        return T(0);
-    }
-    return w2 * ((vp - v0) - (v0 - vm)) + g * (vp - v0);
-}
-
-// Local recurrences over S nodes p0..p0+S-1 from the values v[0..S+1] of
-// nodes p0-1..p0+S.  sum[j] = local E^L + local E^R (zero carry-in at both
-// segment ends); aL = local E^L at the last node, aR = local E^R at the first
-// node, eLM = local E^L at node M if this segment holds it.
-template <typename T, int S>
-__device__ __forceinline__ void seg_recur(const T (&v)[S + 2], int p0, int M, bool dir_end, T d,
-                                          T g, T w2, T (&sum)[S], T &aL, T &aR, T &eLM)
-{
-    T e = T(0);
-    eLM = T(0);
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const int p = p0 + j;
-        e = d * e + force_L(v[j], v[j + 1], v[j + 2], p, M, dir_end, g, w2);
-        sum[j] = e;
-        if (p == M) eLM = e;
-    }
-    aL = e;
-    e = T(0);
-#pragma unroll
-    for (int j = S - 1; j >= 0; --j) {
-        e = d * e + force_R(v[j], v[j + 1], v[j + 2], p0 + j, M, dir_end, g, w2);
-        sum[j] += e;
-    }
-    aR = e;
-}
-
-// In place: sum[j] <- D_j = -(sum[j] + d^{j+1} cL + d^{S-j} cR + A d^p + B d^{M-p}),
-// p = p0 + j; zero beyond the line and at Dirichlet end nodes.  A, B in FP64.
-template <typename T, int S>
-__device__ __forceinline__ void seg_close(T (&sum)[S], T cL, T cR, double A, double B, int p0,
-                                          int M, double nu, T d, bool dir_end)
-{
-    const double dd = exp(-nu);
-    double ta = (A != 0.0) ? A * exp(-nu * (double)p0) : 0.0;
-    T ldec = d * cL;
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        sum[j] += (T)ta + ldec;
-        ta *= dd;
-        ldec *= d;
-    }
-    const int rem = M - p0;
-    const int jmax = (rem >= S - 1) ? (S - 1) : rem;
-    double tb = (B != 0.0 && jmax >= 0) ? B * exp(-nu * (double)(rem - jmax)) : 0.0;
-    T rdec = cR;
-#pragma unroll
-    for (int j = S - 1; j >= 0; --j) {
-        rdec *= d;
-        sum[j] += rdec;
-        if (j <= jmax) {
-            sum[j] += (T)tb;
-            tb *= dd;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const int p = p0 + j;
-        sum[j] = (p > M || (dir_end && (p == 0 || p == M))) ? T(0) : -sum[j];
-    }
-}
-
-// Branch-free recurrences for a segment whose nodes are all interior nodes of
-// a Dirichlet line or of a periodic line (values outside the line read as 0).
-// With dl_j = v_j - v_{j-1}:  F^L_j = w2 dl_{j+1} - (g + w2) dl_j,
-// F^R_j = (g + w2) dl_{j+1} - w2 dl_j.
-template <typename T, int S>
-__device__ __forceinline__ void seg_recur_fast(const T (&v)[S + 2], T d, T gw, T w2, T (&sum)[S],
-                                               T &aL, T &aR)
-{
-    T dl[S + 1];
-#pragma unroll
-    for (int j = 0; j <= S; ++j) dl[j] = v[j + 1] - v[j];
-    T e = T(0);
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        e = d * e + (w2 * dl[j + 1] - gw * dl[j]);
-        sum[j] = e;
-    }
-    aL = e;
-    e = T(0);
-#pragma unroll
-    for (int j = S - 1; j >= 0; --j) {
-        e = d * e + (gw * dl[j + 1] - w2 * dl[j]);
-        sum[j] += e;
-    }
-    aR = e;
-}
-
-// Dirichlet end nodes inside a segment handled by seg_recur_fast: at node 0 the
-// forcing must be F^L = 0, F^R = g v_1 and at node M F^L = g v_{M-1}, F^R = 0
-// (no curvature at a boundary node); the branch-free forcing is off by
-// -w2 v_1 (node 0) and -w2 v_{M-1} (node M) in both directions.  The linear
-// recurrences carry these corrections with powers of d.  v1 = value at node 1,
-// vM1 = value at node M-1 (read by the caller).  Returns E^L_M (local) in eLM.
-template <typename T, int S>
-__device__ __forceinline__ void seg_fix_dirichlet(int p0, int M, T v1, T vM1, T d, T w2,
-                                                  T (&sum)[S], T &aL, T &aR, T &eLM)
-{
-    if (p0 == 0) {
-        const T c = -w2 * v1;
-        T pw = c, last = c;
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            sum[j] += pw;                 // forward: c d^j
-            last = pw;
-            pw *= d;
-        }
-        aL += last;                       // c d^{S-1}
-        sum[0] += c;                      // backward: node 0 only
-        aR += c;
-    }
-    const int jm = M - p0;
-    if (jm >= 0 && jm < S) {
-        const T c = -w2 * vM1;
-        T pf = c, pb = c, lf = T(0), lb = T(0);
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            if (j >= jm) { sum[j] += pf; lf = pf; pf *= d; }
-        }
-#pragma unroll
-        for (int j = S - 1; j >= 0; --j) {
-            if (j <= jm) { sum[j] += pb; lb = pb; pb *= d; }
-        }
-        aL += lf;                         // c d^{S-1-jm}
-        aR += lb;                         // c d^{jm}
-        T em = T(0);
-#pragma unroll
-        for (int j = 0; j < S; ++j)
-            if (j == jm) em = sum[j];     // E^R_M = 0 locally: sum = E^L_M
-        eLM = em;
-    }
-}
-
-// Closure for a segment: D_j = -(sum_j + d^{j+1} cL + d^{S-j} cR + A d^p + B d^{M-p}).
-// Interior segments use two decaying terms with d^j from the kernel
-// arguments; a segment holding node M (or nodes beyond it) adds the B term
-// node by node and zeroes what lies beyond M; Dirichlet end nodes get D = 0.
-template <typename T, int S>
-__device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A, double B, int p0,
-                                               int M, double nu, T d, const T *dpow, bool dir_end)
-{
-    const int jm = M - p0;
-    const bool holdsM = jm < S;
-    const T lt = d * cL + (T)((A != 0.0) ? A * exp(-nu * (double)p0) : 0.0);
-    const T rt = d * cR + (T)((!holdsM && B != 0.0) ? B * exp(-nu * (double)(jm - (S - 1))) : 0.0);
-#pragma unroll
-    for (int j = 0; j < S; ++j) sum[j] = -(sum[j] + lt * dpow[j] + rt * dpow[S - 1 - j]);
-    if (holdsM) {
-        double pw = B;
-        const double dd = exp(-nu);
-#pragma unroll
-        for (int j = S - 1; j >= 0; --j) {
-            if (j > jm) {
-                sum[j] = T(0);
-            } else {
-                sum[j] -= (T)pw;
-                pw *= dd;
-            }
-        }
-        if (dir_end) {
-#pragma unroll
-            for (int j = 0; j < S; ++j)
-                if (j == jm) sum[j] = T(0);
-        }
-    }
-    if (dir_end && p0 == 0) sum[0] = T(0);
-}
-
-// ---------------------------------------------------------------------------
-// x sweep: contiguous lines, one line per workgroup of NT = 64*WPL threads
-// ---------------------------------------------------------------------------
-// D_x of NSW combinations staged in LDS (sm + k*NPAD, padded slots); the D
-// values replace the inputs in place.  Ends with a __syncthreads.
-template <typename T, int S, int WPL, int NSW>
-__device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)[MAXS][WPL],
-                                             T (*ends)[MAXS], int t, int n)
-{
-    constexpr int NT = 64 * WPL;
-    constexpr int NPAD = NT * (S + 1);
-    const int lane = t & 63, wave = t >> 6;
-    const int M = n - 1;
-    const int p0 = t * S;
-    const int jm = M - p0;
-    const bool dir_end = !a.periodic;
-    const bool slow = a.periodic && (p0 + S - 1 > M);   // periodic lane crossing the end
-    T sum[NSW][S];
-    T aL[NSW], aR[NSW], eLM[NSW];
-#pragma unroll
-    for (int k = 0; k < NSW; ++k) {
-        const T *sk = sm + k * NPAD;
-        T v[S + 2];
-#pragma unroll
-        for (int j = 0; j < S; ++j) v[j + 1] = sk[t * (S + 1) + j];
-        if (p0 == 0) v[0] = a.periodic ? sk[(M / S) * (S + 1) + (M % S)] : T(0);
-        else v[0] = sk[(t - 1) * (S + 1) + (S - 1)];
-        v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
-        if (a.periodic && jm >= 0 && jm < S) v[jm + 2] = sk[0];   // wrap at node M
-        if (slow) {
-            seg_recur<T, S>(v, p0, M, false, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
-        } else {
-            seg_recur_fast<T, S>(v, a.d, a.gw, a.w2, sum[k], aL[k], aR[k]);
-            eLM[k] = aL[k];                            // periodic: node M ends its lane
-            if (dir_end) {
-                const T v1 = (p0 == 0 && n > 1) ? sk[1] : T(0);
-                const int q = M - 1;
-                const T vM1 = (jm >= 0 && jm < S && q >= 0) ? sk[(q / S) * (S + 1) + (q % S)] : T(0);
-                seg_fix_dirichlet<T, S>(p0, M, v1, vM1, a.d, a.w2, sum[k], aL[k], aR[k], eLM[k]);
-            }
-        }
-    }
-    // lane scan (multiplier d^S per lane), then waves through LDS
-    T cL[NSW], cR[NSW];
-#pragma unroll
-    for (int k = 0; k < NSW; ++k) {
-        T xl = aL[k], xr = aR[k], m = a.dS;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const T yl = shfl_up(xl, off);
-            const T yr = shfl_down(xr, off);
-            if (lane >= off) xl += m * yl;
-            if (lane + off < 64) xr += m * yr;
-            m *= m;
-        }
-        const T exl = shfl_up(xl, 1);
-        const T exr = shfl_down(xr, 1);
-        cL[k] = (lane == 0) ? T(0) : exl;
-        cR[k] = (lane == 63) ? T(0) : exr;
-        if (WPL > 1) {
-            if (lane == 63) wtot[0][k][wave] = xl;
-            if (lane == 0) wtot[1][k][wave] = xr;
-        }
-    }
-    if (WPL > 1) {
-        __syncthreads();
-        const T pl = (T)exp(-a.nu * (double)S * (double)lane);
-        const T pr = (T)exp(-a.nu * (double)S * (double)(63 - lane));
-#pragma unroll
-        for (int k = 0; k < NSW; ++k) {
-            T cw = T(0), cwr = T(0);
-            for (int w = 0; w < wave; ++w) cw = a.dBlk * cw + wtot[0][k][w];
-            for (int w = WPL - 1; w > wave; --w) cwr = a.dBlk * cwr + wtot[1][k][w];
-            cL[k] += pl * cw;
-            cR[k] += pr * cwr;
-        }
-    }
-    // line ends: E^R_0 (lane holding node 0) and E^L_M (lane holding node M)
-#pragma unroll
-    for (int k = 0; k < NSW; ++k) {
-        if (p0 == 0) ends[0][k] = aR[k] + a.dS * cR[k];
-        if (jm >= 0 && jm < S) ends[1][k] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NSW; ++k) {
-        const double er0 = (double)ends[0][k], elm = (double)ends[1][k];
-        const double A = a.K00 * er0 + a.K01 * elm;
-        const double B = a.K10 * er0 + a.K11 * elm;
-        if (slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, false);
-        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, a.dpow, dir_end);
-        T *sk = sm + k * NPAD;
-#pragma unroll
-        for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
-    }
-    __syncthreads();
-}
-
-template <typename T, int S, int WPL, int NS, int NO, int VW>
-__global__ void __launch_bounds__(64 * WPL)
-k_sweep_x(const KArgs<T> a)
-{
-    constexpr int NT = 64 * WPL;
-    constexpr int NPAD = NT * (S + 1);
-    constexpr int NV = S / VW;
-    typedef T vec_t __attribute__((ext_vector_type(VW)));
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
-    __shared__ T wtot[2][MAXS][WPL];
-    __shared__ T ends[2][MAXS];
-
-    const int t = threadIdx.x;
-    const int64_t line = blockIdx.x;
-    const int n = (int)a.n;
-    const int M = n - 1;
-    const int64_t base = line * a.lineoff;            // uniform per workgroup
-    const bool dir_end = !a.periodic;
-
-    bool bline = false;
-    if (a.proj) {
-        const int64_t i1 = line % a.pn1, i2 = line / a.pn1;
-        bline = (a.pd1 && (i1 == 0 || i1 == a.pn1 - 1)) || (a.pd2 && (i2 == 0 || i2 == a.pn2 - 1));
-    }
-
-    // ---- phase 1: coalesced loads (all of one field at once), prologue ----
-    T sv[NS][S], ev[NO][S];
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) sv[k][j] = T(0);
-#pragma unroll
-        for (int o = 0; o < NO; ++o) ev[o][j] = T(0);
-    }
-    for (int f = 0; f < a.nf; ++f) {
-        const T *src = a.f[f] + base;
-        T x[S];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int e0 = (i * NT + t) * VW;
-            if (a.aligned && e0 + VW <= n) {
-                const vec_t vv = *reinterpret_cast<const vec_t *>(src + e0);
-#pragma unroll
-                for (int c = 0; c < VW; ++c) x[i * VW + c] = vv[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < VW; ++c) x[i * VW + c] = (e0 + c < n) ? src[e0 + c] : T(0);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) sv[k][j] += a.mS[k][f] * x[j];
-#pragma unroll
-            for (int o = 0; o < NO; ++o) ev[o][j] += a.mOF[o][f] * x[j];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-#pragma unroll
-        for (int c = 0; c < VW; ++c) {
-            const int e = (i * NT + t) * VW + c;
-            const int slot = (e / S) * (S + 1) + (e % S);
-            const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
-#pragma unroll
-            for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][i * VW + c];
-        }
-    }
-    __syncthreads();
-
-    // ---- phases 2-3: recurrences, scans, closure (D in LDS) ----
-    x_line_sweep<T, S, WPL, NS>(a, sm, wtot, ends, t, n);
-
-    // ---- phase 4: epilogue in the coalesced layout ----
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const int e0 = (i * NT + t) * VW;
-        T out[NO][VW];
-#pragma unroll
-        for (int c = 0; c < VW; ++c) {
-            const int e = e0 + c;
-            const int slot = (e / S) * (S + 1) + (e % S);
-            T Dk[NS];
-#pragma unroll
-            for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
-            const bool z = a.proj && (bline || (dir_end && (e == 0 || e == M)));
-#pragma unroll
-            for (int o = 0; o < NO; ++o) {
-                T r = ev[o][i * VW + c];
-#pragma unroll
-                for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
-                out[o][c] = z ? T(0) : r;
-            }
-        }
-#pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            T *dst = a.o[o] + base;
-            if (a.aligned && e0 + VW <= n) {
-                vec_t vv;
-#pragma unroll
-                for (int c = 0; c < VW; ++c) vv[c] = out[o][c];
-                *reinterpret_cast<vec_t *>(dst + e0) = vv;
-            } else {
-#pragma unroll
-                for (int c = 0; c < VW; ++c)
-                    if (e0 + c < n) dst[e0 + c] = out[o][c];
-            }
-        }
-        if (a.chain) {
-            // the next x sweep of output 0 starts from these values (each
-            // slot is read and rewritten by the same thread only)
-#pragma unroll
-            for (int c = 0; c < VW; ++c) {
-                const int e = e0 + c;
-                const int slot = (e / S) * (S + 1) + (e % S);
-                const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
-                sm[slot] = zero ? T(0) : out[0][c];
-            }
-        }
-    }
-    if (a.chain) {
-        __syncthreads();
-        x_line_sweep<T, S, WPL, 1>(a, sm, wtot, ends, t, n);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int e0 = (i * NT + t) * VW;
-            T out[VW];
-#pragma unroll
-            for (int c = 0; c < VW; ++c) {
-                const int e = e0 + c;
-                out[c] = sm[(e / S) * (S + 1) + (e % S)];
-            }
-            T *dst = a.ochain + base;
-            if (a.aligned && e0 + VW <= n) {
-                vec_t vv;
-#pragma unroll
-                for (int c = 0; c < VW; ++c) vv[c] = out[c];
-                *reinterpret_cast<vec_t *>(dst + e0) = vv;
-            } else {
-#pragma unroll
-                for (int c = 0; c < VW; ++c)
-                    if (e0 + c < n) dst[e0 + c] = out[c];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// strided sweep (y or z): lanes = 64 consecutive columns, W waves x S nodes
-// ---------------------------------------------------------------------------
-template <typename T, int S, int W, int NS, int NO>
-__global__ void __launch_bounds__(64 * W)
-k_sweep_s(const KArgs<T> a)
-{
-    constexpr int WS = W * S;
-    __shared__ T red[2][NS][W][64];      // cooperative sums, then wave aggregates
-    __shared__ T endv[2][NS][64];        // E^R_0 and E^L_M per column (one tile)
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t L = xcd_remap(blockIdx.x, a.nblocks);
-    const int tile = (int)(L % a.ntiles);
-    const int64_t rest = L / a.ntiles;
-    const int64_t ncg = (a.nlines + 63) / 64;
-    const int64_t cg = rest % ncg;
-    const int64_t outer = rest / ncg;
-    const int col = (int)(cg * 64) + lane;
-    const bool active = col < a.nlines;
-    const int n = (int)a.n, M = n - 1;
-    const int ls = (int)a.ls;
-    const int64_t blk = cg * 64 + outer * a.os;          // uniform per workgroup
-    const int loff = active ? lane : 0;                  // per-lane column offset
-    const bool dir_end = !a.periodic;
-    const bool per = a.periodic != 0;
-    const T d = a.d, g = a.g, w2 = a.w2;
-    const int oa = tile * WS;
-    const int ob = (oa + WS < n) ? oa + WS : n;
-    const bool split = a.ntiles > 1;
-    const int K = a.halo;
-    const int p0 = oa + wave * S;
-
-    // ---- main nodes p0-1 .. p0+S: all rows of one field issued together ----
-    T ev[NO][S];
-    T v[NS][S + 2];
-#pragma unroll
-    for (int j = 0; j < S + 2; ++j) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) v[k][j] = T(0);
-    }
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-#pragma unroll
-        for (int o = 0; o < NO; ++o) ev[o][j] = T(0);
-    }
-    for (int f = 0; f < a.nf; ++f) {
-        const T *src = a.f[f] + blk;
-        T x[S + 2];
-#pragma unroll
-        for (int j = 0; j < S + 2; ++j) {
-            int p = p0 - 1 + j;
-            bool inside;
-            if (per) {
-                p %= n;
-                if (p < 0) p += n;
-                inside = true;
-            } else {
-                inside = (p >= 0 && p <= M);
-            }
-            x[j] = (inside && active) ? src[loff + p * ls] : T(0);
-        }
-#pragma unroll
-        for (int j = 0; j < S + 2; ++j) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) v[k][j] += a.mS[k][f] * x[j];
-            if (j >= 1 && j <= S) {
-#pragma unroll
-                for (int o = 0; o < NO; ++o) ev[o][j - 1] += a.mOF[o][f] * x[j];
-            }
-        }
-    }
-    if (dir_end) {
-#pragma unroll
-        for (int j = 0; j < S + 2; ++j) {
-            const int p = p0 - 1 + j;
-            if (p == 0 || p == M) {
-#pragma unroll
-                for (int k = 0; k < NS; ++k) v[k][j] = T(0);
-            }
-        }
-    }
-
-    // swept combination k at node p of this column (0 outside / at Dirichlet ends)
-    auto sval = [&](int k, int p) -> T {
-        if (per) {
-            p %= n;
-            if (p < 0) p += n;
-        } else if (p <= 0 || p >= M) {
-            return T(0);
-        }
-        if (!active) return T(0);
-        const int off = loff + p * ls;
-        T s = T(0);
-        for (int f = 0; f < a.nf; ++f) s += a.mS[k][f] * a.f[f][blk + off];
-        return s;
-    };
-    // this wave's share of sum_{kk<K} d^kk F(r0 + sg*kk): sg = -1 sums the
-    // forcing of E^L moving up from r0, sg = +1 that of E^R moving down
-    const int q = (K + W - 1) / W;
-    const int k0 = wave * q;
-    const int k1 = (k0 + q < K) ? k0 + q : K;
-    auto part = [&](int k, int r0, int sg) -> T {
-        T acc = T(0);
-        if (k0 >= k1) return acc;
-        T pw = (T)exp(-a.nu * (double)k0);
-        int r = r0 + sg * k0;
-        T vb = sval(k, r - sg), v0 = sval(k, r);
-        for (int kk = k0; kk < k1; ++kk, r += sg) {
-            const T vn = sval(k, r + sg);
-            const int rr = per ? ((r % n) + n) % n : r;
-            const T fv = (sg < 0) ? force_L(vn, v0, vb, rr, M, dir_end, g, w2)
-                                  : force_R(vb, v0, vn, rr, M, dir_end, g, w2);
-            acc += pw * fv;
-            pw *= d;
-            vb = v0;
-            v0 = vn;
-        }
-        return acc;
-    };
-    // cooperative pair of sums over all waves (workgroup-uniform call)
-    auto coop = [&](int r0a, int sga, bool usea, int r0b, int sgb, bool useb, T (&oa_)[NS],
-                    T (&ob_)[NS]) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            red[0][k][wave][lane] = usea ? part(k, r0a, sga) : T(0);
-            red[1][k][wave][lane] = useb ? part(k, r0b, sgb) : T(0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            T x = T(0), y = T(0);
-            for (int w = 0; w < W; ++w) {
-                x += red[0][k][w][lane];
-                y += red[1][k][w][lane];
-            }
-            oa_[k] = x;
-            ob_[k] = y;
-        }
-        __syncthreads();
-    };
-
-    // ---- local recurrences of this wave's S nodes ----
-    const int jm = M - p0;
-    const bool slow = per && (p0 + S - 1 > M);          // periodic wave crossing the end
-    T sum[NS][S];
-    T aL[NS], aR[NS], eLM[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        if (slow) {
-            seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
-        } else {
-            seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
-            eLM[k] = aL[k];
-            if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
-                T vM1 = T(0);
-#pragma unroll
-                for (int j = 0; j < S + 2; ++j)
-                    if (j == jm) vM1 = v[k][j];            // node M-1
-                seg_fix_dirichlet<T, S>(p0, M, v[k][2], vM1, d, w2, sum[k], aL[k], aR[k], eLM[k]);
-            }
-        }
-    }
-
-    // ---- carries entering the tile, and line-end values for split lines ----
-    T cTop[NS], cBot[NS], er0s[NS], elms[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        cTop[k] = T(0);
-        cBot[k] = T(0);
-        er0s[k] = T(0);
-        elms[k] = T(0);
-    }
-    // a tile far (> K nodes) from a line end does not see that end's correction
-    const bool needA = split && !per && oa < K;
-    const bool needB = split && !per && n - ob < K;
-    if (split) {
-        coop(oa - 1, -1, per || oa > 0, ob, +1, per || ob < n, cTop, cBot);
-        if (needA || needB) coop(0, +1, needA, M, -1, needB, er0s, elms);
-    }
-
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        red[0][k][wave][lane] = aL[k];
-        red[1][k][wave][lane] = aR[k];
-    }
-    __syncthreads();
-    // In a short last tile of a split periodic line the bottom carry enters
-    // at node n, inside a wave: it is applied through the closure instead.
-    const bool botAsB = per && split && ob == n;
-    T cL[NS], cR[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        T c = cTop[k];
-        for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
-        cL[k] = c;
-        T cr = botAsB ? T(0) : cBot[k];
-        for (int w = W - 1; w > wave; --w) cr = a.dS * cr + red[1][k][w][lane];
-        cR[k] = cr;
-    }
-    if (!split) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            if (p0 == 0) endv[0][k][lane] = aR[k] + a.dS * cR[k];
-            if (jm >= 0 && jm < S) endv[1][k][lane] = eLM[k] + (T)exp(-a.nu * (double)(jm + 1)) * cL[k];
-        }
-        __syncthreads();
-    }
-
-    // ---- closure and epilogue ----
-    bool bline = false;
-    if (a.proj)
-        bline = (a.pd1 && (col == 0 || col == a.pn1 - 1)) ||
-                (a.pd2 && (outer == 0 || outer == a.pn2 - 1));
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        double A = 0.0, B = 0.0;
-        if (!split) {
-            const double er0 = (double)endv[0][k][lane], elm = (double)endv[1][k][lane];
-            A = a.K00 * er0 + a.K01 * elm;
-            B = a.K10 * er0 + a.K11 * elm;
-        } else if (!per) {
-            const double er0 = (double)er0s[k], elm = (double)elms[k];
-            A = a.K00 * er0 + a.K01 * elm;
-            B = a.K10 * er0 + a.K11 * elm;
-        } else if (botAsB) {
-            B = (double)d * (double)cBot[k];     // cBot d^{n-p} = (d cBot) d^{M-p}
-        }
-        if (slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, false);
-        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, a.dpow, dir_end);
-    }
-    if (!active) return;
-    T *dst[NO];
-#pragma unroll
-    for (int o = 0; o < NO; ++o) dst[o] = a.o[o] + blk;
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const int p = p0 + j;
-        if (p > M) break;
-        const bool z = a.proj && (bline || (dir_end && (p == 0 || p == M)));
-        const int off = loff + p * ls;
-#pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            T r = ev[o][j];
-#pragma unroll
-            for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * sum[k][j];
-            dst[o][off] = z ? T(0) : r;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// elementwise z = a x + b y
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_axpby(int64_t n, T a, const T *x, T b, const T *y, T *z)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = i; k < n; k += stride) z[k] = a * x[k] + b * y[k];
-}
-
-// ---------------------------------------------------------------------------
-// host side: launch dispatch
-// ---------------------------------------------------------------------------
 namespace {
 
-struct XCfg { int S, WPL; };
-struct SCfg { int S, W; };
-// configuration tables (cfg[0] indexes these)
-const XCfg kXCfg[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}, {16, 8}, {8, 2}, {8, 4}};
-const SCfg kSCfg[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {4, 16}, {16, 4}};
-constexpr int NXCFG = sizeof(kXCfg) / sizeof(kXCfg[0]);
-constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);
 
 int g_max_lds = -1;
 int max_lds()
@@ -856,61 +57,6 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
     k.K11 = dc.K[1][1];
 }
 
-template <typename T, int S, int WPL, int NS, int NO>
-hipError_t run_x(const KArgs<T> &k, int64_t nlines, hipStream_t st)
-{
-    constexpr int VW = (sizeof(T) == 4) ? (S >= 4 ? 4 : S) : (S >= 2 ? 2 : 1);
-    const size_t lds = (size_t)NS * 64 * WPL * (S + 1) * sizeof(T);
-    auto fn = k_sweep_x<T, S, WPL, NS, NO, VW>;
-    if (lds > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(fn, dim3((unsigned)nlines), dim3(64 * WPL), lds, st, k);
-    return hipGetLastError();
-}
-
-template <typename T, int S, int W, int NS, int NO>
-hipError_t run_s(const KArgs<T> &k, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_sweep_s<T, S, W, NS, NO>), dim3((unsigned)k.nblocks), dim3(64 * W), 0,
-                       st, k);
-    return hipGetLastError();
-}
-
-template <typename T, int NS, int NO>
-hipError_t dispatch_x(const KArgs<T> &k, int64_t nlines, int id, hipStream_t st)
-{
-    switch (id) {
-    case 0: return run_x<T, 2, 1, NS, NO>(k, nlines, st);
-    case 1: return run_x<T, 4, 1, NS, NO>(k, nlines, st);
-    case 2: return run_x<T, 8, 1, NS, NO>(k, nlines, st);
-    case 3: return run_x<T, 16, 1, NS, NO>(k, nlines, st);
-    case 4: return run_x<T, 16, 2, NS, NO>(k, nlines, st);
-    case 5: return run_x<T, 16, 4, NS, NO>(k, nlines, st);
-    case 6: return run_x<T, 8, 8, NS, NO>(k, nlines, st);
-    case 7: return run_x<T, 16, 8, NS, NO>(k, nlines, st);
-    case 8: return run_x<T, 8, 2, NS, NO>(k, nlines, st);
-    case 9: return run_x<T, 8, 4, NS, NO>(k, nlines, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T, int NS, int NO>
-hipError_t dispatch_s(const KArgs<T> &k, int id, hipStream_t st)
-{
-    switch (id) {
-    case 0: return run_s<T, 16, 16, NS, NO>(k, st);
-    case 1: return run_s<T, 16, 8, NS, NO>(k, st);
-    case 2: return run_s<T, 8, 16, NS, NO>(k, st);
-    case 3: return run_s<T, 8, 8, NS, NO>(k, st);
-    case 4: return run_s<T, 4, 16, NS, NO>(k, st);
-    case 5: return run_s<T, 16, 4, NS, NO>(k, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename T>
 hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
                     const void *const *fptr, void *const *optr, const int *cfg, hipStream_t st)
@@ -938,13 +84,14 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
         k.pn2 = g.n[2];
         k.pd1 = g.ndim > 1 ? g.dirichlet[1] : 0;
         k.pd2 = g.ndim > 2 ? g.dirichlet[2] : 0;
-        switch (nsno) {
-        case 11: return dispatch_x<T, 1, 1>(k, nlines, cfg[0], st);
-        case 12: return dispatch_x<T, 1, 2>(k, nlines, cfg[0], st);
-        case 22: return dispatch_x<T, 2, 2>(k, nlines, cfg[0], st);
-        case 23: return dispatch_x<T, 2, 3>(k, nlines, cfg[0], st);
-        default: return hipErrorInvalidValue;
-        }
+        if (op.chain && (reinterpret_cast<uintptr_t>(optr[op.no]) % (vw * sizeof(T)))) k.aligned = 0;
+        const bool small = op.nf <= 4;
+        if constexpr (sizeof(T) == 4)
+            return small ? dispatch_x_f32_n4(k, nlines, nsno, cfg[0], st)
+                         : dispatch_x_f32_n16(k, nlines, nsno, cfg[0], st);
+        else
+            return small ? dispatch_x_f64_n4(k, nlines, nsno, cfg[0], st)
+                         : dispatch_x_f64_n16(k, nlines, nsno, cfg[0], st);
     }
     const SCfg c = kSCfg[cfg[0]];
     const int WS = c.S * c.W;
@@ -971,13 +118,11 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
     k.nblocks = (int64_t)k.ntiles * ((g.n[0] + 63) / 64) * k.nouter;
     k.dS = (T)exp(-dc.nu * c.S);
     k.dBlk = k.dS;
-    switch (nsno) {
-    case 11: return dispatch_s<T, 1, 1>(k, cfg[0], st);
-    case 12: return dispatch_s<T, 1, 2>(k, cfg[0], st);
-    case 22: return dispatch_s<T, 2, 2>(k, cfg[0], st);
-    case 23: return dispatch_s<T, 2, 3>(k, cfg[0], st);
-    default: return hipErrorInvalidValue;
-    }
+    const bool small = op.nf <= 4;
+    if constexpr (sizeof(T) == 4)
+        return small ? dispatch_s_f32_n4(k, nsno, cfg[0], st) : dispatch_s_f32_n16(k, nsno, cfg[0], st);
+    else
+        return small ? dispatch_s_f64_n4(k, nsno, cfg[0], st) : dispatch_s_f64_n16(k, nsno, cfg[0], st);
 }
 
 }  // namespace
@@ -1022,6 +167,8 @@ int default_config(const Geom &g, int dir, bool fp64, int ns, int no, int *cfg)
     cfg[0] = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
     return config_valid(g, dir, fp64, ns, no, cfg) ? 0 : -1;
 }
+
+int config_count(int dir) { return dir == 0 ? NXCFG : NSCFG; }
 
 int strided_tile_nodes(int cfgid) { return kSCfg[cfgid].S * kSCfg[cfgid].W; }
 

@@ -12,9 +12,13 @@
 //   * a kernel program per entry point: the stage schedule of Table 2 with the
 //     ADI compositions written through directional D's and fused into the
 //     sweeps' prologues/epilogues, the time update fused into the last sweep.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -232,6 +236,13 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
         }
         op.nf = (int)fields.size();
         for (int i = 0; i < op.nf; ++i) op.f[i] = fields[i];
+        if (!pl.masked) {
+            const std::string key = tune_op_key(op);
+            for (const auto &t : pl.tuned) {
+                int c[2] = {t.second, 0};
+                if (t.first == key && config_valid(pl.geom, dir, pl.fp64, ns, no, c)) cfg[0] = t.second;
+            }
+        }
         ProgOp po;
         po.op = op;
         po.cfg[0] = cfg[0];
@@ -490,6 +501,51 @@ bool build_apply(Builder &b, Program &prog, int op)
     return b.emit(prog, 0, {lin(B_IN) + lin(y, -1.0) + lin(z, -1.0) + lin(yz)}, {f}, 1);
 }
 
+std::string tune_problem_key(const mol_plan_ *pl)
+{
+    std::ostringstream o;
+    o << (pl->fp64 ? "f64" : "f32") << " nd" << pl->geom.ndim << " n" << pl->geom.n[0] << "x"
+      << pl->geom.n[1] << "x" << pl->geom.n[2] << " bc" << pl->desc.bc[0] << pl->desc.bc[1]
+      << pl->desc.bc[2] << " P" << pl->desc.P << (pl->masked ? " masked" : "");
+    return o.str();
+}
+
+std::string tune_op_key(const SweepOp &op)
+{
+    std::ostringstream o;
+    o << "dir" << op.dir << " nf" << op.nf << " ns" << op.ns << " no" << op.no << " ch" << op.chain;
+    return o.str();
+}
+
+// Tuning cache: lines "<problem key> | <op key> | <config id>".
+void load_tune_cache(mol_plan_ *pl)
+{
+    std::string path;
+    if (const char *e = std::getenv("MOLT_TUNE_CACHE")) {
+        path = e;
+    } else {
+        Dl_info info;
+        if (dladdr(reinterpret_cast<void *>(&load_tune_cache), &info) && info.dli_fname) {
+            path = info.dli_fname;
+            const size_t sl = path.rfind('/');
+            path = (sl == std::string::npos ? std::string(".") : path.substr(0, sl)) + "/tune_cache.txt";
+        }
+    }
+    if (path.empty()) return;
+    std::ifstream f(path);
+    if (!f) return;
+    const std::string pk = tune_problem_key(pl);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find(" | "), b = line.rfind(" | ");
+        if (a == std::string::npos || b == a) continue;
+        if (line.substr(0, a) != pk) continue;
+        const std::string ok = line.substr(a + 3, b - a - 3);
+        const int id = std::atoi(line.c_str() + b + 3);
+        pl->tuned.push_back({ok, id});
+    }
+}
+
 mol_status validate(const mol_desc *d)
 {
     if (!d) return fail(MOL_E_INVALID, "desc is NULL");
@@ -566,6 +622,7 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
         pl->unknowns = 0;
         for (int64_t i = 0; i < pl->npts; ++i) pl->unknowns += d->mask[i] ? 1 : 0;
     }
+    load_tune_cache(pl);
     Builder b(*pl, dry);
     // step: u_next = 2 u - u_prev + rhs(u)
     bool ok = build_rhs(b, pl->step, B_UCURR, {{B_UNEXT, lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0), 1.0}});
@@ -885,6 +942,62 @@ mol_status mol_profile_step(mol_plan *pl, const void *u_prev, const void *u_curr
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
     return e == hipSuccess ? MOL_OK : dev_err(e, "mol_profile_step");
+}
+
+mol_status mol_plan_kernel_configs(const mol_plan *pl, int kernel, int *ids, int max, int *count,
+                                   int *current)
+{
+    if (!pl) return fail(MOL_E_INVALID, "NULL plan");
+    const Program &sp = pl->solve_step.empty() ? pl->step : pl->solve_step;
+    if (kernel < 0 || kernel >= (int)sp.size()) return fail(MOL_E_INVALID, "kernel index out of range");
+    const SweepOp &op = sp[kernel].op;
+    int cnt = 0;
+    if (!pl->masked) {
+        for (int c = 0; c < config_count(op.dir); ++c) {
+            int cf[2] = {c, 0};
+            if (!config_valid(pl->geom, op.dir, pl->fp64, op.ns, op.no, cf)) continue;
+            if (ids && cnt < max) ids[cnt] = c;
+            ++cnt;
+        }
+    }
+    if (count) *count = cnt;
+    if (current) *current = sp[kernel].cfg[0];
+    return MOL_OK;
+}
+
+mol_status mol_plan_set_kernel_config(mol_plan *pl, int kernel, int config)
+{
+    if (!pl) return fail(MOL_E_INVALID, "NULL plan");
+    if (pl->masked) return fail(MOL_E_UNSUPPORTED, "masked plans have a single configuration");
+    Program &sp = pl->solve_step.empty() ? pl->step : pl->solve_step;
+    if (kernel < 0 || kernel >= (int)sp.size()) return fail(MOL_E_INVALID, "kernel index out of range");
+    const SweepOp ref = sp[kernel].op;
+    int cf[2] = {config, 0};
+    if (!config_valid(pl->geom, ref.dir, pl->fp64, ref.ns, ref.no, cf))
+        return fail(MOL_E_INVALID, "configuration not valid for this kernel");
+    const std::string key = tune_op_key(ref);
+    for (Program *pr : {&pl->step, &pl->start, &pl->inc_step, &pl->solve_pro, &pl->solve_step,
+                        &pl->solve_inc_step}) {
+        for (ProgOp &po : *pr)
+            if (tune_op_key(po.op) == key) po.cfg[0] = config;
+    }
+    for (Program &pr : pl->apply)
+        for (ProgOp &po : pr)
+            if (tune_op_key(po.op) == key) po.cfg[0] = config;
+    // the captured graph holds the old launches
+    if (pl->gexec) { (void)hipGraphExecDestroy(pl->gexec); pl->gexec = nullptr; }
+    if (pl->graph) { (void)hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+    return MOL_OK;
+}
+
+mol_status mol_plan_tune_key(const mol_plan *pl, int kernel, char *buf, int len)
+{
+    if (!pl || !buf || len < 1) return fail(MOL_E_INVALID, "bad arguments");
+    const Program &sp = pl->solve_step.empty() ? pl->step : pl->solve_step;
+    if (kernel < 0 || kernel >= (int)sp.size()) return fail(MOL_E_INVALID, "kernel index out of range");
+    const std::string k = tune_problem_key(pl) + " | " + tune_op_key(sp[kernel].op);
+    snprintf(buf, (size_t)len, "%s", k.c_str());
+    return MOL_OK;
 }
 
 mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,

@@ -51,6 +51,8 @@ struct mol_plan_ {
     size_t table_bytes = 0;
     std::vector<unsigned char> h_mask;  // kept for table construction
     std::vector<double> h_cross;
+    // tuned launch configurations: key "dir nf ns no" -> config id
+    std::vector<std::pair<std::string, int>> tuned;
 };
 
 namespace molt {
@@ -96,6 +98,9 @@ struct FinalOut {
     Lin elem;
     double r;
 };
+
+std::string tune_problem_key(const mol_plan_ *pl);
+std::string tune_op_key(const SweepOp &op);
 
 std::vector<OutSpec> finals(const std::vector<FinalOut> &fo, const Lin &rhs_elem, double rhs_dcoef);
 double stage_c(int p, int m, double beta);

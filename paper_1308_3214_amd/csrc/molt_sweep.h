@@ -1,0 +1,988 @@
+// Directional sweep kernels for gfx950 (templates; instantiated in molt_sweep_*.hip): the O(N) recursive convolution
+// L_gamma^{-1} (Sec. 2: characteristic split I^L + I^R, each an exponential
+// recurrence with decay e^{-alpha h}, local integrals over one cell against the
+// quadratic through three nodes, then the boundary correction
+// A e^{-alpha(x-a)} + B e^{-alpha(b-x)}) applied along x, y or z lines, with
+// D_gamma = 1 - L_gamma^{-1} (Sec. 4, eq. LD_gam) emitted directly.
+//
+// Formulation used on the device.  With E = I - v/2 the recurrences are forced
+// only by differences of the data,
+//   E^L_p = d E^L_{p-1} + w2 (v_{p+1} - 2 v_p + v_{p-1}) - g (v_p - v_{p-1}),
+//   E^R_p = d E^R_{p+1} + w2 (v_{p+1} - 2 v_p + v_{p-1}) + g (v_{p+1} - v_p),
+//   D v_p = -(E^L_p + E^R_p + A d^p + B d^{M-p}),
+// (d = e^{-nu}, g = (1-d)/(2 nu), nu = alpha h), which is the same discrete
+// operator as I^L + I^R (exact in real arithmetic) but never forms v - L^{-1} v,
+// so D keeps full relative precision in FP32.  At a Dirichlet end node the
+// curvature term is dropped (the data's curvature there is 0 for homogeneous
+// boundary values, Sec. 3.2).
+//
+// Each launch computes up to MAXS swept combinations s_k = sum_f mS[k][f] F_f
+// of up to MAXF loaded fields and writes up to MAXO outputs
+// out_o = sum_f mOF[o][f] F_f + sum_k mOD[o][k] D(s_k): the ADI compositions
+// (eqs. C_def_ADI, D_def_ADI, ...) and the time update are fused this way.
+//
+// x lines (contiguous): one workgroup per line, the line staged through LDS
+// (coalesced vector loads, padded to avoid bank conflicts), every lane runs
+// the recurrences over S consecutive nodes, lane carries are combined by a
+// wave-level scan of the linear recurrence (multiplier d^S) and waves through
+// LDS: exact.
+//
+// y / z lines (strided): lanes own consecutive columns (coalesced rows), waves
+// of a workgroup stack along the line, each lane runs S nodes, wave carries
+// are scanned through LDS.  Lines longer than one tile of W*S nodes are split
+// into tiles; the carry entering a tile is the truncated sum over a halo of
+// K nodes with d^K below the dtype's rounding (the exponential decay of the
+// Green's function), computed cooperatively by all waves of the tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "molt_internal.h"
+
+namespace molt {
+
+template <typename T>
+struct KArgs {
+    const T *f[MAXF];
+    T *o[MAXO];
+    T mS[MAXS][MAXF];
+    T mOF[MAXO][MAXF];
+    T mOD[MAXO][MAXS];
+    int nf;
+    int proj;
+    int chain;        // x: also write D_x(out_0) to ochain (next sweep of out_0)
+    T *ochain;
+    int64_t n;        // nodes per line
+    int64_t nlines;   // x: lines; strided: columns (x extent)
+    int64_t lineoff;  // x: element offset between lines
+    int64_t ls;       // strided: stride between nodes of a line
+    int64_t os;       // strided: stride of the outer index
+    int64_t nouter;   // strided: outer extent
+    int64_t nblocks;  // strided: total workgroups (XCD remap)
+    int ntiles;       // strided: tiles per line
+    int halo;         // strided: halo nodes per side
+    int aligned;      // x: vector loads allowed
+    int periodic;     // along the sweep
+    T d, g, w2;
+    T gw;             // g + w2
+    T dpow[33];       // d^0 .. d^32
+    T dS;             // d^S
+    T dBlk;           // x: d^{64 S} (one wave of lanes)
+    double nu;
+    double K00, K01, K10, K11;
+    // projection: line index = (i1 in [0,pn1), i2 in [0,pn2)); Dirichlet flags
+    int64_t pn1, pn2;
+    int pd1, pd2;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t N)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
+    // contiguous range of logical tiles so that neighbouring tiles of a line
+    // (which read each other's halo) share one L2.
+    const int64_t X = 8;
+    int64_t x = i % X, local = i / X;
+    int64_t per = N / X, rem = N % X;
+    return x * per + (x < rem ? x : rem) + local;
+}
+
+template <int C>
+struct ic {
+    static constexpr int value = C;
+};
+
+// Calls body(f0, ic<c>{}) over the fields [0, nf) in chunks of c <= CH fields
+// (c static): each chunk issues all of its loads before it uses any of them.
+template <int CH, int NFMAX, typename F>
+__device__ __forceinline__ void field_chunks(int nf, F &&body)
+{
+    static_assert(CH >= 1 && CH <= 4, "chunk of 1..4 fields");
+    if constexpr (NFMAX <= 4) {
+#pragma unroll
+        for (int f0 = 0; f0 < NFMAX; f0 += CH) {
+            const int left = nf - f0;
+            if (left <= 0) break;
+            if constexpr (CH >= 4) { if (left >= 4) { body(f0, ic<4>{}); continue; } }
+            if constexpr (CH >= 3) { if (left == 3) { body(f0, ic<3>{}); continue; } }
+            if constexpr (CH >= 2) { if (left >= 2) { body(f0, ic<2>{}); continue; } }
+            body(f0, ic<1>{});
+        }
+    } else {
+        for (int f0 = 0; f0 < nf; f0 += CH) {
+            const int left = nf - f0;
+            if constexpr (CH >= 4) { if (left >= 4) { body(f0, ic<4>{}); continue; } }
+            if constexpr (CH >= 3) { if (left == 3) { body(f0, ic<3>{}); continue; } }
+            if constexpr (CH >= 2) { if (left >= 2) { body(f0, ic<2>{}); continue; } }
+            body(f0, ic<1>{});
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_up(T v, int off) { return __shfl_up(v, off, 64); }
+template <typename T>
+__device__ __forceinline__ T shfl_down(T v, int off) { return __shfl_down(v, off, 64); }
+
+// A row of zeros in device memory.  Loads of nodes that read as 0 (outside a
+// line, Dirichlet end rows of a halo) are pointed here instead of being
+// predicated: every load is issued unconditionally, so a wave keeps all of its
+// loads in flight at once.
+__device__ double kZeroRow[64] = {};   // never written
+template <typename T>
+__device__ __forceinline__ const T *zero_row()
+{
+    return reinterpret_cast<const T *>(kZeroRow);
+}
+
+// e^{-x} for x >= 0 in the kernel's precision: FP32 kernels use the hardware
+// base-2 exponential (about 1 ulp), FP64 kernels the FP64 library exp.
+template <typename T>
+__device__ __forceinline__ T expneg(double x);
+template <>
+__device__ __forceinline__ float expneg<float>(double x)
+{
+    return exp2f((float)(-x * 1.4426950408889634));
+}
+template <>
+__device__ __forceinline__ double expneg<double>(double x)
+{
+    return exp(-x);
+}
+
+// Forcing of the two recurrences at node p from its neighbours vm, v0, vp
+// (end and outside nodes already read as 0).  Dirichlet end nodes drop the
+// curvature term; E^L starts at node 0 and E^R at node M.
+template <typename T>
+__device__ __forceinline__ T force_L(T vm, T v0, T vp, int p, int M, bool dir_end, T g, T w2)
+{
+    if (dir_end) {
+        if (p <= 0 || p > M) return T(0);
+        if (p == M) return -g * (v0 - vm);
+    } else if (p > M) {
+        return T(0);
+    }
+    return w2 * ((vp - v0) - (v0 - vm)) - g * (v0 - vm);
+}
+template <typename T>
+__device__ __forceinline__ T force_R(T vm, T v0, T vp, int p, int M, bool dir_end, T g, T w2)
+{
+    if (dir_end) {
+        if (p < 0 || p >= M) return T(0);
+        if (p == 0) return g * (vp - v0);
+    } else if (p > M) {
+        return T(0);
+    }
+    return w2 * ((vp - v0) - (v0 - vm)) + g * (vp - v0);
+}
+
+// Local recurrences over S nodes p0..p0+S-1 from the values v[0..S+1] of
+// nodes p0-1..p0+S.  sum[j] = local E^L + local E^R (zero carry-in at both
+// segment ends); aL = local E^L at the last node, aR = local E^R at the first
+// node, eLM = local E^L at node M if this segment holds it.
+template <typename T, int S>
+__device__ __forceinline__ void seg_recur(const T (&v)[S + 2], int p0, int M, bool dir_end, T d,
+                                          T g, T w2, T (&sum)[S], T &aL, T &aR, T &eLM)
+{
+    T e = T(0);
+    eLM = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        e = d * e + force_L(v[j], v[j + 1], v[j + 2], p, M, dir_end, g, w2);
+        sum[j] = e;
+        if (p == M) eLM = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        e = d * e + force_R(v[j], v[j + 1], v[j + 2], p0 + j, M, dir_end, g, w2);
+        sum[j] += e;
+    }
+    aR = e;
+}
+
+// In place: sum[j] <- D_j = -(sum[j] + d^{j+1} cL + d^{S-j} cR + A d^p + B d^{M-p}),
+// p = p0 + j; zero beyond the line and at Dirichlet end nodes.  A, B in FP64.
+template <typename T, int S>
+__device__ __forceinline__ void seg_close(T (&sum)[S], T cL, T cR, double A, double B, int p0,
+                                          int M, double nu, T d, bool dir_end)
+{
+    const double dd = exp(-nu);
+    double ta = (A != 0.0) ? A * exp(-nu * (double)p0) : 0.0;
+    T ldec = d * cL;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        sum[j] += (T)ta + ldec;
+        ta *= dd;
+        ldec *= d;
+    }
+    const int rem = M - p0;
+    const int jmax = (rem >= S - 1) ? (S - 1) : rem;
+    double tb = (B != 0.0 && jmax >= 0) ? B * exp(-nu * (double)(rem - jmax)) : 0.0;
+    T rdec = cR;
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        rdec *= d;
+        sum[j] += rdec;
+        if (j <= jmax) {
+            sum[j] += (T)tb;
+            tb *= dd;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        sum[j] = (p > M || (dir_end && (p == 0 || p == M))) ? T(0) : -sum[j];
+    }
+}
+
+// Branch-free recurrences for a segment whose nodes are all interior nodes of
+// a Dirichlet line or of a periodic line (values outside the line read as 0).
+// With dl_j = v_j - v_{j-1}:  F^L_j = w2 dl_{j+1} - (g + w2) dl_j,
+// F^R_j = (g + w2) dl_{j+1} - w2 dl_j.
+template <typename T, int S>
+__device__ __forceinline__ void seg_recur_fast(const T (&v)[S + 2], T d, T gw, T w2, T (&sum)[S],
+                                               T &aL, T &aR)
+{
+    T dl[S + 1];
+#pragma unroll
+    for (int j = 0; j <= S; ++j) dl[j] = v[j + 1] - v[j];
+    T e = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        e = d * e + (w2 * dl[j + 1] - gw * dl[j]);
+        sum[j] = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        e = d * e + (gw * dl[j + 1] - w2 * dl[j]);
+        sum[j] += e;
+    }
+    aR = e;
+}
+
+// Dirichlet end nodes inside a segment handled by seg_recur_fast: at node 0 the
+// forcing must be F^L = 0, F^R = g v_1 and at node M F^L = g v_{M-1}, F^R = 0
+// (no curvature at a boundary node); the branch-free forcing is off by
+// -w2 v_1 (node 0) and -w2 v_{M-1} (node M) in both directions.  The linear
+// recurrences carry these corrections with powers of d.  v1 = value at node 1,
+// vM1 = value at node M-1 (read by the caller).  Returns E^L_M (local) in eLM.
+template <typename T, int S>
+__device__ __forceinline__ void seg_fix_dirichlet(int p0, int M, T v1, T vM1, T d, T w2,
+                                                  T (&sum)[S], T &aL, T &aR, T &eLM)
+{
+    if (p0 == 0) {
+        const T c = -w2 * v1;
+        T pw = c, last = c;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            sum[j] += pw;                 // forward: c d^j
+            last = pw;
+            pw *= d;
+        }
+        aL += last;                       // c d^{S-1}
+        sum[0] += c;                      // backward: node 0 only
+        aR += c;
+    }
+    const int jm = M - p0;
+    if (jm >= 0 && jm < S) {
+        const T c = -w2 * vM1;
+        T pf = c, pb = c, lf = T(0), lb = T(0);
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (j >= jm) { sum[j] += pf; lf = pf; pf *= d; }
+        }
+#pragma unroll
+        for (int j = S - 1; j >= 0; --j) {
+            if (j <= jm) { sum[j] += pb; lb = pb; pb *= d; }
+        }
+        aL += lf;                         // c d^{S-1-jm}
+        aR += lb;                         // c d^{jm}
+        T em = T(0);
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            if (j == jm) em = sum[j];     // E^R_M = 0 locally: sum = E^L_M
+        eLM = em;
+    }
+}
+
+// Closure for a segment: D_j = -(sum_j + d^{j+1} cL + d^{S-j} cR + A d^p + B d^{M-p}).
+// Interior segments use two decaying terms with d^j from the kernel
+// arguments; a segment holding node M (or nodes beyond it) adds the B term
+// node by node and zeroes what lies beyond M; Dirichlet end nodes get D = 0.
+template <typename T, int S>
+__device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A, double B, int p0,
+                                               int M, double nu, T d, const T *dpow, bool dir_end)
+{
+    const int jm = M - p0;
+    const bool holdsM = jm < S;
+    const T lt = d * cL + ((A != 0.0) ? (T)A * expneg<T>(nu * (double)p0) : T(0));
+    const T rt = d * cR + ((!holdsM && B != 0.0) ? (T)B * expneg<T>(nu * (double)(jm - (S - 1))) : T(0));
+    T tl = lt, tr = rt;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        sum[j] += tl;                 // lt d^j
+        tl *= d;
+        sum[S - 1 - j] += tr;         // rt d^{S-1-j}
+        tr *= d;
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) sum[j] = -sum[j];
+    if (holdsM) {
+        T pw = (T)B;
+#pragma unroll
+        for (int j = S - 1; j >= 0; --j) {
+            if (j > jm) {
+                sum[j] = T(0);
+            } else {
+                sum[j] -= pw;
+                pw *= d;
+            }
+        }
+        if (dir_end) {
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                if (j == jm) sum[j] = T(0);
+        }
+    }
+    if (dir_end && p0 == 0) sum[0] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// x sweep: contiguous lines, one line per workgroup of NT = 64*WPL threads
+// ---------------------------------------------------------------------------
+// D_x of NSW combinations staged in LDS (sm + k*NPAD, padded slots); the D
+// values replace the inputs in place.  Ends with a __syncthreads.
+template <typename T, int S, int WPL, int NSW, bool PER>
+__device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)[MAXS][WPL],
+                                             T (*ends)[MAXS], int t, int n)
+{
+    constexpr int NT = 64 * WPL;
+    constexpr int NPAD = NT * (S + 1);
+    const int lane = t & 63, wave = t >> 6;
+    const int M = n - 1;
+    const int p0 = t * S;
+    const int jm = M - p0;
+    constexpr bool dir_end = !PER;
+    const bool slow = PER && (p0 + S - 1 > M);          // periodic lane crossing the end
+    T sum[NSW][S];
+    T aL[NSW], aR[NSW], eLM[NSW];
+#pragma unroll
+    for (int k = 0; k < NSW; ++k) {
+        const T *sk = sm + k * NPAD;
+        T v[S + 2];
+#pragma unroll
+        for (int j = 0; j < S; ++j) v[j + 1] = sk[t * (S + 1) + j];
+        if (p0 == 0) v[0] = PER ? sk[(M / S) * (S + 1) + (M % S)] : T(0);
+        else v[0] = sk[(t - 1) * (S + 1) + (S - 1)];
+        v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
+        if (PER && jm >= 0 && jm < S) v[jm + 2] = sk[0];          // wrap at node M
+        if (PER && slow) {
+            seg_recur<T, S>(v, p0, M, false, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+        } else {
+            seg_recur_fast<T, S>(v, a.d, a.gw, a.w2, sum[k], aL[k], aR[k]);
+            eLM[k] = aL[k];                            // periodic: node M ends its lane
+            if (dir_end) {
+                const T v1 = (p0 == 0 && n > 1) ? sk[1] : T(0);
+                const int q = M - 1;
+                const T vM1 = (jm >= 0 && jm < S && q >= 0) ? sk[(q / S) * (S + 1) + (q % S)] : T(0);
+                seg_fix_dirichlet<T, S>(p0, M, v1, vM1, a.d, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+            }
+        }
+    }
+    // lane scan (multiplier d^S per lane), then waves through LDS
+    T cL[NSW], cR[NSW];
+#pragma unroll
+    for (int k = 0; k < NSW; ++k) {
+        T xl = aL[k], xr = aR[k], m = a.dS;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T yl = shfl_up(xl, off);
+            const T yr = shfl_down(xr, off);
+            if (lane >= off) xl += m * yl;
+            if (lane + off < 64) xr += m * yr;
+            m *= m;
+        }
+        const T exl = shfl_up(xl, 1);
+        const T exr = shfl_down(xr, 1);
+        cL[k] = (lane == 0) ? T(0) : exl;
+        cR[k] = (lane == 63) ? T(0) : exr;
+        if (WPL > 1) {
+            if (lane == 63) wtot[0][k][wave] = xl;
+            if (lane == 0) wtot[1][k][wave] = xr;
+        }
+    }
+    if (WPL > 1) {
+        __syncthreads();
+        const T pl = expneg<T>(a.nu * (double)S * (double)lane);
+        const T pr = expneg<T>(a.nu * (double)S * (double)(63 - lane));
+#pragma unroll
+        for (int k = 0; k < NSW; ++k) {
+            T cw = T(0), cwr = T(0);
+            for (int w = 0; w < wave; ++w) cw = a.dBlk * cw + wtot[0][k][w];
+            for (int w = WPL - 1; w > wave; --w) cwr = a.dBlk * cwr + wtot[1][k][w];
+            cL[k] += pl * cw;
+            cR[k] += pr * cwr;
+        }
+    }
+    // line ends: E^R_0 (lane holding node 0) and E^L_M (lane holding node M)
+#pragma unroll
+    for (int k = 0; k < NSW; ++k) {
+        if (p0 == 0) ends[0][k] = aR[k] + a.dS * cR[k];
+        if (jm >= 0 && jm < S) ends[1][k] = eLM[k] + expneg<T>(a.nu * (double)(jm + 1)) * cL[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NSW; ++k) {
+        const double er0 = (double)ends[0][k], elm = (double)ends[1][k];
+        const double A = a.K00 * er0 + a.K01 * elm;
+        const double B = a.K10 * er0 + a.K11 * elm;
+        if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, false);
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, a.dpow, dir_end);
+        T *sk = sm + k * NPAD;
+#pragma unroll
+        for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
+    }
+    __syncthreads();
+}
+
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
+__global__ void __launch_bounds__(64 * WPL)
+k_sweep_x(const KArgs<T> a)
+{
+    constexpr int NT = 64 * WPL;
+    constexpr int NPAD = NT * (S + 1);
+    constexpr int NV = S / VW;
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
+    __shared__ T wtot[2][MAXS][WPL];
+    __shared__ T ends[2][MAXS];
+
+    const int t = threadIdx.x;
+    const int64_t line = blockIdx.x;
+    const int n = (int)a.n;
+    const int M = n - 1;
+    const int64_t base = line * a.lineoff;            // uniform per workgroup
+    constexpr bool dir_end = !PER;
+
+    bool bline = false;
+    if (a.proj) {
+        const int64_t i1 = line % a.pn1, i2 = line / a.pn1;
+        bline = (a.pd1 && (i1 == 0 || i1 == a.pn1 - 1)) || (a.pd2 && (i2 == 0 || i2 == a.pn2 - 1));
+    }
+
+    // ---- phase 1: coalesced loads (all of one field at once), prologue ----
+    T sv[NS][S], ev[NO][S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sv[k][j] = T(0);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) ev[o][j] = T(0);
+    }
+    // Loads are unconditional (clamped addresses, values beyond the line
+    // zeroed afterwards) so that all of a field's loads are in flight at once;
+    // vector loads need an aligned line whose length is a multiple of VW, so a
+    // vector lies wholly inside or wholly beyond the line.
+    auto accumulate = [&](int f, const T (&x)[S]) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sv[k][j] += a.mS[k][f] * x[j];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ev[o][j] += a.mOF[o][f] * x[j];
+        }
+    };
+    auto load_vec = [&](int f0, auto cc) {
+        constexpr int C = decltype(cc)::value;
+        T x[C][S];
+#pragma unroll
+        for (int c0 = 0; c0 < C; ++c0) {
+            const T *src = a.f[f0 + c0] + base;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int e0 = (i * NT + t) * VW;
+                const bool in = e0 < n;
+                const vec_t vv = *reinterpret_cast<const vec_t *>(src + (in ? (unsigned)e0 : 0u));
+#pragma unroll
+                for (int c = 0; c < VW; ++c) x[c0][i * VW + c] = in ? vv[c] : T(0);
+            }
+        }
+#pragma unroll
+        for (int c0 = 0; c0 < C; ++c0) accumulate(f0 + c0, x[c0]);
+    };
+    auto load_scalar = [&](int f) {
+        const T *src = a.f[f] + base;
+        T x[S];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+                const int e = (i * NT + t) * VW + c;
+                const T val = src[(unsigned)(e < n ? e : n - 1)];
+                x[i * VW + c] = (e < n) ? val : T(0);
+            }
+        }
+        accumulate(f, x);
+    };
+    if (a.aligned) {
+        field_chunks<4, NFMAX>(a.nf, load_vec);
+    } else {
+        for (int f = 0; f < a.nf; ++f) load_scalar(f);
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int e = (i * NT + t) * VW + c;
+            const int slot = (e / S) * (S + 1) + (e % S);
+            const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][i * VW + c];
+        }
+    }
+    __syncthreads();
+
+    // ---- phases 2-3: recurrences, scans, closure (D in LDS) ----
+    x_line_sweep<T, S, WPL, NS, PER>(a, sm, wtot, ends, t, n);
+
+    // ---- phase 4: epilogue in the coalesced layout ----
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int e0 = (i * NT + t) * VW;
+        T out[NO][VW];
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int e = e0 + c;
+            const int slot = (e / S) * (S + 1) + (e % S);
+            T Dk[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
+            const bool z = a.proj && (bline || (dir_end && (e == 0 || e == M)));
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                T r = ev[o][i * VW + c];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
+                out[o][c] = z ? T(0) : r;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            T *dst = a.o[o] + base;
+            if (a.aligned && e0 + VW <= n) {
+                vec_t vv;
+#pragma unroll
+                for (int c = 0; c < VW; ++c) vv[c] = out[o][c];
+                *reinterpret_cast<vec_t *>(dst + e0) = vv;
+            } else {
+#pragma unroll
+                for (int c = 0; c < VW; ++c)
+                    if (e0 + c < n) dst[e0 + c] = out[o][c];
+            }
+        }
+        if (a.chain) {
+            // the next x sweep of output 0 starts from these values (each
+            // slot is read and rewritten by the same thread only)
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+                const int e = e0 + c;
+                const int slot = (e / S) * (S + 1) + (e % S);
+                const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
+                sm[slot] = zero ? T(0) : out[0][c];
+            }
+        }
+    }
+    if (a.chain) {
+        __syncthreads();
+        x_line_sweep<T, S, WPL, 1, PER>(a, sm, wtot, ends, t, n);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int e0 = (i * NT + t) * VW;
+            T out[VW];
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+                const int e = e0 + c;
+                out[c] = sm[(e / S) * (S + 1) + (e % S)];
+            }
+            T *dst = a.ochain + base;
+            if (a.aligned && e0 + VW <= n) {
+                vec_t vv;
+#pragma unroll
+                for (int c = 0; c < VW; ++c) vv[c] = out[c];
+                *reinterpret_cast<vec_t *>(dst + e0) = vv;
+            } else {
+#pragma unroll
+                for (int c = 0; c < VW; ++c)
+                    if (e0 + c < n) dst[e0 + c] = out[c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// strided sweep (y or z): lanes = 64 consecutive columns, W waves x S nodes
+// ---------------------------------------------------------------------------
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_s(const KArgs<T> a)
+{
+    constexpr int WS = W * S;
+    __shared__ T red[2][NS][W][64];      // cooperative sums, then wave aggregates
+    __shared__ T endv[2][NS][64];        // E^R_0 and E^L_M per column (one tile)
+
+    const int lane = threadIdx.x & 63;
+    // wave index as a scalar: row numbers, row pointers and every per-row
+    // decision below are wave-uniform (scalar registers, one shared lane offset)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t L = xcd_remap(blockIdx.x, a.nblocks);
+    const int tile = (int)(L % a.ntiles);
+    const int64_t rest = L / a.ntiles;
+    const int64_t ncg = (a.nlines + 63) / 64;
+    const int64_t cg = rest % ncg;
+    const int64_t outer = rest / ncg;
+    const int col = (int)(cg * 64) + lane;
+    const bool active = col < a.nlines;
+    const int n = (int)a.n, M = n - 1;
+    const int ls = (int)a.ls;
+    const int64_t blk = cg * 64 + outer * a.os;          // uniform per workgroup
+    const int loff = active ? lane : 0;                  // per-lane column offset
+    constexpr bool dir_end = !PER;
+    constexpr bool per = PER;
+    const T d = a.d, g = a.g, w2 = a.w2;
+    const int oa = tile * WS;
+    const int ob = (oa + WS < n) ? oa + WS : n;
+    const bool split = a.ntiles > 1;
+    const int K = a.halo;
+    const int p0 = oa + wave * S;
+
+    // this wave's share of the halo sums: kk in [k0, k1) (truncation length K)
+    constexpr int QB = 2;                                // halo rows per wave in the batched path
+    const int q = (K + W - 1) / W;
+    const int k0 = wave * q;
+    const int k1 = (k0 + q < K) ? k0 + q : K;
+    const bool hb_top = split && (per || oa > 0);
+    const bool hb_bot = split && (per || ob < n);
+    const bool batched = (q <= QB);
+    // row index as read: periodic wrap, or -1 when the node reads as 0
+    auto rowidx = [&](int p) -> int {
+        if (per) {
+            p %= n;
+            if (p < 0) p += n;
+            return p;
+        }
+        return (p <= 0 || p >= M) ? -1 : p;
+    };
+
+    // ---- main nodes p0-1 .. p0+S and the halo rows: one batch of loads per field ----
+    T ev[NO][S];
+    T v[NS][S + 2];
+    T ht[NS][QB + 2], hbv[NS][QB + 2];   // top rows oa-k0-i, bottom rows ob+k0-1+i
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) v[k][j] = T(0);
+#pragma unroll
+        for (int i = 0; i < QB + 2; ++i) { ht[k][i] = T(0); hbv[k][i] = T(0); }
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) ev[o][j] = T(0);
+    }
+    const unsigned lo = (unsigned)loff;
+    // row pointer of node p of this column group (wave-uniform), or the zero
+    // row when the node reads as 0 (outside a Dirichlet line)
+    auto rowptr = [&](const T *fb, int p) -> const T * {
+        if (per) {
+            if (p < 0) p += n;
+            if (p >= n) p -= n;
+        }
+        return (p >= 0 && p <= M) ? fb + (int64_t)p * ls : zero_row<T>();
+    };
+    auto load_fields = [&](int f0, auto cc) {
+        constexpr int C = decltype(cc)::value;
+        T x[C][S + 2], xt[C][QB + 2], xb[C][QB + 2];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const T *fb = a.f[f0 + c] + blk;
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j) x[c][j] = rowptr(fb, p0 - 1 + j)[lo];
+            if (batched) {
+#pragma unroll
+                for (int i = 0; i < QB + 2; ++i) {
+                    const int rt = rowidx(oa - k0 - i);
+                    const int rb = rowidx(ob + k0 - 1 + i);
+                    xt[c][i] = (hb_top && rt >= 0 && rt <= M ? fb + (int64_t)rt * ls : zero_row<T>())[lo];
+                    xb[c][i] = (hb_bot && rb >= 0 && rb <= M ? fb + (int64_t)rb * ls : zero_row<T>())[lo];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int f = f0 + c;
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) v[k][j] += a.mS[k][f] * x[c][j];
+                if (j >= 1 && j <= S) {
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) ev[o][j - 1] += a.mOF[o][f] * x[c][j];
+                }
+            }
+            if (batched) {
+#pragma unroll
+                for (int i = 0; i < QB + 2; ++i) {
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) {
+                        ht[k][i] += a.mS[k][f] * xt[c][i];
+                        hbv[k][i] += a.mS[k][f] * xb[c][i];
+                    }
+                }
+            }
+        }
+    };
+    field_chunks<2, NFMAX>(a.nf, load_fields);
+    if (dir_end) {
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            const int p = p0 - 1 + j;
+            if (p == 0 || p == M) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) v[k][j] = T(0);
+            }
+        }
+    }
+
+    // swept combination k at node p of this column (0 outside / at Dirichlet ends)
+    auto sval = [&](int k, int p) -> T {
+        const int r = rowidx(p);
+        if (r < 0 || !active) return T(0);
+        const int off = loff + r * ls;
+        T s = T(0);
+        for (int f = 0; f < a.nf; ++f) s += a.mS[k][f] * a.f[f][blk + off];
+        return s;
+    };
+    // this wave's share of sum_{kk<K} d^kk F(r0 + sg*kk) by direct loads (long
+    // halos only): sg = -1 sums the forcing of E^L moving up from r0, sg = +1
+    // that of E^R moving down
+    auto part = [&](int k, int r0, int sg) -> T {
+        T acc = T(0);
+        if (k0 >= k1) return acc;
+        T pw = expneg<T>(a.nu * (double)k0);
+        int r = r0 + sg * k0;
+        T vb = sval(k, r - sg), v0 = sval(k, r);
+        for (int kk = k0; kk < k1; ++kk, r += sg) {
+            const T vn = sval(k, r + sg);
+            const int rr = per ? ((r % n) + n) % n : r;
+            const T fv = (sg < 0) ? force_L(vn, v0, vb, rr, M, dir_end, g, w2)
+                                  : force_R(vb, v0, vn, rr, M, dir_end, g, w2);
+            acc += pw * fv;
+            pw *= d;
+            vb = v0;
+            v0 = vn;
+        }
+        return acc;
+    };
+    // the same sums from the batched halo rows
+    auto part_batched = [&](int k, bool top) -> T {
+        T acc = T(0);
+        T pw = expneg<T>(a.nu * (double)k0);
+#pragma unroll
+        for (int i = 0; i < QB; ++i) {
+            const int kk = k0 + i;
+            if (kk < k1) {
+                T fv;
+                if (top) {
+                    const int r = oa - 1 - kk;      // values at r+1, r, r-1 = ht[i], ht[i+1], ht[i+2]
+                    const int rr = per ? ((r % n) + n) % n : r;
+                    fv = force_L(ht[k][i + 2], ht[k][i + 1], ht[k][i], rr, M, dir_end, g, w2);
+                } else {
+                    const int r = ob + kk;          // values at r-1, r, r+1 = hbv[i], hbv[i+1], hbv[i+2]
+                    const int rr = per ? ((r % n) + n) % n : r;
+                    fv = force_R(hbv[k][i], hbv[k][i + 1], hbv[k][i + 2], rr, M, dir_end, g, w2);
+                }
+                acc += pw * fv;
+                pw *= d;
+            }
+        }
+        return acc;
+    };
+    // cooperative pair of sums over all waves (workgroup-uniform call)
+    auto coop = [&](int r0a, int sga, bool usea, int r0b, int sgb, bool useb, bool fromregs,
+                    T (&oa_)[NS], T (&ob_)[NS]) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            red[0][k][wave][lane] = !usea ? T(0) : fromregs ? part_batched(k, true) : part(k, r0a, sga);
+            red[1][k][wave][lane] = !useb ? T(0) : fromregs ? part_batched(k, false) : part(k, r0b, sgb);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T x = T(0), y = T(0);
+            for (int w = 0; w < W; ++w) {
+                x += red[0][k][w][lane];
+                y += red[1][k][w][lane];
+            }
+            oa_[k] = x;
+            ob_[k] = y;
+        }
+        __syncthreads();
+    };
+
+    // ---- local recurrences of this wave's S nodes ----
+    const int jm = M - p0;
+    const bool slow = per && (p0 + S - 1 > M);          // periodic wave crossing the end
+    T sum[NS][S];
+    T aL[NS], aR[NS], eLM[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (PER && slow) {
+            seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
+        } else {
+            seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
+            eLM[k] = aL[k];
+            if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
+                T vM1 = T(0);
+#pragma unroll
+                for (int j = 0; j < S + 2; ++j)
+                    if (j == jm) vM1 = v[k][j];            // node M-1
+                seg_fix_dirichlet<T, S>(p0, M, v[k][2], vM1, d, w2, sum[k], aL[k], aR[k], eLM[k]);
+            }
+        }
+    }
+
+    // ---- carries entering the tile, and line-end values for split lines ----
+    T cTop[NS], cBot[NS], er0s[NS], elms[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        cTop[k] = T(0);
+        cBot[k] = T(0);
+        er0s[k] = T(0);
+        elms[k] = T(0);
+    }
+    // a tile that does not hold a line end but lies within K nodes of it
+    // needs that end's value (cooperative sums, rare)
+    const bool needA = split && !per && oa > 0 && oa < K;
+    const bool needB = split && !per && ob < n && n - ob < K;
+    if (split) {
+        coop(oa - 1, -1, hb_top, ob, +1, hb_bot, batched, cTop, cBot);
+        if (needA || needB) coop(0, +1, needA, M, -1, needB, false, er0s, elms);
+    }
+
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        red[0][k][wave][lane] = aL[k];
+        red[1][k][wave][lane] = aR[k];
+    }
+    __syncthreads();
+    // In a short last tile of a split periodic line the bottom carry enters
+    // at node n, inside a wave: it is applied through the closure instead.
+    const bool botAsB = per && split && ob == n;
+    T cL[NS], cR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T c = cTop[k];
+        for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
+        cL[k] = c;
+        T cr = botAsB ? T(0) : cBot[k];
+        for (int w = W - 1; w > wave; --w) cr = a.dS * cr + red[1][k][w][lane];
+        cR[k] = cr;
+    }
+    const bool has0 = (oa == 0), hasM = (ob == n);
+    if (!per || !split) {
+        // exact line-end values from this tile's own scan
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (p0 == 0) endv[0][k][lane] = aR[k] + a.dS * cR[k];
+            if (jm >= 0 && jm < S) endv[1][k][lane] = eLM[k] + expneg<T>(a.nu * (double)(jm + 1)) * cL[k];
+        }
+        __syncthreads();
+    }
+
+    // ---- closure and epilogue ----
+    bool bline = false;
+    if (a.proj)
+        bline = (a.pd1 && (col == 0 || col == a.pn1 - 1)) ||
+                (a.pd2 && (outer == 0 || outer == a.pn2 - 1));
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double A = 0.0, B = 0.0;
+        if (!per || !split) {
+            // a split Dirichlet line takes each end value from the tile holding
+            // it, or from the cooperative sums within K nodes of it
+            const double er0 = has0 ? (double)endv[0][k][lane] : (double)er0s[k];
+            const double elm = hasM ? (double)endv[1][k][lane] : (double)elms[k];
+            A = a.K00 * er0 + a.K01 * elm;
+            B = a.K10 * er0 + a.K11 * elm;
+        } else if (botAsB) {
+            B = (double)d * (double)cBot[k];     // cBot d^{n-p} = (d cBot) d^{M-p}
+        }
+        if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, false);
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, a.dpow, dir_end);
+    }
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        if (p > M) break;
+        const bool z = a.proj && (bline || (dir_end && (p == 0 || p == M)));
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            T r = ev[o][j];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * sum[k][j];
+            (a.o[o] + blk + (int64_t)p * ls)[lo] = z ? T(0) : r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise z = a x + b y
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T *x, T b, const T *y, T *z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride) z[k] = a * x[k] + b * y[k];
+}
+
+// ---------------------------------------------------------------------------
+// host side: launch dispatch
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// launch configurations (cfg id -> template parameters)
+// ---------------------------------------------------------------------------
+struct XCfg { int S, WPL; };
+struct SCfg { int S, W; };
+constexpr XCfg kXCfg[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}, {16, 8}, {8, 2}, {8, 4}};
+constexpr SCfg kSCfg[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {4, 16}, {16, 4}};
+constexpr int NXCFG = sizeof(kXCfg) / sizeof(kXCfg[0]);
+constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);
+
+// one per (dtype, direction class): launch a prepared KArgs with config id
+// `id` and (swept, output) counts encoded as nsno = 10*ns + no
+// _n4: field loop unrolled with static indices (op.nf <= 4); _n16: runtime loop
+hipError_t dispatch_x_f32_n4(const KArgs<float> &k, int64_t nlines, int nsno, int id, hipStream_t st);
+hipError_t dispatch_x_f64_n4(const KArgs<double> &k, int64_t nlines, int nsno, int id, hipStream_t st);
+hipError_t dispatch_s_f32_n4(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_s_f64_n4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_x_f32_n16(const KArgs<float> &k, int64_t nlines, int nsno, int id, hipStream_t st);
+hipError_t dispatch_x_f64_n16(const KArgs<double> &k, int64_t nlines, int nsno, int id, hipStream_t st);
+hipError_t dispatch_s_f32_n16(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_s_f64_n16(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+
+}  // namespace molt

@@ -1,0 +1,3 @@
+// strided-sweep kernels, double, field loop bound 4.
+#define MOLT_NFMAX 4
+#include "molt_sweep_s64.inc"

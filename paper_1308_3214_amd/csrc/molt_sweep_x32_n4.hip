@@ -1,0 +1,3 @@
+// x-sweep kernels, float, field loop bound 4.
+#define MOLT_NFMAX 4
+#include "molt_sweep_x32.inc"

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmolt.so")
+LIB_PATH = os.environ.get("MOLT_LIB") or os.path.join(_HERE, "libmolt.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmolt.so is not built (run __graft_entry__.build() or "
@@ -87,13 +87,19 @@ _lib.mol_profile_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_int)]
-for _f in ("mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
+_lib.mol_plan_kernel_configs.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.mol_plan_set_kernel_config.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+_lib.mol_plan_tune_key.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
+           "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
            "mol_solve", "mol_apply", "mol_step_batch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
            "mol_workspace_bytes", "mol_start", "mol_step", "mol_solve", "mol_step_batch",
-           "mol_apply", "mol_profile_step", "mol_last_error")
+           "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
+           "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error")
 
 
 def _check(st):
@@ -227,6 +233,22 @@ class Plan:
                                      ctypes.byref(cnt)))
         return [{"ms": ms[i], "bytes": by[i], "dir": "xyz"[dr[i]], "sweeps": ns[i]}
                 for i in range(min(cnt.value, mx))]
+
+    def kernel_configs(self, kernel):
+        """(valid configuration ids, id in use) of kernel `kernel` of the solve step."""
+        ids = (ctypes.c_int * 64)()
+        cnt, cur = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.mol_plan_kernel_configs(self._h, int(kernel), ids, 64, ctypes.byref(cnt),
+                                            ctypes.byref(cur)))
+        return [ids[i] for i in range(min(cnt.value, 64))], cur.value
+
+    def set_kernel_config(self, kernel, config):
+        _check(_lib.mol_plan_set_kernel_config(self._h, int(kernel), int(config)))
+
+    def tune_key(self, kernel):
+        buf = ctypes.create_string_buffer(256)
+        _check(_lib.mol_plan_tune_key(self._h, int(kernel), buf, 256))
+        return buf.value.decode()
 
     def apply(self, op, x, out, stream=None):
         code = OPS[op] if isinstance(op, str) else int(op)
