@@ -11,20 +11,19 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmolt.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["molt_sweep_%s%s_n%d.hip" % (k, t, n) for k in ("x", "s") for t in ("32", "64")
-           for n in (4, 16)] + ["molt_kernels.hip", "molt_plan.cpp", "molt_masked.cpp", "molt_seg.hip"]
+SOURCES = (["molt_sweep_%s%s_n%d.hip" % (k, t, n) for k in ("x", "s") for t in ("32", "64")
+            for n in (4, 16)]
+           + ["molt_sweep_p%s_p%d.hip" % (t, n) for t in ("32", "64") for n in (1, 2, 4)]
+           + ["molt_kernels.hip", "molt_plan.cpp", "molt_masked.cpp", "molt_seg.hip"])
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed-FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
 
-EXTRA = os.environ.get("MOLT_EXTRA_FLAGS", "").split()
-
-
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *EXTRA, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -56,8 +56,12 @@ hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, boo
                         hipStream_t st);
 
 // Per-direction launch configuration chosen by the plan: cfg[0] = variant id.
-int default_config(const Geom &g, int dir, bool fp64, int ns, int no, int *cfg);
-bool config_valid(const Geom &g, int dir, bool fp64, int ns, int no, const int *cfg);
+// Strided sweeps: ids below config_count_tiled() are the tile kernel, the
+// rest the pipelined strip kernel.
+int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
+                   int *cfg);
+bool config_valid(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
+                  const int *cfg);
 int config_count(int dir);
 
 // Elementwise a*x + b*y -> z on n values (state conversion for the increment form).

@@ -93,8 +93,6 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
             return small ? dispatch_x_f64_n4(k, nlines, nsno, cfg[0], st)
                          : dispatch_x_f64_n16(k, nlines, nsno, cfg[0], st);
     }
-    const SCfg c = kSCfg[cfg[0]];
-    const int WS = c.S * c.W;
     k.nlines = g.n[0];
     if (dir == 1) {
         k.ls = g.n[0];
@@ -113,12 +111,38 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
         k.pd1 = g.dirichlet[0];
         k.pd2 = g.dirichlet[1];
     }
-    k.ntiles = (int)((dc.n + WS - 1) / WS);
     k.halo = dc.halo;
-    k.nblocks = (int64_t)k.ntiles * ((g.n[0] + 63) / 64) * k.nouter;
+    const int64_t ncg = (g.n[0] + 63) / 64;
+    const bool small = op.nf <= 4;
+    if (cfg[0] >= NSCFG) {
+        // pipelined strips
+        const PCfg c = kPCfg[cfg[0] - NSCFG];
+        const int64_t WS = (int64_t)c.S * c.W;
+        const int64_t Tt = (dc.n + WS - 1) / WS;
+        int64_t ns_ = (c.target + ncg * k.nouter - 1) / (ncg * k.nouter);
+        if (ns_ > Tt / 2) ns_ = Tt / 2;
+        if (ns_ < 1) ns_ = 1;
+        k.ntiles = (int)ns_;
+        k.nblocks = ns_ * ncg * k.nouter;
+        k.dS = (T)exp(-dc.nu * c.S);
+        k.dBlk = k.dS;
+        const int id = cfg[0] - NSCFG;
+        if constexpr (sizeof(T) == 4) {
+            if (op.nf == 1) return dispatch_p_f32_p1(k, nsno, id, st);
+            if (op.nf == 2) return dispatch_p_f32_p2(k, nsno, id, st);
+            return dispatch_p_f32_p4(k, nsno, id, st);
+        } else {
+            if (op.nf == 1) return dispatch_p_f64_p1(k, nsno, id, st);
+            if (op.nf == 2) return dispatch_p_f64_p2(k, nsno, id, st);
+            return dispatch_p_f64_p4(k, nsno, id, st);
+        }
+    }
+    const SCfg c = kSCfg[cfg[0]];
+    const int WS = c.S * c.W;
+    k.ntiles = (int)((dc.n + WS - 1) / WS);
+    k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
     k.dS = (T)exp(-dc.nu * c.S);
     k.dBlk = k.dS;
-    const bool small = op.nf <= 4;
     if constexpr (sizeof(T) == 4)
         return small ? dispatch_s_f32_n4(k, nsno, cfg[0], st) : dispatch_s_f32_n16(k, nsno, cfg[0], st);
     else
@@ -127,7 +151,8 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
 
 }  // namespace
 
-bool config_valid(const Geom &g, int dir, bool fp64, int ns, int no, const int *cfg)
+bool config_valid(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
+                  const int *cfg)
 {
     const size_t es = fp64 ? 8 : 4;
     if (!((ns == 1 && (no == 1 || no == 2)) || (ns == 2 && (no == 2 || no == 3)))) return false;
@@ -140,11 +165,24 @@ bool config_valid(const Geom &g, int dir, bool fp64, int ns, int no, const int *
         if (lds > (size_t)max_lds()) return false;
         return true;
     }
-    if (cfg[0] < 0 || cfg[0] >= NSCFG) return false;
+    if (cfg[0] < 0 || cfg[0] >= NSCFG + NPCFG) return false;
+    if (cfg[0] >= NSCFG) {
+        // pipelined strips: at most 4 fields, sub-tiles at least as tall as
+        // the halo and lines of at least two sub-tiles per strip
+        const PCfg c = kPCfg[cfg[0] - NSCFG];
+        const int64_t WS = (int64_t)c.S * c.W;
+        if (nf < 1 || nf > 4) return false;
+        if (dc.halo > WS) return false;
+        if (dc.n < 2 * WS) return false;
+        // 32-bit buffer offsets over the rows of a column group
+        const int64_t ls = dir == 1 ? g.n[0] : g.n[0] * g.n[1];
+        if ((dc.n + 2 * WS + 8) * ls * (int64_t)es + 64 * (int64_t)es >= ((int64_t)1 << 31)) return false;
+    }
     return true;
 }
 
-int default_config(const Geom &g, int dir, bool fp64, int ns, int no, int *cfg)
+int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
+                   int *cfg)
 {
     if (dir == 0) {
         const int64_t n = g.n[0];
@@ -157,26 +195,33 @@ int default_config(const Geom &g, int dir, bool fp64, int ns, int no, int *cfg)
         for (int i = 0; i < cnt; ++i) {
             cfg[0] = ord[i];
             const XCfg c = kXCfg[cfg[0]];
-            if (64 * c.WPL * c.S >= n && config_valid(g, dir, fp64, ns, no, cfg)) return 0;
+            if (64 * c.WPL * c.S >= n && config_valid(g, dc, dir, fp64, nf, ns, no, cfg)) return 0;
         }
         return -1;
     }
-    // strided: prefer tall tiles (16 waves x 16 nodes) for FP32 single sweeps,
-    // shorter lanes when more registers are live
+    // strided: the pipelined strip kernel for one swept combination, else
+    // tall tiles (16 waves x 16 nodes) for FP32 single sweeps, shorter lanes
+    // when more registers are live
+    if (ns == 1) {
+        // only when the strips give enough workgroups to fill the chip
+        cfg[0] = NSCFG + (fp64 ? 2 : 0);     // {8,16,256} FP32, {8,8,512} FP64
+        const PCfg c = kPCfg[cfg[0] - NSCFG];
+        const int64_t tiles = (dc.n + (int64_t)c.S * c.W - 1) / ((int64_t)c.S * c.W);
+        const int64_t groups = ((g.n[0] + 63) / 64) * (dir == 1 ? g.n[2] : g.n[1]);
+        if (groups * (tiles / 2) >= 256 && config_valid(g, dc, dir, fp64, nf, ns, no, cfg)) return 0;
+    }
     const int regs = (2 * ns + no) * (fp64 ? 2 : 1);
     cfg[0] = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
-    return config_valid(g, dir, fp64, ns, no, cfg) ? 0 : -1;
+    return config_valid(g, dc, dir, fp64, nf, ns, no, cfg) ? 0 : -1;
 }
 
-int config_count(int dir) { return dir == 0 ? NXCFG : NSCFG; }
-
-int strided_tile_nodes(int cfgid) { return kSCfg[cfgid].S * kSCfg[cfgid].W; }
+int config_count(int dir) { return dir == 0 ? NXCFG : NSCFG + NPCFG; }
 
 hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
                         const void *const *fptr, void *const *optr, const int *cfg,
                         hipStream_t st)
 {
-    if (!config_valid(g, op.dir, fp64, op.ns, op.no, cfg)) return hipErrorInvalidValue;
+    if (!config_valid(g, dc, op.dir, fp64, op.nf, op.ns, op.no, cfg)) return hipErrorInvalidValue;
     return fp64 ? launch_t<double>(op, g, dc, fptr, optr, cfg, st)
                 : launch_t<float>(op, g, dc, fptr, optr, cfg, st);
 }

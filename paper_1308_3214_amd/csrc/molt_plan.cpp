@@ -171,34 +171,6 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
             err = "internal: launch shape";
             return false;
         }
-        // does the preferred config exist? else split two combos into two launches
-        int cfg[2] = {0, 0};
-        if (!pl.masked && default_config(pl.geom, dir, pl.fp64, ns, no, cfg) != 0) {
-            if (ns == 2) {
-                std::vector<OutSpec> o0, o1;
-                for (const OutSpec &o : outs) {
-                    const bool u0 = o.dc[0] != 0.0, u1 = o.dc[1] != 0.0;
-                    if (u0 && u1) {
-                        err = "internal: cannot split a launch whose output needs both sweeps";
-                        return false;
-                    }
-                    OutSpec t = o;
-                    if (u1) { t.dc[0] = t.dc[1]; t.dc[1] = 0; o1.push_back(t); }
-                    else o0.push_back(t);
-                }
-                bool ok = true;
-                if (!o0.empty()) ok = ok && emit(prog, dir, {combos[0]}, o0, proj);
-                if (!o1.empty()) ok = ok && emit(prog, dir, {combos[1]}, o1, proj);
-                return ok;
-            }
-            if (no > 1) {
-                bool ok = true;
-                for (const OutSpec &o : outs) ok = ok && emit(prog, dir, combos, {o}, proj);
-                return ok;
-            }
-            err = "no kernel configuration fits this line length";
-            return false;
-        }
         if (chain_buf >= 0 && dir != 0) {
             err = "internal: chained sweeps are x sweeps";
             return false;
@@ -236,11 +208,42 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
         }
         op.nf = (int)fields.size();
         for (int i = 0; i < op.nf; ++i) op.f[i] = fields[i];
+
+        // does a configuration exist? else split two combos into two launches
+        int cfg[2] = {0, 0};
+        if (!pl.masked && default_config(pl.geom, pl.dc[dir], dir, pl.fp64, op.nf, ns, no, cfg) != 0) {
+            if (ns == 2) {
+                std::vector<OutSpec> o0, o1;
+                for (const OutSpec &o : outs) {
+                    const bool u0 = o.dc[0] != 0.0, u1 = o.dc[1] != 0.0;
+                    if (u0 && u1) {
+                        err = "internal: cannot split a launch whose output needs both sweeps";
+                        return false;
+                    }
+                    OutSpec t = o;
+                    if (u1) { t.dc[0] = t.dc[1]; t.dc[1] = 0; o1.push_back(t); }
+                    else o0.push_back(t);
+                }
+                bool ok = true;
+                if (!o0.empty()) ok = ok && emit(prog, dir, {combos[0]}, o0, proj);
+                if (!o1.empty()) ok = ok && emit(prog, dir, {combos[1]}, o1, proj);
+                return ok;
+            }
+            if (no > 1) {
+                bool ok = true;
+                for (const OutSpec &o : outs) ok = ok && emit(prog, dir, combos, {o}, proj);
+                return ok;
+            }
+            err = "no kernel configuration fits this line length";
+            return false;
+        }
         if (!pl.masked) {
             const std::string key = tune_op_key(op);
             for (const auto &t : pl.tuned) {
                 int c[2] = {t.second, 0};
-                if (t.first == key && config_valid(pl.geom, dir, pl.fp64, ns, no, c)) cfg[0] = t.second;
+                if (t.first == key &&
+                    config_valid(pl.geom, pl.dc[dir], dir, pl.fp64, op.nf, ns, no, c))
+                    cfg[0] = t.second;
             }
         }
         ProgOp po;
@@ -955,7 +958,8 @@ mol_status mol_plan_kernel_configs(const mol_plan *pl, int kernel, int *ids, int
     if (!pl->masked) {
         for (int c = 0; c < config_count(op.dir); ++c) {
             int cf[2] = {c, 0};
-            if (!config_valid(pl->geom, op.dir, pl->fp64, op.ns, op.no, cf)) continue;
+            if (!config_valid(pl->geom, pl->dc[op.dir], op.dir, pl->fp64, op.nf, op.ns, op.no, cf))
+                continue;
             if (ids && cnt < max) ids[cnt] = c;
             ++cnt;
         }
@@ -973,7 +977,7 @@ mol_status mol_plan_set_kernel_config(mol_plan *pl, int kernel, int config)
     if (kernel < 0 || kernel >= (int)sp.size()) return fail(MOL_E_INVALID, "kernel index out of range");
     const SweepOp ref = sp[kernel].op;
     int cf[2] = {config, 0};
-    if (!config_valid(pl->geom, ref.dir, pl->fp64, ref.ns, ref.no, cf))
+    if (!config_valid(pl->geom, pl->dc[ref.dir], ref.dir, pl->fp64, ref.nf, ref.ns, ref.no, cf))
         return fail(MOL_E_INVALID, "configuration not valid for this kernel");
     const std::string key = tune_op_key(ref);
     for (Program *pr : {&pl->step, &pl->start, &pl->inc_step, &pl->solve_pro, &pl->solve_step,

@@ -105,7 +105,6 @@ std::string tune_op_key(const SweepOp &op);
 std::vector<OutSpec> finals(const std::vector<FinalOut> &fo, const Lin &rhs_elem, double rhs_dcoef);
 double stage_c(int p, int m, double beta);
 double A_p(int p, double beta);
-int strided_tile_nodes(int cfgid);
 
 // masked (embedded boundary) plans
 bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo);

@@ -141,6 +141,39 @@ __device__ __forceinline__ const T *zero_row()
     return reinterpret_cast<const T *>(kZeroRow);
 }
 
+// Raw buffer access: a 128-bit resource (base, size in bytes) and a 32-bit
+// per-lane byte offset.  The hardware range check on that offset returns 0 for
+// reads beyond the resource (negative offsets included) and drops such writes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
+}
+
 // e^{-x} for x >= 0 in the kernel's precision: FP32 kernels use the hardware
 // base-2 exponential (about 1 ulp), FP64 kernels the FP64 library exp.
 template <typename T>
@@ -949,6 +982,353 @@ k_sweep_s(const KArgs<T> a)
 }
 
 // ---------------------------------------------------------------------------
+// pipelined strided sweep (y or z): a workgroup walks a strip of R sub-tiles
+// of WS = W*S rows down 64 columns
+// ---------------------------------------------------------------------------
+// The forward carry entering a sub-tile is exact (the strip is walked in
+// order).  The backward carry entering sub-tile t is the backward aggregate of
+// sub-tile t+1, whose loads and local recurrences run one step ahead; what
+// enters t+1 from below reaches t damped by d^WS <= d^K, below the rounding of
+// the result (the host requires WS >= K).  Only the two strip ends take the
+// decay-bounded halo sums.  The cross terms of the Dirichlet closure (weight
+// e^{-nu(n-1)}) are dropped and the A (B) term is applied only within the
+// first (last) sub-tiles: the host requires n >= 2 WS >= 2 K, where both are
+// below the rounding as well.  NFP fields are loaded per sub-tile (op.nf <= NFP;
+// missing fields read the zero row with zero coefficients).
+template <typename T, int S, int NS, int NO>
+struct SubTile {
+    T sum[NS][S];
+    T ev[NO][S];
+    T aL[NS], aR[NS], eLM[NS];
+};
+
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFP>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_p(const KArgs<T> a)
+{
+    constexpr int WS = W * S;
+    constexpr int HB = 4;                        // halo rows per wave and round
+    __shared__ T agg[3][2][NS][W][64];           // aL, aR of every wave, 3 sub-tiles in flight
+    __shared__ T endv[NS][64];                   // E^L_M of each column
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nstrips = a.ntiles;
+    const int64_t L = blockIdx.x;
+    const int strip = (int)(L % nstrips);
+    const int64_t rest = L / nstrips;
+    const int64_t ncg = (a.nlines + 63) / 64;
+    const int64_t cg = rest % ncg;
+    const int64_t outer = rest / ncg;
+    const int col = (int)(cg * 64) + lane;
+    const bool active = col < a.nlines;
+    const int n = (int)a.n, M = n - 1;
+    const int64_t ls = a.ls;
+    const int64_t blk = cg * 64 + outer * a.os;
+    const unsigned lo = active ? (unsigned)lane : 0u;
+    constexpr bool per = PER;
+    constexpr bool dir_end = !PER;
+    const T d = a.d, g = a.g, w2 = a.w2, gw = a.gw, dS = a.dS;
+    const int K = a.halo;
+
+    // sub-tiles [t0, t0 + R) of the line belong to this strip
+    const int Tt = (n + WS - 1) / WS;
+    const int base = Tt / nstrips, extra = Tt % nstrips;
+    const int t0 = strip * base + (strip < extra ? strip : extra);
+    const int R = base + (strip < extra ? 1 : 0);
+    const int s0 = t0 * WS;
+    const int s1 = ((t0 + R) * WS < n) ? (t0 + R) * WS : n;
+    const bool hb_top = per || s0 > 0;
+    const bool hb_bot = per || s1 < n;
+
+    // Fields through buffer resources over the n rows of this column group
+    // (the host keeps every row offset used here, n + 2 WS + 8 rows, below
+    // 2^31 bytes): a row outside the line reads 0 from the range check, a
+    // missing field (c >= nf) has an empty resource.
+    const int rowb = (int)(ls * (int64_t)sizeof(T));
+    const int lineb = n * rowb;
+    const int vl = (int)lo * (int)sizeof(T);
+    __amdgpu_buffer_rsrc_t rsf[NFP];
+#pragma unroll
+    for (int c = 0; c < NFP; ++c)
+        rsf[c] = make_rsrc(c < a.nf ? a.f[c] + blk : a.f[0] + blk, c < a.nf ? lineb : 0);
+    // node p as read: periodic lines wrap once (|p| stays below 2n)
+    auto wrap = [&](int p) -> int {
+        if (per) {
+            if (p < 0) p += n;
+            if (p >= n) p -= n;
+        }
+        return p;
+    };
+
+    // raw loads of a sub-tile ahead: nodes p0-1 .. p0+S of this wave
+    T xr[NFP][S + 2];
+    auto issue = [&](int t) {
+        const int p0 = s0 + t * WS + wave * S;
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            const int off = vl + wrap(p0 - 1 + j) * rowb;
+#pragma unroll
+            for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(rsf[c], off);
+        }
+    };
+    // swept combinations, elementwise parts and local recurrences of sub-tile t
+    auto combine = [&](int t, SubTile<T, S, NS, NO> &st) {
+        const int p0 = s0 + t * WS + wave * S;
+        T v[NS][S + 2];
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                T x = T(0);
+#pragma unroll
+                for (int c = 0; c < NFP; ++c) x += a.mS[k][c] * xr[c][j];
+                v[k][j] = x;
+            }
+            if (j >= 1 && j <= S) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    T x = T(0);
+#pragma unroll
+                    for (int c = 0; c < NFP; ++c) x += a.mOF[o][c] * xr[c][j];
+                    st.ev[o][j - 1] = x;
+                }
+            }
+        }
+        if (dir_end) {
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j) {
+                const int p = p0 - 1 + j;
+                if (p == 0 || p == M) {
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) v[k][j] = T(0);
+                }
+            }
+        }
+        const int jm = M - p0;
+        const bool slow = per && (p0 + S - 1 > M);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (PER && slow) {
+                seg_recur<T, S>(v[k], p0, M, false, d, g, w2, st.sum[k], st.aL[k], st.aR[k], st.eLM[k]);
+            } else {
+                seg_recur_fast<T, S>(v[k], d, gw, w2, st.sum[k], st.aL[k], st.aR[k]);
+                st.eLM[k] = st.aL[k];
+                if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
+                    T vM1 = T(0);
+#pragma unroll
+                    for (int j = 0; j < S + 2; ++j)
+                        if (j == jm) vM1 = v[k][j];            // node M-1
+                    seg_fix_dirichlet<T, S>(p0, M, v[k][2], vM1, d, w2, st.sum[k], st.aL[k], st.aR[k],
+                                            st.eLM[k]);
+                }
+            }
+            agg[t % 3][0][k][wave][lane] = st.aL[k];
+            agg[t % 3][1][k][wave][lane] = st.aR[k];
+        }
+    };
+
+    SubTile<T, S, NS, NO> cur, nxt;
+    issue(0);
+
+    // ---- halo sums at the strip ends (cooperative over all waves) ----
+    T ctop[NS], cbs[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        ctop[k] = T(0);
+        cbs[k] = T(0);
+    }
+    if (hb_top || hb_bot) {
+        const int q = (K + W - 1) / W;
+        const int k0 = wave * q;
+        const int k1 = (k0 + q < K) ? k0 + q : K;
+        T st_[NS], sb_[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            st_[k] = T(0);
+            sb_[k] = T(0);
+        }
+        T pw = expneg<T>(a.nu * (double)k0);
+        for (int kb = k0; kb < k1; kb += HB) {
+            // top: E^L forcing at rows s0-1-kk needs rows s0-kb-i, i = 0..HB+1;
+            // bottom: E^R forcing at rows s1+kk needs rows s1+kb-1+i
+            T xt[NFP][HB + 2], xb[NFP][HB + 2];
+#pragma unroll
+            for (int i = 0; i < HB + 2; ++i) {
+                // a side without halo reads beyond the resource (0)
+                const int ot = hb_top ? vl + wrap(s0 - kb - i) * rowb : -16;
+                const int ob = hb_bot ? vl + wrap(s1 + kb - 1 + i) * rowb : -16;
+#pragma unroll
+                for (int c = 0; c < NFP; ++c) {
+                    xt[c][i] = buf_load<T>(rsf[c], ot);
+                    xb[c][i] = buf_load<T>(rsf[c], ob);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                T ht[HB + 2], hv[HB + 2];
+#pragma unroll
+                for (int i = 0; i < HB + 2; ++i) {
+                    T x = T(0), y = T(0);
+#pragma unroll
+                    for (int c = 0; c < NFP; ++c) {
+                        x += a.mS[k][c] * xt[c][i];
+                        y += a.mS[k][c] * xb[c][i];
+                    }
+                    // Dirichlet end rows read as 0
+                    const int pt = s0 - kb - i, pb = s1 + kb - 1 + i;
+                    ht[i] = (dir_end && (pt == 0 || pt == M)) ? T(0) : x;
+                    hv[i] = (dir_end && (pb == 0 || pb == M)) ? T(0) : y;
+                }
+                T pk = pw;
+#pragma unroll
+                for (int i = 0; i < HB; ++i) {
+                    const int kk = kb + i;
+                    if (kk < k1) {
+                        int rt = s0 - 1 - kk, rb = s1 + kk;
+                        if (per) {
+                            if (rt < 0) rt += n;
+                            if (rb >= n) rb -= n;
+                        }
+                        st_[k] += pk * force_L(ht[i + 2], ht[i + 1], ht[i], rt, M, dir_end, g, w2);
+                        sb_[k] += pk * force_R(hv[i], hv[i + 1], hv[i + 2], rb, M, dir_end, g, w2);
+                    }
+                    pk *= d;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < HB; ++i) pw *= d;
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            agg[0][0][k][wave][lane] = st_[k];
+            agg[0][1][k][wave][lane] = sb_[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T x = T(0), y = T(0);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                x += agg[0][0][k][w][lane];
+                y += agg[0][1][k][w][lane];
+            }
+            ctop[k] = hb_top ? x : T(0);
+            cbs[k] = hb_bot ? y : T(0);
+        }
+        __syncthreads();
+    }
+
+    combine(0, cur);
+    if (R > 1) issue(1);
+
+    bool bline = false;
+    if (a.proj)
+        bline = (a.pd1 && (col == 0 || col == a.pn1 - 1)) ||
+                (a.pd2 && (outer == 0 || outer == a.pn2 - 1));
+    __amdgpu_buffer_rsrc_t rso[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) rso[o] = make_rsrc(a.o[o] + blk, lineb);
+
+    for (int t = 0; t < R; ++t) {
+        const bool last = (t + 1 == R);
+        if (!last) {
+            combine(t + 1, nxt);
+            if (t + 2 < R) issue(t + 2);
+        }
+        __syncthreads();
+
+        // ---- finish sub-tile t ----
+        const int st0 = s0 + t * WS;
+        const int p0 = st0 + wave * S;
+        const bool botAsB = per && last && s1 == n;
+        T cL[NS], cR[NS], ctopn[NS], er0[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T c = ctop[k];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                if (w == wave) cL[k] = c;
+                c = dS * c + agg[t % 3][0][k][w][lane];
+            }
+            ctopn[k] = c;
+            T cb;
+            if (!last) {
+                T ag = T(0);
+#pragma unroll
+                for (int w = W - 1; w >= 0; --w) ag = dS * ag + agg[(t + 1) % 3][1][k][w][lane];
+                if (t + 2 == R) ag += expneg<T>(a.nu * (double)(s1 - (st0 + WS))) * cbs[k];
+                cb = ag;
+            } else {
+                cb = botAsB ? T(0) : cbs[k];
+            }
+            T cr = cb;
+#pragma unroll
+            for (int w = W - 1; w >= 0; --w) {
+                if (w == wave) cR[k] = cr;
+                cr = dS * cr + agg[t % 3][1][k][w][lane];
+            }
+            er0[k] = cr;                                 // E^R at node st0
+        }
+        double A[NS], B[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            A[k] = (dir_end && st0 == 0) ? a.K00 * (double)er0[k] : 0.0;
+            B[k] = botAsB ? (double)d * (double)cbs[k] : 0.0;
+        }
+        // E^L_M when node M lies in this sub-tile or the next one
+        const bool mhere = dir_end && M < st0 + WS;
+        const bool mnext = dir_end && !last && M >= st0 + WS && M < st0 + 2 * WS;
+        if (mhere || mnext) {
+            if (mhere && wave == (M - st0) / S) {
+                const int jmw = M - p0;
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+                    endv[k][lane] = cur.eLM[k] + expneg<T>(a.nu * (double)(jmw + 1)) * cL[k];
+            }
+            if (mnext && wave == (M - st0 - WS) / S) {
+                const int jmw = M - (p0 + WS);
+#pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    T c = ctopn[k];
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        if (w < wave) c = dS * c + agg[(t + 1) % 3][0][k][w][lane];
+                    endv[k][lane] = nxt.eLM[k] + expneg<T>(a.nu * (double)(jmw + 1)) * c;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NS; ++k) B[k] = a.K11 * (double)endv[k][lane];
+        }
+        const bool slow = per && (p0 + S - 1 > M);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (PER && slow) seg_close<T, S>(cur.sum[k], cL[k], cR[k], A[k], B[k], p0, M, a.nu, d, false);
+            else seg_close_fast<T, S>(cur.sum[k], cL[k], cR[k], A[k], B[k], p0, M, a.nu, d, a.dpow, dir_end);
+        }
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const int p = p0 + j;
+                if (p > M) break;
+                const bool z = a.proj && (bline || (dir_end && (p == 0 || p == M)));
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    T r = cur.ev[o][j];
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * cur.sum[k][j];
+                    buf_store<T>(z ? T(0) : r, rso[o], vl + p * rowb);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) ctop[k] = ctopn[k];
+        cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // elementwise z = a x + b y
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -972,6 +1352,11 @@ constexpr XCfg kXCfg[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8,
 constexpr SCfg kSCfg[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {4, 16}, {16, 4}};
 constexpr int NXCFG = sizeof(kXCfg) / sizeof(kXCfg[0]);
 constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);
+// pipelined strided configurations: S, W and the number of workgroups aimed at
+// (strips per line = target / column groups, at least 2 sub-tiles per strip)
+struct PCfg { int S, W, target; };
+constexpr PCfg kPCfg[] = {{8, 16, 256}, {16, 8, 512}, {8, 8, 512}, {8, 16, 512}, {16, 8, 256}, {4, 16, 256}};
+constexpr int NPCFG = sizeof(kPCfg) / sizeof(kPCfg[0]);
 
 // one per (dtype, direction class): launch a prepared KArgs with config id
 // `id` and (swept, output) counts encoded as nsno = 10*ns + no
@@ -983,6 +1368,13 @@ hipError_t dispatch_s_f64_n4(const KArgs<double> &k, int nsno, int id, hipStream
 hipError_t dispatch_x_f32_n16(const KArgs<float> &k, int64_t nlines, int nsno, int id, hipStream_t st);
 hipError_t dispatch_x_f64_n16(const KArgs<double> &k, int64_t nlines, int nsno, int id, hipStream_t st);
 hipError_t dispatch_s_f32_n16(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+// pipelined strided kernels: _p<NFP>, fields loaded per sub-tile (op.nf <= NFP)
+hipError_t dispatch_p_f32_p1(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_p_f32_p2(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_p_f32_p4(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_p_f64_p1(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_p_f64_p2(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_p_f64_p4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
 hipError_t dispatch_s_f64_n16(const KArgs<double> &k, int nsno, int id, hipStream_t st);
 
 }  // namespace molt

@@ -1,0 +1,5 @@
+// Pipelined strided-sweep kernels, double, 2 field(s) per sub-tile.
+#define MOLT_T double
+#define MOLT_TAG f64
+#define MOLT_NFP 2
+#include "molt_sweep_p.inc"

@@ -214,3 +214,59 @@ def test_split_tiles_long_columns(torch_cuda, molt, oracle_mod, dtype):
         plan.apply("rhs", vd, o)
         torch.cuda.synchronize()
         check("rhs 2100 rows cfl=%g" % cfl, host(o), pb.rhs(v, 2, plan.info["beta"]), dtype)
+
+
+# long y lines (several strips of the pipelined strided kernel, ragged last
+# sub-tile, periodic wrap) and one long z line case
+STRIP_CASES = [
+    ((1100, 70), 1.0 / 1099, 0, 2.0),
+    ((1100, 70), (1.0 / 70, 1.0 / 1100), (0, 1), 2.0),
+    ((1024, 100), 1.0 / 1024, 1, 3.0),
+    ((700, 130), 1.0 / 699, 0, 4.0),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(STRIP_CASES)))
+def test_every_strided_config(torch_cuda, molt, oracle_mod, case, dtype):
+    # every valid configuration of every strided kernel of the fused solve
+    # step, three steps against the 80-bit oracle
+    torch = torch_cuda
+    shape, h, bc, cfl = STRIP_CASES[case]
+    plan = molt.Plan(shape, h, bc, P=2, cfl=cfl, dtype=dtype)
+    pb = oracle_mod.Problem(shape, h, bc, plan.info["alpha"], precision="ld")
+    u0 = W.random_field(shape, seed=20 + case, dirichlet_axes=_dirichlet_axes(shape, bc))
+    u1 = pb.start(u0, 2, plan.info["beta"])
+    a, b = pb.run(u0, u1, 3, 2, plan.info["beta"])
+    tol = TOL[dtype] * (1 if dtype == "f64" else 2)
+    nk = plan.info["kernels_per_step"]
+    tried = 0
+    for k in range(nk):
+        ids, cur = plan.kernel_configs(k)
+        for cfg in ids:
+            plan.set_kernel_config(k, cfg)
+            da, db = dev(torch, u0, dtype), dev(torch, u1, dtype)
+            plan.solve(da, db, 3)
+            torch.cuda.synchronize()
+            check("strips %s kernel %d cfg %d" % (shape, k, cfg), host(db), b, dtype, tol)
+            tried += 1
+        plan.set_kernel_config(k, cur)
+    assert tried > 0
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_long_z_lines(torch_cuda, molt, oracle_mod, dtype):
+    torch = torch_cuda
+    shape, h = (600, 12, 20), (1.0 / 19, 1.0 / 11, 1.0 / 599)     # z lines of 600 nodes
+    plan = molt.Plan(shape, h, 0, P=2, cfl=2.0, dtype=dtype)
+    pb = oracle_mod.Problem(shape, h, 0, plan.info["alpha"])
+    v = W.random_field(shape, 5, (0, 1, 2))
+    vd = dev(torch, v, dtype)
+    o = torch.empty_like(vd)
+    plan.apply("d_z", vd, o)
+    torch.cuda.synchronize()
+    check("D_z 600 planes", host(o), pb.Dg(v, 2), dtype)
+    plan.apply("rhs", vd, o)
+    torch.cuda.synchronize()
+    check("rhs 600 planes", host(o), pb.rhs(v, 2, plan.info["beta"]), dtype)
