@@ -68,16 +68,44 @@ int config_count(int dir);
 hipError_t launch_axpby(bool fp64, int64_t n, double a, const void *x, double b, const void *y,
                         void *z, hipStream_t st);
 
-// ---- embedded boundary (2D masked) line objects ----
+// ---- embedded boundary (2D masked) line objects (Sec. 4.3) ----
+// One record per line object: the inside nodes base + j*pstride, j < m, of one
+// grid line, closed by boundary points theta_lo*h before the first and
+// theta_hi*h after the last inside node.  The FP64 constants give the forcing
+// of the end cells (E = I - v/2 form), the end values I^R and I^L at the two
+// boundary points, and the 2x2 closure:
+//   first node   F^L = AL0 v0 + AL1 v1,  F^R = AR0 v0 + AR1 v1
+//   last node    F^L = BL0 v_{m-2} + BL1 v_{m-1},  F^R = BR0 v_{m-2} + BR1 v_{m-1}
+//   (m = 1: F^L = AL0 v0, F^R = AR0 v0)
+//   I^R(a) = EA E^R_0 + QA v0,  I^L(b) = EB E^L_{m-1} + QB v_{m-1}
+//   A = (-I^R(a) + MU I^L(b)) INV,  B = (-I^L(b) + MU I^R(a)) INV
+//   D v_j = -(E^L_j + E^R_j + A EA d^j + B EB d^{m-1-j})
+enum {
+    SEG_AL0, SEG_AL1, SEG_AR0, SEG_AR1, SEG_EA, SEG_QA,
+    SEG_BL0, SEG_BL1, SEG_BR0, SEG_BR1, SEG_EB, SEG_QB,
+    SEG_MU, SEG_INV, NSEGC
+};
+struct SegRec {
+    int64_t base;   // element offset of the first inside node
+    int32_t m;      // inside nodes, >= 1
+    int32_t cls;    // length class
+    double c[NSEGC];
+};
+// length classes: one workgroup of 64*WPL lanes x S nodes per line object
+constexpr int NSEGCLS = 6;
+int seg_class_capacity(int cls);
 struct SegTable {
     int64_t nseg = 0;
-    int64_t *d_idx = nullptr;     // [nseg][4]: line, first inside node, count, pad
-    double *d_coef = nullptr;     // [nseg][NSEGCOEF] FP64 per-segment constants
+    int64_t pstride = 1;                  // element stride along the line
+    int64_t cls_begin[NSEGCLS + 1] = {};  // records [cls_begin[c], cls_begin[c+1]) have class c
+    SegRec *d_rec = nullptr;              // device copy
 };
-constexpr int NSEGCOEF = 16;
 
-hipError_t launch_seg_sweep(const SweepOp &op, const Geom &g, int dir, const SegTable &tab,
-                            const DirCoef &dc, bool fp64, const void *const *fptr,
-                            void *const *optr, const unsigned char *d_mask, hipStream_t st);
+// All line objects of one direction (every class), one launch per class.
+hipError_t launch_seg_sweep(const SweepOp &op, const SegTable &tab, const DirCoef &dc, bool fp64,
+                            const void *const *fptr, void *const *optr, hipStream_t st);
+// out[i] = 0 where mask[i] == 0 (outside nodes of a user-visible output)
+hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, void *out,
+                            hipStream_t st);
 
 }  // namespace molt

@@ -690,8 +690,16 @@ hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, co
 
 double program_bytes(const mol_plan_ *pl, const Program &prog)
 {
-    double b = 0;
-    for (const ProgOp &po : prog) b += (double)(po.op.nf + po.op.no + po.op.chain);
+    // fields read and written by every launch; a masked plan moves the
+    // inside nodes only (plus the zero fill of its user-visible outputs)
+    double b = 0, fill = 0;
+    for (const ProgOp &po : prog) {
+        b += (double)(po.op.nf + po.op.no + po.op.chain);
+        if (pl->masked && po.op.proj) fill += (double)po.op.no;
+    }
+    if (pl->masked)
+        return b * (double)pl->unknowns * (double)pl->es +
+               fill * ((double)pl->npts + (double)(pl->npts - pl->unknowns) * (double)pl->es);
     return b * (double)pl->npts * (double)pl->es;
 }
 

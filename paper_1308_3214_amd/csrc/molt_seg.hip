@@ -1,0 +1,348 @@
+// Sweeps over the line objects of an embedded boundary (Sec. 4.3): every
+// maximal run of inside nodes of a grid line, closed by the two boundary
+// points where the line crosses the curve.  One workgroup per line object: the
+// object's nodes are staged through LDS, every lane runs the E = I - v/2
+// recurrences over S consecutive nodes (uniform cells inside, the end cells of
+// widths theta*h through per-object FP64 forcing coefficients), lane and wave
+// carries are scanned exactly (multiplier d^S), and the per-object 2x2 closure
+// enforces L^{-1}v = 0 at the two boundary points.  Outputs follow the same
+// linear prologue / epilogue as the box sweeps (SweepOp).
+#include "molt_sweep.h"
+
+namespace molt {
+namespace {
+
+template <typename T>
+struct SegArgs {
+    const T *f[MAXF];
+    T *o[MAXO];
+    T mS[MAXS][MAXF];
+    T mOF[MAXO][MAXF];
+    T mOD[MAXO][MAXS];
+    int nf;
+    const SegRec *rec;
+    int64_t seg0;        // first record of this launch
+    int64_t pstride;     // element stride along the line
+    T d, g, w2, gw, dS, dBlk;
+    T dpow[33];
+    double nu;
+};
+
+// Forcing of the two recurrences at node p of an object of m inside nodes
+// (vm, v0, vp = values at p-1, p, p+1; outside the object 0).
+template <typename T>
+__device__ __forceinline__ T obj_force_L(T vm, T v0, T vp, int p, int m, const T *cf, T g, T w2)
+{
+    if (p >= m) return T(0);
+    if (m == 1) return cf[SEG_AL0] * v0;
+    if (p == 0) return cf[SEG_AL0] * v0 + cf[SEG_AL1] * vp;
+    if (p == m - 1) return cf[SEG_BL0] * vm + cf[SEG_BL1] * v0;
+    return w2 * ((vp - v0) - (v0 - vm)) - g * (v0 - vm);
+}
+template <typename T>
+__device__ __forceinline__ T obj_force_R(T vm, T v0, T vp, int p, int m, const T *cf, T g, T w2)
+{
+    if (p >= m) return T(0);
+    if (m == 1) return cf[SEG_AR0] * v0;
+    if (p == 0) return cf[SEG_AR0] * v0 + cf[SEG_AR1] * vp;
+    if (p == m - 1) return cf[SEG_BR0] * vm + cf[SEG_BR1] * v0;
+    return w2 * ((vp - v0) - (v0 - vm)) + g * (vp - v0);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void obj_recur(const T (&v)[S + 2], int p0, int m, const T *cf, T d, T g,
+                                          T w2, T (&sum)[S], T &aL, T &aR, T &eLast)
+{
+    T e = T(0);
+    eLast = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        e = d * e + obj_force_L(v[j], v[j + 1], v[j + 2], p, m, cf, g, w2);
+        sum[j] = e;
+        if (p == m - 1) eLast = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        e = d * e + obj_force_R(v[j], v[j + 1], v[j + 2], p0 + j, m, cf, g, w2);
+        sum[j] += e;
+    }
+    aR = e;
+}
+
+template <typename T, int S, int WPL, int NS, int NO>
+__global__ void __launch_bounds__(64 * WPL)
+k_seg_sweep(const SegArgs<T> a)
+{
+    constexpr int NT = 64 * WPL;
+    constexpr int NPAD = NT * (S + 1);
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
+    __shared__ T wtot[2][MAXS][WPL];
+    __shared__ T ends[2][MAXS];
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const SegRec &rec = a.rec[a.seg0 + blockIdx.x];
+    const int m = rec.m;
+    const int64_t base = rec.base;
+    const int64_t ps = a.pstride;
+    T cf[NSEGC];
+#pragma unroll
+    for (int i = 0; i < NSEGC; ++i) cf[i] = (T)rec.c[i];
+    const T d = a.d, g = a.g, w2 = a.w2;
+
+    // ---- loads: node e = i*NT + t (consecutive threads, consecutive nodes) ----
+    T sv[NS][S], ev[NO][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sv[k][i] = T(0);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) ev[o][i] = T(0);
+    }
+    for (int f = 0; f < a.nf; ++f) {
+        const T *src = a.f[f] + base;
+        T x[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int e = i * NT + t;
+            const T val = src[(int64_t)(e < m ? e : 0) * ps];
+            x[i] = (e < m) ? val : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) sv[k][i] += a.mS[k][f] * x[i];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ev[o][i] += a.mOF[o][f] * x[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const int e = i * NT + t;
+        const int slot = (e / S) * (S + 1) + (e % S);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = sv[k][i];
+    }
+    __syncthreads();
+
+    // ---- recurrences over S consecutive nodes per lane ----
+    const int p0 = t * S;
+    const int jm = m - 1 - p0;                       // position of the last node in this lane
+    const bool interior = (p0 >= 1) && (p0 + S - 1 <= m - 2);
+    T sum[NS][S], aL[NS], aR[NS], eLast[NS], v0s[NS], vls[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const T *sk = sm + k * NPAD;
+        T v[S + 2];
+#pragma unroll
+        for (int j = 0; j < S; ++j) v[j + 1] = sk[t * (S + 1) + j];
+        v[0] = (t > 0) ? sk[(t - 1) * (S + 1) + (S - 1)] : T(0);
+        v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
+        if (interior) {
+            seg_recur_fast<T, S>(v, d, a.gw, w2, sum[k], aL[k], aR[k]);
+            eLast[k] = T(0);
+        } else {
+            obj_recur<T, S>(v, p0, m, cf, d, g, w2, sum[k], aL[k], aR[k], eLast[k]);
+        }
+        // end values of the swept data, read before the D values replace them
+        v0s[k] = sk[0];
+        vls[k] = sk[((m - 1) / S) * (S + 1) + ((m - 1) % S)];
+    }
+    T cL[NS], cR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T xl = aL[k], xr = aR[k], mm = a.dS;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const T yl = shfl_up(xl, off);
+            const T yr = shfl_down(xr, off);
+            if (lane >= off) xl += mm * yl;
+            if (lane + off < 64) xr += mm * yr;
+            mm *= mm;
+        }
+        const T exl = shfl_up(xl, 1);
+        const T exr = shfl_down(xr, 1);
+        cL[k] = (lane == 0) ? T(0) : exl;
+        cR[k] = (lane == 63) ? T(0) : exr;
+        if (WPL > 1) {
+            if (lane == 63) wtot[0][k][wave] = xl;
+            if (lane == 0) wtot[1][k][wave] = xr;
+        }
+    }
+    if (WPL > 1) {
+        __syncthreads();
+        const T pl = expneg<T>(a.nu * (double)S * (double)lane);
+        const T pr = expneg<T>(a.nu * (double)S * (double)(63 - lane));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T cw = T(0), cwr = T(0);
+            for (int w = 0; w < wave; ++w) cw = a.dBlk * cw + wtot[0][k][w];
+            for (int w = WPL - 1; w > wave; --w) cwr = a.dBlk * cwr + wtot[1][k][w];
+            cL[k] += pl * cw;
+            cR[k] += pr * cwr;
+        }
+    }
+    // E^R at the first and E^L at the last inside node
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (p0 == 0) ends[0][k] = aR[k] + a.dS * cR[k];
+        if (jm >= 0 && jm < S) ends[1][k] = eLast[k] + expneg<T>(a.nu * (double)(jm + 1)) * cL[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const double IRa = rec.c[SEG_EA] * (double)ends[0][k] + rec.c[SEG_QA] * (double)v0s[k];
+        const double ILb = rec.c[SEG_EB] * (double)ends[1][k] + rec.c[SEG_QB] * (double)vls[k];
+        const double A = (-IRa + rec.c[SEG_MU] * ILb) * rec.c[SEG_INV];
+        const double B = (-ILb + rec.c[SEG_MU] * IRa) * rec.c[SEG_INV];
+        seg_close_fast<T, S>(sum[k], cL[k], cR[k], A * rec.c[SEG_EA], B * rec.c[SEG_EB], p0, m - 1,
+                             a.nu, d, a.dpow, false);
+    }
+    __syncthreads();                                 // every read of the swept data is done
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T *sk = sm + k * NPAD;
+#pragma unroll
+        for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
+    }
+    __syncthreads();
+
+    // ---- epilogue in the load layout ----
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const int e = i * NT + t;
+        if (e < m) {
+            const int slot = (e / S) * (S + 1) + (e % S);
+            T Dk[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                T r = ev[o][i];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
+                a.o[o][base + (int64_t)e * ps] = r;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_mask_zero(int64_t n, const unsigned char *mask, T *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride)
+        if (!mask[k]) out[k] = T(0);
+}
+
+struct SegCfg { int S, WPL; };
+constexpr SegCfg kSegCfg[NSEGCLS] = {{4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {16, 8}};
+
+template <typename T, int S, int WPL, int NS, int NO>
+hipError_t run_seg(const SegArgs<T> &k, int64_t count, hipStream_t st)
+{
+    const size_t lds = (size_t)NS * 64 * WPL * (S + 1) * sizeof(T);
+    auto fn = k_seg_sweep<T, S, WPL, NS, NO>;
+    if (lds > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)count), dim3(64 * WPL), lds, st, k);
+    return hipGetLastError();
+}
+
+template <typename T, int NS, int NO>
+hipError_t dispatch_seg(const SegArgs<T> &k, int cls, int64_t count, hipStream_t st)
+{
+    switch (cls) {
+    case 0: return run_seg<T, kSegCfg[0].S, kSegCfg[0].WPL, NS, NO>(k, count, st);
+    case 1: return run_seg<T, kSegCfg[1].S, kSegCfg[1].WPL, NS, NO>(k, count, st);
+    case 2: return run_seg<T, kSegCfg[2].S, kSegCfg[2].WPL, NS, NO>(k, count, st);
+    case 3: return run_seg<T, kSegCfg[3].S, kSegCfg[3].WPL, NS, NO>(k, count, st);
+    case 4: return run_seg<T, kSegCfg[4].S, kSegCfg[4].WPL, NS, NO>(k, count, st);
+    case 5: return run_seg<T, kSegCfg[5].S, kSegCfg[5].WPL, NS, NO>(k, count, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t seg_sweep_t(const SweepOp &op, const SegTable &tab, const DirCoef &dc,
+                       const void *const *fptr, void *const *optr, hipStream_t st)
+{
+    SegArgs<T> k{};
+    for (int i = 0; i < MAXF; ++i) k.f[i] = i < op.nf ? static_cast<const T *>(fptr[i]) : nullptr;
+    for (int i = 0; i < MAXO; ++i) k.o[i] = i < op.no ? static_cast<T *>(optr[i]) : nullptr;
+    for (int s = 0; s < MAXS; ++s)
+        for (int f = 0; f < MAXF; ++f) k.mS[s][f] = (T)op.mS[s][f];
+    for (int o = 0; o < MAXO; ++o) {
+        for (int f = 0; f < MAXF; ++f) k.mOF[o][f] = (T)op.mOF[o][f];
+        for (int s = 0; s < MAXS; ++s) k.mOD[o][s] = (T)op.mOD[o][s];
+    }
+    k.nf = op.nf;
+    k.rec = tab.d_rec;
+    k.pstride = tab.pstride;
+    k.d = (T)dc.d;
+    k.g = (T)dc.g;
+    k.w2 = (T)dc.w2;
+    k.gw = (T)(dc.g + dc.w2);
+    for (int j = 0; j < 33; ++j) k.dpow[j] = (T)std::exp(-dc.nu * (double)j);
+    k.nu = dc.nu;
+    const int nsno = op.ns * 10 + op.no;
+    for (int c = 0; c < NSEGCLS; ++c) {
+        const int64_t count = tab.cls_begin[c + 1] - tab.cls_begin[c];
+        if (count <= 0) continue;
+        k.seg0 = tab.cls_begin[c];
+        k.dS = (T)std::exp(-dc.nu * kSegCfg[c].S);
+        k.dBlk = (T)std::exp(-dc.nu * kSegCfg[c].S * 64.0);
+        hipError_t e;
+        switch (nsno) {
+        case 11: e = dispatch_seg<T, 1, 1>(k, c, count, st); break;
+        case 12: e = dispatch_seg<T, 1, 2>(k, c, count, st); break;
+        case 22: e = dispatch_seg<T, 2, 2>(k, c, count, st); break;
+        case 23: e = dispatch_seg<T, 2, 3>(k, c, count, st); break;
+        default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+int seg_class_capacity(int cls)
+{
+    return (cls >= 0 && cls < NSEGCLS) ? 64 * kSegCfg[cls].WPL * kSegCfg[cls].S : 0;
+}
+
+hipError_t launch_seg_sweep(const SweepOp &op, const SegTable &tab, const DirCoef &dc, bool fp64,
+                            const void *const *fptr, void *const *optr, hipStream_t st)
+{
+    if (!((op.ns == 1 && (op.no == 1 || op.no == 2)) || (op.ns == 2 && (op.no == 2 || op.no == 3))))
+        return hipErrorInvalidValue;
+    return fp64 ? seg_sweep_t<double>(op, tab, dc, fptr, optr, st)
+                : seg_sweep_t<float>(op, tab, dc, fptr, optr, st);
+}
+
+hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, void *out,
+                            hipStream_t st)
+{
+    const int bs = 256;
+    int64_t nb = (n + bs - 1) / bs;
+    if (nb > 65536) nb = 65536;
+    if (nb < 1) nb = 1;
+    if (fp64)
+        hipLaunchKernelGGL(k_mask_zero<double>, dim3((unsigned)nb), dim3(bs), 0, st, n, d_mask,
+                           static_cast<double *>(out));
+    else
+        hipLaunchKernelGGL(k_mask_zero<float>, dim3((unsigned)nb), dim3(bs), 0, st, n, d_mask,
+                           static_cast<float *>(out));
+    return hipGetLastError();
+}
+
+}  // namespace molt

@@ -135,10 +135,16 @@ def make_desc(shape, h, bc=DIRICHLET, P=2, c=1.0, dt=None, cfl=None, beta=0.0, d
     keep = []
     if mask is not None:
         m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if nd == 2 and m.shape != shape:
+            raise ValueError("mask shape %s does not match the field shape %s" % (m.shape, shape))
+        if m.size != int(np.prod(shape)):
+            raise ValueError("mask has %d entries for %d nodes" % (m.size, int(np.prod(shape))))
         keep.append(m)
         d.mask = m.ctypes.data
     if cross is not None:
         cr = np.ascontiguousarray(cross, dtype=np.float64)
+        if cr.shape != (4,) + shape:
+            raise ValueError("cross must have shape (4,) + field shape, got %s" % (cr.shape,))
         keep.append(cr)
         d.cross = cr.ctypes.data
     d.P = int(P)

@@ -57,5 +57,20 @@ def test_descriptor_validation_and_workspace(lib):
                                 flags=molt.ALLOW_UNSTABLE) > 0
     assert "beta" in molt.last_error() or True
     # a mask in 3D is not supported
-    m = np.ones((4, 4), np.uint8)
+    m = np.ones((4, 4, 4), np.uint8)
     assert molt.workspace_bytes(shape=(4, 4, 4), h=0.1, P=1, cfl=1.0, mask=m) == 0
+    # a 2D mask: the line-object tables are built on the host (no device)
+    from paper_1308_3214_amd import workloads as W
+    dom, mask, cross = W.star_domain(64, seed=1)
+    w0 = molt.workspace_bytes(shape=(64, 64), h=1 / 63, P=3, cfl=1.5, dtype="f32")
+    wm = molt.workspace_bytes(shape=(64, 64), h=1 / 63, P=3, cfl=1.5, dtype="f32",
+                              mask=mask, cross=cross)
+    assert wm > 0 and wm != w0
+    # the outer ring must lie outside; crossings must lie in (0, 1]
+    bad = mask.copy()
+    bad[0, 5] = 1
+    assert molt.workspace_bytes(shape=(64, 64), h=1 / 63, P=1, cfl=1.0, mask=bad) == 0
+    assert "ring" in molt.last_error()
+    cr = cross.copy()
+    cr[~np.isnan(cr)] = 1.5
+    assert molt.workspace_bytes(shape=(64, 64), h=1 / 63, P=1, cfl=1.0, mask=mask, cross=cr) == 0

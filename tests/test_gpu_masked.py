@@ -1,0 +1,156 @@
+"""GPU parity of the embedded-boundary path (line objects of Sec. 4.3, the
+non-commuting compositions C = L_y^{-1} D_x + L_x^{-1} D_y and
+D = 1 - L_x^{-1} L_y^{-1}) through the C-ABI against the FP64 oracle (single
+operators and steps) and its 80-bit build (runs of several steps).
+Tolerances as for the box path: relative L2 1e-12 (FP64), 1e-5 (FP32)."""
+import numpy as np
+import pytest
+
+from oracle import lines
+from paper_1308_3214_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def molt(torch_cuda):
+    from paper_1308_3214_amd import molt as m
+    return m
+
+
+def dev(torch, a, dtype):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to(device="cuda", dtype=torch.float64 if dtype == "f64" else torch.float32)
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def check(name, got, ref, dtype, tol=None):
+    nb = np.linalg.norm(ref)
+    e = np.linalg.norm(got - ref) / (nb if nb > 0 else 1.0)
+    print("%-44s %s rel L2 = %.3e" % (name, dtype, e))
+    assert np.isfinite(got).all()
+    assert e <= (tol if tol is not None else TOL[dtype]), (name, e)
+
+
+def domain(kind):
+    if kind == "star":
+        dom, mask, cross = W.star_domain(120, seed=2)
+        return mask, cross, 1.0 / 119, 1.5
+    if kind == "ellipse":
+        mask, cross = W.ellipse_domain(80)
+        return mask, cross, 1.0 / 79, 2.0
+    if kind == "long":
+        # rows of 2298 inside nodes, columns of 38: the longer object classes
+        ny, nx = 40, 2300
+        mask = np.zeros((ny, nx), np.uint8)
+        mask[1:-1, 1:-1] = 1
+        mask[10:14, 700:705] = 0           # a hole: objects of unequal lengths
+        return mask, None, 1.0 / (nx - 1), 2.0
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["star", "ellipse", "long"])
+def test_masked_operators(torch_cuda, molt, oracle_mod, kind, dtype):
+    torch = torch_cuda
+    mask, cross, h, cfl = domain(kind)
+    shape = mask.shape
+    segs = lines.segments(mask, cross)
+    v = W.random_field(shape, seed=7) * mask
+    vd = dev(torch, v, dtype)
+    out = torch.empty_like(vd)
+    for P in (1, 2, 3):
+        plan = molt.Plan(shape, h, 0, P=P, cfl=cfl, dtype=dtype, mask=mask, cross=cross)
+        info = plan.info
+        assert tuple(info["segments"]) == (len(segs[0][0]), len(segs[1][0]))
+        pb = oracle_mod.Problem(shape, h, 0, info["alpha"], segments=segs, mask=mask)
+        if P == 2:
+            for ax, nm in ((0, "x"), (1, "y")):
+                plan.apply("linv_" + nm, vd, out)
+                torch.cuda.synchronize()
+                check("%s linv_%s" % (kind, nm), host(out) * mask, pb.linv(v, ax), dtype)
+                plan.apply("d_" + nm, vd, out)
+                torch.cuda.synchronize()
+                check("%s D_%s" % (kind, nm), host(out), pb.Dg(v, ax), dtype)
+            plan.apply("C", vd, out)
+            torch.cuda.synchronize()
+            check("%s C" % kind, host(out), pb.C(v), dtype)
+            plan.apply("D", vd, out)
+            torch.cuda.synchronize()
+            check("%s D" % kind, host(out), pb.D(v), dtype)
+        plan.apply("rhs", vd, out)
+        torch.cuda.synchronize()
+        check("%s rhs P=%d" % (kind, P), host(out), pb.rhs(v, P, info["beta"]), dtype)
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("P", [1, 3])
+def test_masked_steps_and_solve(torch_cuda, molt, oracle_mod, P, dtype):
+    torch = torch_cuda
+    dom, mask, cross = W.star_domain(120, seed=3)
+    h = 1.0 / 119
+    shape = mask.shape
+    segs = lines.segments(mask, cross)
+    plan = molt.Plan(shape, h, 0, P=P, cfl=1.5, dtype=dtype, mask=mask, cross=cross)
+    beta = plan.info["beta"]
+    pb = oracle_mod.Problem(shape, h, 0, plan.info["alpha"], segments=segs, mask=mask)
+    u0 = W.star_pulses(dom, mask, seed=3, npulses=4, sigma=0.05)
+    u1 = pb.start(u0, P, beta)
+    d0 = dev(torch, u0, dtype)
+    o = torch.full_like(d0, 7.0)           # outside nodes must come back as 0
+    plan.start(d0, o)
+    torch.cuda.synchronize()
+    check("star start P=%d" % P, host(o), u1, dtype)
+    assert (host(o)[mask == 0] == 0).all()
+    d1 = dev(torch, u1, dtype)
+    o.fill_(7.0)
+    plan.step(d0, d1, o)
+    torch.cuda.synchronize()
+    check("star step P=%d" % P, host(o), pb.step(u0, u1, P, beta), dtype)
+    # several steps through the captured graph against the 80-bit oracle
+    pl = oracle_mod.Problem(shape, h, 0, plan.info["alpha"], segments=segs, mask=mask,
+                            precision="ld")
+    a, b = pl.run(u0, u1, 12, P, beta)
+    da, db = dev(torch, u0, dtype), dev(torch, u1, dtype)
+    plan.solve(da, db, 12)
+    torch.cuda.synchronize()
+    tol = TOL[dtype] * (1 if dtype == "f64" else 2)
+    check("star solve 12 P=%d prev" % P, host(da), a, dtype, tol)
+    check("star solve 12 P=%d curr" % P, host(db), b, dtype, tol)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_interior_mask_matches_rectangle(torch_cuda, molt, dtype):
+    # crossings on the ring nodes: the line objects are the rectangle's lines
+    torch = torch_cuda
+    ny, nx = 70, 90
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[1:-1, 1:-1] = 1
+    h = (1.0 / (nx - 1), 1.0 / (ny - 1))
+    v = W.random_field((ny, nx), seed=11, dirichlet_axes=(0, 1))
+    vd = dev(torch, v, dtype)
+    a, b = torch.empty_like(vd), torch.empty_like(vd)
+    for P in (1, 2, 3):
+        pm = molt.Plan((ny, nx), h, 0, P=P, cfl=2.0, dtype=dtype, mask=mask)
+        pr = molt.Plan((ny, nx), h, 0, P=P, cfl=2.0, dtype=dtype)
+        pm.apply("rhs", vd, a)
+        pr.apply("rhs", vd, b)
+        torch.cuda.synchronize()
+        check("full mask vs rectangle rhs P=%d" % P, host(a), host(b), dtype)
+        pm.close()
+        pr.close()
