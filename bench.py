@@ -90,6 +90,54 @@ def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1):
     return ms, kern, info
 
 
+def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=4, burst=False, steps=100):
+    """The serving workload: a Poisson stream of independent FP32 requests
+    (n log-uniform in [128, 2048], P in {1, 2, 3}, CFL in [1, 4], 100 steps,
+    4 Gaussian pulses) through the request server with a device budget.
+    Latency = scheduled arrival -> completion seen by the polling loop."""
+    import numpy as np
+    import torch
+    from paper_1308_3214_amd import molt
+    from paper_1308_3214_amd import workloads as W
+    reqs = W.request_stream(count, rate_hz, seed, steps=steps, burst=burst)
+    # initial fields in pinned host memory, made before the clock starts
+    inits = [torch.from_numpy(W.request_initial(r).astype(np.float32)).pin_memory() for r in reqs]
+    srv = molt.Server(budget, nstreams)
+    arrival, done_t, rid_of = {}, {}, {}
+    t0 = time.perf_counter()
+    i = 0
+    while len(done_t) < count:
+        now = time.perf_counter() - t0
+        while i < count and reqs[i].arrival_s <= now:
+            r = reqs[i]
+            rid = srv.submit(inits[i], (r.n, r.n), 1.0 / (r.n - 1), r.steps, P=r.P, cfl=r.cfl,
+                             dtype="f32")
+            arrival[rid] = r.arrival_s
+            rid_of[rid] = i
+            i += 1
+        got = srv.poll()
+        tn = time.perf_counter() - t0
+        for rid in got:
+            done_t[rid] = tn
+            srv.result(rid)                 # back to the client (host)
+        if not got:
+            time.sleep(50e-6)
+        if tn > 300:
+            raise RuntimeError("serving run did not finish")
+    st = srv.stats()
+    srv.close()
+    lat = np.array([done_t[k] - arrival[k] for k in done_t]) * 1e3
+    pts = float(sum(r.n * r.n * r.steps for r in reqs))
+    span = max(done_t.values()) - min(r.arrival_s for r in reqs)
+    return {"requests": count, "rate_hz": None if burst else rate_hz, "burst": burst,
+            "budget_bytes": budget, "streams": nstreams,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "max_ms": round(float(lat.max()), 3),
+            "Mpoint-updates/s": round(pts / span / 1e6, 1),
+            "span_s": round(span, 3), "peak_bytes": st["bytes_peak"]}
+
+
 def cpu_baseline(n, P, cfl, nsteps=1, seed=1):
     import numpy as np
     import oracle
@@ -118,6 +166,7 @@ def main():
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is built and measured on a single "
@@ -174,6 +223,8 @@ def main():
         also["%dx%d_P%d_f64" % (n, n, P)] = {
             "Mpoint-updates/s": round(points / (fp64[0] / max(20, args.steps // 4) * 1e-3) / 1e6, 2)}
         out["also"] = also
+    if not args.no_serve:
+        out["serving"] = {"poisson": serve(), "burst": serve(burst=True)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, P, args.cfl, 1)
     print(json.dumps(out))

@@ -136,13 +136,63 @@ mol_status mol_step(mol_plan *plan, const void *u_prev, const void *u_curr, void
 mol_status mol_solve(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
                      void *stream);
 
-/* One step for each of count independent plans (serving): equivalent to
- * mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream) for every i,
- * with the sweeps of plans of the same dtype and direction fused into shared
- * launches.  Plans must be distinct. */
+/* One step for each of count independent plans: equivalent to
+ * mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream) for every i, in
+ * order, on one stream.  Plans must be distinct.  (Concurrent serving of many
+ * requests is the request server below.) */
 mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
                           const void *const *u_curr, void *const *u_next, int count,
                           void *stream);
+
+/* ---- Request server (serving many independent solves on one GPU) ----
+ *
+ * Continuous batching of independent requests of differing n, P, CFL and
+ * dtype (any descriptor mol_plan_create accepts).  A request is admitted in
+ * arrival order when its device footprint -- mol_workspace_bytes(desc) plus
+ * two fields -- fits the server's byte budget next to the requests already
+ * running; it then owns a plan and two resident fields, runs mol_start and
+ * nsteps - 1 steps (mol_solve, graph-captured) on one stream of the server's
+ * pool, and finishes with an event.  Requests on different streams run
+ * concurrently.  Allocations are stream-ordered: admitting or retiring a
+ * request never synchronises the device.  One host thread at a time per
+ * server (calls are serialised by a mutex).
+ */
+typedef struct mol_server_ mol_server;
+
+typedef struct mol_server_info {
+    int64_t queued;         /* submitted, not admitted yet */
+    int64_t running;        /* admitted, not finished */
+    int64_t finished;       /* finished, result not taken yet */
+    int64_t completed;      /* finished since creation */
+    size_t bytes_in_use;    /* footprint of admitted requests and untaken results */
+    size_t bytes_peak;
+    size_t budget;
+} mol_server_info;
+
+/* hbm_budget_bytes > 0: device bytes the server may hold; nstreams in 1..64
+ * (default-priority, non-blocking streams on the current device). */
+mol_status mol_server_create(size_t hbm_budget_bytes, int nstreams, mol_server **server);
+/* Waits for running requests and frees everything, results not taken included. */
+mol_status mol_server_destroy(mol_server *server);
+/* Queues a request: the solution u^nsteps (nsteps >= 1) from u^0 = u0 with
+ * zero initial velocity (Sec. 2, start of the three-level scheme).  u0 is a
+ * host (u0_on_device = 0) or device pointer to one field of the descriptor's
+ * shape and dtype; it must stay valid and unchanged until the request is
+ * reported finished.  The descriptor (and its mask / cross arrays) is copied.
+ * MOL_E_INVALID for a descriptor mol_plan_create would reject, MOL_E_NOMEM if
+ * the footprint exceeds the budget.  *id receives the request id (> 0). */
+mol_status mol_server_submit(mol_server *server, const mol_desc *desc, const void *u0,
+                             int u0_on_device, int64_t nsteps, int64_t *id);
+/* Retires finished requests, admits queued ones, and writes up to max ids of
+ * requests that finished since the last poll to done_ids (*ndone of them).
+ * Never blocks. */
+mol_status mol_server_poll(mol_server *server, int64_t *done_ids, int max, int *ndone);
+/* Copies the result of a finished request to dst (host or device pointer,
+ * one field) and releases the request.  MOL_E_DEVICE if the request failed
+ * (mol_server_last_error() tells why). */
+mol_status mol_server_result(mol_server *server, int64_t id, void *dst, int dst_on_device);
+mol_status mol_server_stats(mol_server *server, mol_server_info *info);
+const char *mol_server_last_error(void);
 
 /* Single operators, for testing and composition.  in and out must not overlap. */
 typedef enum {

@@ -703,13 +703,16 @@ double program_bytes(const mol_plan_ *pl, const Program &prog)
     return b * (double)pl->npts * (double)pl->es;
 }
 
-void free_plan(mol_plan_ *pl)
+void free_plan(mol_plan_ *pl, hipStream_t st = nullptr)
 {
     if (!pl) return;
     if (pl->gexec) hipGraphExecDestroy(pl->gexec);
     if (pl->graph) hipGraphDestroy(pl->graph);
-    for (void *p : pl->ws)
-        if (p) hipFree(p);
+    for (void *p : pl->ws) {
+        if (!p) continue;
+        if (pl->async_ws) (void)hipFreeAsync(p, st);
+        else (void)hipFree(p);
+    }
     masked_free(pl);
     delete pl;
 }
@@ -722,7 +725,35 @@ mol_status dev_err(hipError_t e, const char *what)
     return fail(MOL_E_DEVICE, m);
 }
 
-}  // namespace
+mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out)
+{
+    if (!out) return fail(MOL_E_INVALID, "plan out-pointer is NULL");
+    mol_plan_ *pl = new (std::nothrow) mol_plan_();
+    if (!pl) return fail(MOL_E_NOMEM, "host allocation failed");
+    mol_status s = build_plan(desc, pl, false);
+    if (s != MOL_OK) {
+        free_plan(pl);
+        return s;
+    }
+    hipGetDevice(&pl->dev);
+    pl->async_ws = true;
+    pl->ws.assign(pl->nws, nullptr);
+    for (int i = 0; i < pl->nws; ++i) {
+        hipError_t e = hipMallocAsync(&pl->ws[i], (size_t)pl->npts * pl->es, st);
+        if (e != hipSuccess) {
+            pl->ws[i] = nullptr;
+            free_plan(pl, st);
+            return fail(MOL_E_NOMEM, "stream-ordered allocation of the workspace failed");
+        }
+        (void)hipMemsetAsync(pl->ws[i], 0, (size_t)pl->npts * pl->es, st);
+    }
+    *out = pl;
+    return MOL_OK;
+}
+
+void plan_destroy_async(mol_plan_ *pl, hipStream_t st) { free_plan(pl, st); }
+
+}  // namespace molt
 
 // ---------------------------------------------------------------------------
 // C-ABI

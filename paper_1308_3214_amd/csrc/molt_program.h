@@ -53,6 +53,8 @@ struct mol_plan_ {
     std::vector<double> h_cross;
     // tuned launch configurations: key "dir nf ns no" -> config id
     std::vector<std::pair<std::string, int>> tuned;
+    // workspace from the stream-ordered allocator (plans of the request server)
+    bool async_ws = false;
 };
 
 namespace molt {
@@ -113,5 +115,10 @@ mol_status masked_tables(mol_plan_ *pl, bool dry, std::string &err);
 void masked_free(mol_plan_ *pl);
 hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *const *fptr,
                          void *const *optr, hipStream_t st);
+
+// plans whose workspace is allocated and freed in stream order on st (no
+// device-wide synchronisation; used by the request server)
+mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out);
+void plan_destroy_async(mol_plan_ *pl, hipStream_t st);
 
 }  // namespace molt

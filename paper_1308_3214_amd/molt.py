@@ -91,15 +91,37 @@ _lib.mol_plan_kernel_configs.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctype
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.mol_plan_set_kernel_config.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
 _lib.mol_plan_tune_key.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+
+
+
+class _SrvInfo(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("finished", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
+                ("budget", ctypes.c_size_t)]
+
+
+_lib.mol_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.mol_server_destroy.argtypes = [_vp]
+_lib.mol_server_submit.argtypes = [_vp, ctypes.POINTER(_Desc), _vp, ctypes.c_int, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)]
+_lib.mol_server_poll.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int)]
+_lib.mol_server_result.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int]
+_lib.mol_server_stats.argtypes = [_vp, ctypes.POINTER(_SrvInfo)]
+_lib.mol_server_last_error.restype = ctypes.c_char_p
 for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
            "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
-           "mol_solve", "mol_apply", "mol_step_batch"):
+           "mol_solve", "mol_apply", "mol_step_batch", "mol_server_create", "mol_server_destroy",
+           "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
            "mol_workspace_bytes", "mol_start", "mol_step", "mol_solve", "mol_step_batch",
            "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
-           "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error")
+           "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error",
+           "mol_server_create", "mol_server_destroy", "mol_server_submit", "mol_server_poll",
+           "mol_server_result", "mol_server_stats", "mol_server_last_error")
 
 
 def _check(st):
@@ -259,6 +281,77 @@ class Plan:
     def apply(self, op, x, out, stream=None):
         code = OPS[op] if isinstance(op, str) else int(op)
         _check(_lib.mol_apply(self._h, code, self._t(x), self._t(out), _stream(stream)))
+
+
+class Server:
+    """Request server (continuous batching of independent solves, admitted by
+    device footprint).  submit() takes the initial field as a host numpy array
+    or a device tensor; the server keeps a reference until the result is
+    taken."""
+
+    def __init__(self, budget_bytes, nstreams=4):
+        h = _vp()
+        st = _lib.mol_server_create(int(budget_bytes), int(nstreams), ctypes.byref(h))
+        if st != MOL_OK:
+            raise MolError(st, _lib.mol_server_last_error().decode())
+        self._h = h
+        self._keep = {}
+
+    def _chk(self, st):
+        if st != MOL_OK:
+            raise MolError(st, _lib.mol_server_last_error().decode())
+
+    def submit(self, u0, shape, h, nsteps, **kw):
+        d, keep = make_desc(shape, h, **kw)
+        if isinstance(u0, np.ndarray):
+            arr = np.ascontiguousarray(u0, dtype=np.float64 if d.dtype == F64 else np.float32)
+            ptr, ondev = arr.ctypes.data, 0
+        else:                      # torch tensor: device, or (pinned) host memory
+            arr = u0
+            ptr, ondev = u0.data_ptr(), 1 if u0.is_cuda else 0
+        rid = ctypes.c_int64()
+        self._chk(_lib.mol_server_submit(self._h, ctypes.byref(d), ctypes.c_void_p(ptr), ondev,
+                                         int(nsteps), ctypes.byref(rid)))
+        self._keep[rid.value] = (arr, keep, tuple(int(x) for x in shape),
+                                 np.float64 if d.dtype == F64 else np.float32)
+        return rid.value
+
+    def poll(self, max_ids=1024):
+        ids = (ctypes.c_int64 * max_ids)()
+        n = ctypes.c_int()
+        self._chk(_lib.mol_server_poll(self._h, ids, max_ids, ctypes.byref(n)))
+        return [ids[i] for i in range(n.value)]
+
+    def result(self, rid, out=None):
+        """Copies u^nsteps into out (device tensor) or returns a host array."""
+        _, _, shape, dt = self._keep[rid]
+        if out is None:
+            host = np.empty(shape, dtype=dt)
+            st = _lib.mol_server_result(self._h, int(rid), ctypes.c_void_p(host.ctypes.data), 0)
+            self._keep.pop(rid, None)
+            self._chk(st)
+            return host
+        st = _lib.mol_server_result(self._h, int(rid), ctypes.c_void_p(out.data_ptr()), 1)
+        self._keep.pop(rid, None)
+        self._chk(st)
+        return out
+
+    def stats(self):
+        i = _SrvInfo()
+        self._chk(_lib.mol_server_stats(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _SrvInfo._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.mol_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def step_batch(plans, u_prev, u_curr, u_next, stream=None):
