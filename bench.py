@@ -32,62 +32,106 @@ METRIC = "Mpoint-updates/s & %HBM roofline (2D ADI P=2); p50/p99 served latency"
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel and plan sources: counter data taken on other
+    sources is not reported."""
     h = hashlib.sha256()
-    for f in ("molt_kernels.hip", "molt_plan.cpp"):
-        with open(os.path.join(ROOT, "paper_1308_3214_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1308_3214_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def traffic_for(kernel_tag: str):
-    """Measured HBM bytes per launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
+    by the copy calibration) from profiles/traffic.txt, if the counters were
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(p):
         return None
-    try:
-        d = json.load(open(p))
-    except Exception:
+    src, found = None, None
+    for line in open(p):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source_hash":
+            src = f[1]
+        elif len(f) >= 6 and f[0] == "kernel" and f[1] == kernel_tag:
+            found = float(f[3]) + float(f[5])
+    if src != kernel_source_hash():
         return None
-    if d.get("source_hash") != kernel_source_hash():
-        return None
-    ent = d.get("kernels", {}).get(kernel_tag)
-    return None if ent is None else ent.get("bytes_per_launch")
+    return found
 
 
-def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1):
+def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, **kw):
+    """Time `steps` steps of mol_solve (graph replay) after `warmup` steps, with
+    HIP events on the library's stream; optional per-kernel breakdown."""
     import torch
     from paper_1308_3214_amd import molt
-    from paper_1308_3214_amd import workloads as W
 
-    h = 1.0 / (n - 1)
-    plan = molt.Plan((n, n), h, molt.DIRICHLET, P=P, cfl=cfl, dtype=dtype)
+    plan = molt.Plan(shape, h, bc, P=P, cfl=cfl, dtype=dtype, **kw)
     td = torch.float64 if dtype == "f64" else torch.float32
-    u0 = torch.tensor(W.gaussian_pulses_2d(n, seed=seed), dtype=td, device="cuda")
-    u1 = torch.empty_like(u0)
+    a = torch.tensor(u0, dtype=td, device="cuda")
+    b = torch.empty_like(a)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        plan.start(u0, u1)
-        plan.solve(u0, u1, warmup)           # also captures the graph
+        plan.start(a, b)
+        plan.solve(a, b, warmup)             # also captures the graph
         stream.synchronize()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        plan.solve(u0, u1, steps)
+        plan.solve(a, b, steps)
         e1.record(stream)
         stream.synchronize()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    assert torch.isfinite(u1).all().item(), "non-finite field"
-    # per-kernel breakdown of one step (events around every launch)
-    scratch = torch.empty_like(u0)
-    with torch.cuda.stream(stream):
-        kern = plan.profile_step(u0, u1, scratch, reps=max(3, min(20, steps // 5)))
-    torch.cuda.synchronize()
+    assert torch.isfinite(b).all().item(), "non-finite field"
+    kern = None
+    if profile:
+        # per-kernel breakdown of one step (events around every launch)
+        scratch = torch.empty_like(a)
+        with torch.cuda.stream(stream):
+            kern = plan.profile_step(a, b, scratch, reps=max(3, min(20, steps // 5)))
+        torch.cuda.synchronize()
     info = plan.info
     plan.close()
     return ms, kern, info
+
+
+def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1):
+    from paper_1308_3214_amd import workloads as W
+    u0 = W.gaussian_pulses_2d(n, seed=seed)
+    return run_plan((n, n), 1.0 / (n - 1), 0, P, cfl, dtype, u0, steps, warmup)
+
+
+def also_line(ms, steps, info, points):
+    step_ms = ms / steps
+    return {"Mpoint-updates/s": round(points / (step_ms * 1e-3) / 1e6, 2),
+            "ms_per_step": round(step_ms, 5),
+            "model_hbm_frac": round(info["bytes_per_step"] / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def star_workload(steps=300, warmup=10):
+    """2048^2 star cavity, P = 3, CFL 1.5, FP32 (line objects, Sec. 4.3)."""
+    from paper_1308_3214_amd import workloads as W
+    n = 2048
+    dom, mask, cross = W.star_domain(n, seed=1)
+    u0 = W.star_pulses(dom, mask, seed=1)
+    ms, _, info = run_plan((n, n), 1.0 / (n - 1), 0, 3, 1.5, "f32", u0, steps, warmup,
+                           profile=False, mask=mask, cross=cross)
+    out = also_line(ms, steps, info, info["unknowns"])
+    out["points"] = "inside nodes (%d)" % info["unknowns"]
+    return out
+
+
+def periodic3d_workload(steps=200, warmup=10):
+    """3D periodic 256^3, P = 2, CFL 2, FP32, four plane waves."""
+    from paper_1308_3214_amd import workloads as W
+    n = 256
+    u0, _, _ = W.plane_waves_3d(n, seed=1)
+    ms, _, info = run_plan((n, n, n), 1.0 / n, 1, 2, 2.0, "f32", u0, steps, warmup, profile=False)
+    return also_line(ms, steps, info, n ** 3)
 
 
 def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=4, burst=False, steps=100):
@@ -158,8 +202,8 @@ def cpu_baseline(n, P, cfl, nsteps=1, seed=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--P", type=int, default=2)
     ap.add_argument("--cfl", type=float, default=2.0)
@@ -167,7 +211,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 64 MiB buffer 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 64 << 20, "copies": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is built and measured on a single "
               "MI355X (multi-GPU slab decomposition is a design note, not built)", file=sys.stderr)
@@ -216,12 +271,12 @@ def main():
         also = {}
         for dt in ("f64", "f32"):
             ms2, _, inf2 = run_gpu(1024, 2, 2.0, dt, 500, 10)
-            also["1024x1024_P2_%s_500steps" % dt] = {
-                "Mpoint-updates/s": round(1024 * 1024 * 500 / (ms2 * 1e-3) / 1e6, 2),
-                "ms_per_step": round(ms2 / 500, 5)}
-        fp64 = run_gpu(n, P, args.cfl, "f64", max(20, args.steps // 4), 5)
-        also["%dx%d_P%d_f64" % (n, n, P)] = {
-            "Mpoint-updates/s": round(points / (fp64[0] / max(20, args.steps // 4) * 1e-3) / 1e6, 2)}
+            also["1024x1024_P2_%s_500steps" % dt] = also_line(ms2, 500, inf2, 1024 * 1024)
+        k64 = max(20, args.steps // 4)
+        ms2, _, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
+        also["%dx%d_P%d_f64" % (n, n, P)] = also_line(ms2, k64, inf2, points)
+        also["star2048_P3_f32_300steps"] = star_workload()
+        also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
         out["also"] = also
     if not args.no_serve:
         out["serving"] = {"poisson": serve(), "burst": serve(burst=True)}

@@ -6,6 +6,14 @@
 
 namespace molt {
 
+// Kernel-duration events of mol_profile_step: when set, the next box-sweep
+// launch of this thread takes them as its dispatch's start / stop timestamps
+// (and clears them), so a duration excludes launch gaps.
+struct ProfEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local ProfEvents g_prof;
+
 constexpr int MAXF = 16;  // fields loaded by one launch
 constexpr int MAXS = 2;   // swept combinations per launch
 constexpr int MAXO = 3;   // outputs per launch

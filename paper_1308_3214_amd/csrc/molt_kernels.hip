@@ -10,6 +10,9 @@
 
 namespace molt {
 
+thread_local ProfEvents g_prof;
+
+
 namespace {
 
 

@@ -18,11 +18,12 @@
 #include <algorithm>
 #include <cstdlib>
 #include <fstream>
+#include <map>
+#include <mutex>
 #include <sstream>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -521,6 +522,8 @@ std::string tune_op_key(const SweepOp &op)
 }
 
 // Tuning cache: lines "<problem key> | <op key> | <config id>".
+// The tuning cache (tune_cache.txt beside the library, or the file named by
+// MOLT_TUNE_CACHE) is parsed once per process and path.
 void load_tune_cache(mol_plan_ *pl)
 {
     std::string path;
@@ -535,18 +538,27 @@ void load_tune_cache(mol_plan_ *pl)
         }
     }
     if (path.empty()) return;
-    std::ifstream f(path);
-    if (!f) return;
-    const std::string pk = tune_problem_key(pl);
-    std::string line;
-    while (std::getline(f, line)) {
-        const size_t a = line.find(" | "), b = line.rfind(" | ");
-        if (a == std::string::npos || b == a) continue;
-        if (line.substr(0, a) != pk) continue;
-        const std::string ok = line.substr(a + 3, b - a - 3);
-        const int id = std::atoi(line.c_str() + b + 3);
-        pl->tuned.push_back({ok, id});
+    // problem key -> (kernel key, config id)
+    typedef std::vector<std::pair<std::string, std::pair<std::string, int>>> Entries;
+    static std::mutex mu;
+    static std::map<std::string, Entries> parsed;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = parsed.find(path);
+    if (it == parsed.end()) {
+        Entries ent;
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            const size_t a = line.find(" | "), b = line.rfind(" | ");
+            if (a == std::string::npos || b == a) continue;
+            ent.push_back({line.substr(0, a),
+                           {line.substr(a + 3, b - a - 3), std::atoi(line.c_str() + b + 3)}});
+        }
+        it = parsed.emplace(path, std::move(ent)).first;
     }
+    const std::string pk = tune_problem_key(pl);
+    for (const auto &e : it->second)
+        if (e.first == pk) pl->tuned.push_back(e.second);
 }
 
 mol_status validate(const mol_desc *d)
@@ -625,7 +637,7 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
         pl->unknowns = 0;
         for (int64_t i = 0; i < pl->npts; ++i) pl->unknowns += d->mask[i] ? 1 : 0;
     }
-    load_tune_cache(pl);
+    if (!dry) load_tune_cache(pl);
     Builder b(*pl, dry);
     // step: u_next = 2 u - u_prev + rhs(u)
     bool ok = build_rhs(b, pl->step, B_UCURR, {{B_UNEXT, lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0), 1.0}});
@@ -963,9 +975,19 @@ mol_status mol_profile_step(mol_plan *pl, const void *u_prev, const void *u_curr
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
         for (int i = 0; i < nk && e == hipSuccess; ++i) {
             Program one(1, sp[i]);
-            e = hipEventRecord(ev[2 * ((size_t)r * nk + i)], st);
-            if (e == hipSuccess) e = run_program(pl, one, u_prev, u_curr, u_next, nullptr, nullptr, st);
-            if (e == hipSuccess) e = hipEventRecord(ev[2 * ((size_t)r * nk + i) + 1], st);
+            hipEvent_t e0 = ev[2 * ((size_t)r * nk + i)], e1 = ev[2 * ((size_t)r * nk + i) + 1];
+            if (pl->masked) {
+                // several launches per sweep: events around the group
+                e = hipEventRecord(e0, st);
+                if (e == hipSuccess) e = run_program(pl, one, u_prev, u_curr, u_next, nullptr, nullptr, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+            } else {
+                // the launch records the kernel's own start and stop
+                g_prof.start = e0;
+                g_prof.stop = e1;
+                e = run_program(pl, one, u_prev, u_curr, u_next, nullptr, nullptr, st);
+                g_prof = ProfEvents{};
+            }
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -35,6 +35,7 @@
 // Green's function), computed cooperatively by all waves of the tile.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -44,6 +45,18 @@
 #include "molt_internal.h"
 
 namespace molt {
+
+template <typename... A, typename F>
+inline void launch_k(F fn, dim3 grid, dim3 block, size_t shmem, hipStream_t st, A... args)
+{
+    if (g_prof.start) {
+        hipExtLaunchKernelGGL(fn, grid, block, (std::uint32_t)shmem, st, g_prof.start, g_prof.stop, 0u,
+                              args...);
+        g_prof = ProfEvents{};
+    } else {
+        hipLaunchKernelGGL(fn, grid, block, shmem, st, args...);
+    }
+}
 
 template <typename T>
 struct KArgs {
