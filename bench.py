@@ -182,6 +182,30 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=4, burst=Fal
             "span_s": round(span, 3), "peak_bytes": st["bytes_peak"]}
 
 
+def stream_copy(n_bytes=64 << 20, nsets=6, reps=24):
+    """Measured device copy bandwidth, GB/s counting read + write: `nsets`
+    buffer pairs rotated so that every copy starts from data outside the
+    256 MB last-level cache (cold), and one pair copied repeatedly (warm)."""
+    import torch
+    src = [torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda") for _ in range(nsets)]
+    dst = [torch.empty_like(x) for x in src]
+    out = {}
+    for name, k in (("cold", nsets), ("warm", 1)):
+        for i in range(k):
+            dst[i].copy_(src[i])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            dst[i % k].copy_(src[i % k])
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(2.0 * n_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst
+    return out
+
+
 def cpu_baseline(n, P, cfl, nsteps=1, seed=1):
     import numpy as np
     import oracle
@@ -263,6 +287,7 @@ def main():
                      "traffic": traffic, "kernel": tag,
                      "kernel_ms": round(k["ms"], 5), "kernel_bytes": k["bytes"]},
         "step_bytes": info["bytes_per_step"],
+        "stream_copy_GBs": stream_copy(),
         "step_hbm_frac": round(step_gbs / HBM_PEAK_GBS, 4),
         "kernels": [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
                      "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kern],

@@ -1019,10 +1019,13 @@ template <typename T, int S, int W, int NS, int NO, bool PER, int NFP>
 __global__ void __launch_bounds__(64 * W)
 k_sweep_p(const KArgs<T> a)
 {
+    static_assert(W >= 2, "the carry scans take waves 0 and 1");
     constexpr int WS = W * S;
     constexpr int HB = 4;                        // halo rows per wave and round
     __shared__ T agg[3][2][NS][W][64];           // aL, aR of every wave, 3 sub-tiles in flight
     __shared__ T endv[NS][64];                   // E^L_M of each column
+    __shared__ T cLs[NS][W][64], cRs[NS][W][64]; // carries entering every wave of a sub-tile
+    __shared__ T ctopS[NS][64], er0S[NS][64];
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1074,9 +1077,11 @@ k_sweep_p(const KArgs<T> a)
         return p;
     };
 
-    // raw loads of a sub-tile ahead: nodes p0-1 .. p0+S of this wave
-    T xr[NFP][S + 2];
-    auto issue = [&](int t) {
+    // raw loads of the sub-tiles ahead (two buffers: loads run two sub-tiles
+    // ahead of the finish): nodes p0-1 .. p0+S of this wave
+    typedef T Raw[NFP][S + 2];
+    Raw xa, xb;
+    auto issue = [&](int t, Raw &xr) {
         const int p0 = s0 + t * WS + wave * S;
 #pragma unroll
         for (int j = 0; j < S + 2; ++j) {
@@ -1086,7 +1091,7 @@ k_sweep_p(const KArgs<T> a)
         }
     };
     // swept combinations, elementwise parts and local recurrences of sub-tile t
-    auto combine = [&](int t, SubTile<T, S, NS, NO> &st) {
+    auto combine = [&](int t, SubTile<T, S, NS, NO> &st, const Raw &xr) {
         const int p0 = s0 + t * WS + wave * S;
         T v[NS][S + 2];
 #pragma unroll
@@ -1142,7 +1147,7 @@ k_sweep_p(const KArgs<T> a)
     };
 
     SubTile<T, S, NS, NO> cur, nxt;
-    issue(0);
+    issue(0, xa);
 
     // ---- halo sums at the strip ends (cooperative over all waves) ----
     T ctop[NS], cbs[NS];
@@ -1232,8 +1237,9 @@ k_sweep_p(const KArgs<T> a)
         __syncthreads();
     }
 
-    combine(0, cur);
-    if (R > 1) issue(1);
+    combine(0, cur, xa);
+    if (R > 1) issue(1, xa);
+    if (R > 2) issue(2, xb);
 
     bool bline = false;
     if (a.proj)
@@ -1243,11 +1249,12 @@ k_sweep_p(const KArgs<T> a)
 #pragma unroll
     for (int o = 0; o < NO; ++o) rso[o] = make_rsrc(a.o[o] + blk, lineb);
 
-    for (int t = 0; t < R; ++t) {
+    // sub-tile t + 1 sits in buffer xa when t is even, xb when odd
+    auto finish = [&](int t, Raw &xr) {
         const bool last = (t + 1 == R);
         if (!last) {
-            combine(t + 1, nxt);
-            if (t + 2 < R) issue(t + 2);
+            combine(t + 1, nxt, xr);
+            if (t + 3 < R) issue(t + 3, xr);
         }
         __syncthreads();
 
@@ -1255,33 +1262,51 @@ k_sweep_p(const KArgs<T> a)
         const int st0 = s0 + t * WS;
         const int p0 = st0 + wave * S;
         const bool botAsB = per && last && s1 == n;
+        // carries of every wave, computed once: wave 0 scans forward (and
+        // keeps the carry into the next sub-tile), wave 1 the look-ahead
+        // aggregate and backward
+        if (wave == 0) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                T c = ctop[k];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    cLs[k][w][lane] = c;
+                    c = dS * c + agg[t % 3][0][k][w][lane];
+                }
+                ctop[k] = c;
+                ctopS[k][lane] = c;
+            }
+        } else if (wave == 1) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                T cb;
+                if (!last) {
+                    T ag = T(0);
+#pragma unroll
+                    for (int w = W - 1; w >= 0; --w) ag = dS * ag + agg[(t + 1) % 3][1][k][w][lane];
+                    if (t + 2 == R) ag += expneg<T>(a.nu * (double)(s1 - (st0 + WS))) * cbs[k];
+                    cb = ag;
+                } else {
+                    cb = botAsB ? T(0) : cbs[k];
+                }
+                T cr = cb;
+#pragma unroll
+                for (int w = W - 1; w >= 0; --w) {
+                    cRs[k][w][lane] = cr;
+                    cr = dS * cr + agg[t % 3][1][k][w][lane];
+                }
+                er0S[k][lane] = cr;                  // E^R at node st0
+            }
+        }
+        __syncthreads();
         T cL[NS], cR[NS], ctopn[NS], er0[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            T c = ctop[k];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                if (w == wave) cL[k] = c;
-                c = dS * c + agg[t % 3][0][k][w][lane];
-            }
-            ctopn[k] = c;
-            T cb;
-            if (!last) {
-                T ag = T(0);
-#pragma unroll
-                for (int w = W - 1; w >= 0; --w) ag = dS * ag + agg[(t + 1) % 3][1][k][w][lane];
-                if (t + 2 == R) ag += expneg<T>(a.nu * (double)(s1 - (st0 + WS))) * cbs[k];
-                cb = ag;
-            } else {
-                cb = botAsB ? T(0) : cbs[k];
-            }
-            T cr = cb;
-#pragma unroll
-            for (int w = W - 1; w >= 0; --w) {
-                if (w == wave) cR[k] = cr;
-                cr = dS * cr + agg[t % 3][1][k][w][lane];
-            }
-            er0[k] = cr;                                 // E^R at node st0
+            cL[k] = cLs[k][wave][lane];
+            cR[k] = cRs[k][wave][lane];
+            ctopn[k] = ctopS[k][lane];
+            er0[k] = er0S[k][lane];
         }
         double A[NS], B[NS];
 #pragma unroll
@@ -1335,9 +1360,11 @@ k_sweep_p(const KArgs<T> a)
                 }
             }
         }
-#pragma unroll
-        for (int k = 0; k < NS; ++k) ctop[k] = ctopn[k];
         cur = nxt;
+    };
+    for (int t = 0; t < R; t += 2) {
+        finish(t, xa);
+        if (t + 1 < R) finish(t + 1, xb);
     }
 }
 
