@@ -112,6 +112,10 @@ struct SegTable {
 // All line objects of one direction (every class), one launch per class.
 hipError_t launch_seg_sweep(const SweepOp &op, const SegTable &tab, const DirCoef &dc, bool fp64,
                             const void *const *fptr, void *const *optr, hipStream_t st);
+// out = transpose of the R x C array in (C x R); with d_mask (of out's
+// layout) the outside nodes of out are written as 0
+hipError_t launch_transpose(bool fp64, const void *in, void *out, int64_t R, int64_t C,
+                            const unsigned char *d_mask, hipStream_t st);
 // out[i] = 0 where mask[i] == 0 (outside nodes of a user-visible output)
 hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, void *out,
                             hipStream_t st);

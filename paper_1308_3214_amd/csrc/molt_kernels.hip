@@ -205,9 +205,9 @@ int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf,
     // strided: the pipelined strip kernel for one swept combination, else
     // tall tiles (16 waves x 16 nodes) for FP32 single sweeps, shorter lanes
     // when more registers are live
-    if (ns == 1) {
+    if (ns <= 2) {
         // only when the strips give enough workgroups to fill the chip
-        cfg[0] = NSCFG + (fp64 ? 2 : 0);     // {8,16,256} FP32, {8,8,512} FP64
+        cfg[0] = NSCFG + ((fp64 || ns == 2) ? 2 : 0);   // {8,16,256} FP32 one combo, else {8,8,512}
         const PCfg c = kPCfg[cfg[0] - NSCFG];
         const int64_t tiles = (dc.n + (int64_t)c.S * c.W - 1) / ((int64_t)c.S * c.W);
         const int64_t groups = ((g.n[0] + 63) / 64) * (dir == 1 ? g.n[2] : g.n[1]);

@@ -157,27 +157,55 @@ mol_status masked_tables(mol_plan_ *pl, bool dry, std::string &err)
                 i = j + 1;
             }
         }
-        // group by length class (stable: line order within a class)
+        // one launch per sweep: every object of the direction in the class of
+        // the longest one, longest objects first
+        int cmax = 0;
+        for (const SegRec &r : recs) cmax = std::max(cmax, (int)r.cls);
+        for (SegRec &r : recs) r.cls = cmax;
         std::stable_sort(recs.begin(), recs.end(),
-                         [](const SegRec &a, const SegRec &b) { return a.cls < b.cls; });
-        SegTable &t = pl->seg[dir];
-        t.nseg = (int64_t)recs.size();
-        t.pstride = ps;
-        for (int c = 0; c <= NSEGCLS; ++c) t.cls_begin[c] = 0;
-        for (const SegRec &r : recs) t.cls_begin[r.cls + 1] += 1;
-        for (int c = 0; c < NSEGCLS; ++c) t.cls_begin[c + 1] += t.cls_begin[c];
-        pl->nsegs[dir] = t.nseg;
-        pl->table_bytes += recs.size() * sizeof(SegRec);
-        if (!dry && !recs.empty()) {
-            if (hipMalloc(&t.d_rec, recs.size() * sizeof(SegRec)) != hipSuccess) {
+                         [](const SegRec &a, const SegRec &b) { return a.m > b.m; });
+        auto upload = [&](SegTable &t, const std::vector<SegRec> &rv, int64_t pstride) -> mol_status {
+            t.nseg = (int64_t)rv.size();
+            t.pstride = pstride;
+            for (int c = 0; c <= NSEGCLS; ++c) t.cls_begin[c] = 0;
+            for (const SegRec &r : rv) t.cls_begin[r.cls + 1] += 1;
+            for (int c = 0; c < NSEGCLS; ++c) t.cls_begin[c + 1] += t.cls_begin[c];
+            pl->table_bytes += rv.size() * sizeof(SegRec);
+            if (dry || rv.empty()) return MOL_OK;
+            if (hipMalloc(&t.d_rec, rv.size() * sizeof(SegRec)) != hipSuccess) {
                 err = "hipMalloc of the line-object table failed";
                 return MOL_E_NOMEM;
             }
-            if (hipMemcpy(t.d_rec, recs.data(), recs.size() * sizeof(SegRec),
-                          hipMemcpyHostToDevice) != hipSuccess) {
+            if (hipMemcpy(t.d_rec, rv.data(), rv.size() * sizeof(SegRec), hipMemcpyHostToDevice) !=
+                hipSuccess) {
                 err = "copy of the line-object table failed";
                 return MOL_E_DEVICE;
             }
+            return MOL_OK;
+        };
+        mol_status us = upload(pl->seg[dir], recs, ps);
+        if (us != MOL_OK) return us;
+        pl->nsegs[dir] = (int64_t)recs.size();
+        if (dir == 1) {
+            // the same objects on the transposed grid: column l, first row i at l*ny + i
+            std::vector<SegRec> rt = recs;
+            for (SegRec &r : rt) {
+                const int64_t l = r.base % nx, i = r.base / nx;
+                r.base = l * ny + i;
+            }
+            us = upload(pl->segT, rt, 1);
+            if (us != MOL_OK) return us;
+        }
+    }
+    // transposed copies of a y launch's fields
+    pl->table_bytes += (size_t)mol_plan_::NTBUF * (size_t)pl->npts * pl->es;
+    if (!dry) {
+        for (int i = 0; i < mol_plan_::NTBUF; ++i) {
+            if (hipMalloc(&pl->tbuf[i], (size_t)pl->npts * pl->es) != hipSuccess) {
+                err = "hipMalloc of the transposed buffers failed";
+                return MOL_E_NOMEM;
+            }
+            (void)hipMemset(pl->tbuf[i], 0, (size_t)pl->npts * pl->es);
         }
     }
     if (!dry) {
@@ -199,6 +227,12 @@ void masked_free(mol_plan_ *pl)
         if (pl->seg[dir].d_rec) (void)hipFree(pl->seg[dir].d_rec);
         pl->seg[dir].d_rec = nullptr;
     }
+    if (pl->segT.d_rec) (void)hipFree(pl->segT.d_rec);
+    pl->segT.d_rec = nullptr;
+    for (int i = 0; i < mol_plan_::NTBUF; ++i) {
+        if (pl->tbuf[i]) (void)hipFree(pl->tbuf[i]);
+        pl->tbuf[i] = nullptr;
+    }
     if (pl->d_mask) (void)hipFree(pl->d_mask);
     pl->d_mask = nullptr;
 }
@@ -207,6 +241,23 @@ hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *con
                          void *const *optr, hipStream_t st)
 {
     if (op.dir < 0 || op.dir > 1 || op.chain) return hipErrorInvalidValue;
+    const int64_t nx = pl->geom.n[0], ny = pl->geom.n[1];
+    if (op.dir == 1 && op.nf + op.no <= mol_plan_::NTBUF) {
+        // y objects as rows of the transposed grid: coalesced sweeps; the
+        // outputs come back with their outside nodes written as 0
+        const void *tf[MAXF];
+        void *to[MAXO];
+        hipError_t e = hipSuccess;
+        for (int f = 0; f < op.nf && e == hipSuccess; ++f) {
+            tf[f] = pl->tbuf[f];
+            e = launch_transpose(pl->fp64, fptr[f], pl->tbuf[f], ny, nx, nullptr, st);
+        }
+        for (int o = 0; o < op.no; ++o) to[o] = pl->tbuf[op.nf + o];
+        if (e == hipSuccess) e = launch_seg_sweep(op, pl->segT, pl->dc[1], pl->fp64, tf, to, st);
+        for (int o = 0; o < op.no && e == hipSuccess; ++o)
+            e = launch_transpose(pl->fp64, pl->tbuf[op.nf + o], optr[o], nx, ny, pl->d_mask, st);
+        return e;
+    }
     hipError_t e = launch_seg_sweep(op, pl->seg[op.dir], pl->dc[op.dir], pl->fp64, fptr, optr, st);
     if (e != hipSuccess) return e;
     if (op.proj) {

@@ -46,6 +46,11 @@ struct mol_plan_ {
     // masked plans (embedded boundary)
     bool masked = false;
     molt::SegTable seg[2];
+    // y line objects on the transposed grid (x <-> y), swept through
+    // transposed copies of a launch's fields (coalesced rows)
+    molt::SegTable segT;
+    static constexpr int NTBUF = 4;
+    void *tbuf[NTBUF] = {};
     unsigned char *d_mask = nullptr;
     int64_t nsegs[2] = {0, 0};
     size_t table_bytes = 0;

@@ -231,6 +231,79 @@ k_seg_sweep(const SegArgs<T> a)
     }
 }
 
+// out[c][r] = in[r][c] for an R x C array (64 x 64 tiles through LDS, both
+// sides coalesced); with a mask (of out's layout), outside nodes become 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_transpose(const T *__restrict__ in, T *__restrict__ out, int R, int C, const unsigned char *mask)
+{
+    __shared__ T tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4 threads
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = r0 + ty + 4 * i, c = c0 + tx;
+        if (r < R && c < C) tile[ty + 4 * i][tx] = in[(int64_t)r * C + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int c = c0 + ty + 4 * i, r = r0 + tx;           // out row c, column r
+        if (r < R && c < C) {
+            const int64_t o = (int64_t)c * R + r;
+            const T v = tile[tx][ty + 4 * i];
+            out[o] = (mask && !mask[o]) ? T(0) : v;
+        }
+    }
+}
+
+// The same with 16-byte accesses on both sides (R and C multiples of 4 and
+// 16-byte aligned arrays): thread t reads rows t/16 + 16 i, four columns
+// 4 (t % 16) .. + 3, of a 64 x 64 tile, and writes four consecutive entries
+// of the transposed rows.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_transpose4(const T *__restrict__ in, T *__restrict__ out, int R, int C, const unsigned char *mask)
+{
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    __shared__ T tile[64][65];
+    const int t = threadIdx.x;
+    const int tr = t >> 4, tc = (t & 15) * 4;
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + tr + 16 * i, c = c0 + tc;
+        if (r < R && c < C) {
+            const v4 x = *reinterpret_cast<const v4 *>(in + (int64_t)r * C + c);
+            tile[tr + 16 * i][tc + 0] = x[0];
+            tile[tr + 16 * i][tc + 1] = x[1];
+            tile[tr + 16 * i][tc + 2] = x[2];
+            tile[tr + 16 * i][tc + 3] = x[3];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = c0 + tr + 16 * i, r = r0 + tc;            // out row c, columns r .. r+3
+        if (c < C && r < R) {
+            const int64_t o = (int64_t)c * R + r;
+            v4 y;
+            y[0] = tile[tc + 0][tr + 16 * i];
+            y[1] = tile[tc + 1][tr + 16 * i];
+            y[2] = tile[tc + 2][tr + 16 * i];
+            y[3] = tile[tc + 3][tr + 16 * i];
+            if (mask) {
+                const uchar4 mk = *reinterpret_cast<const uchar4 *>(mask + o);
+                if (!mk.x) y[0] = T(0);
+                if (!mk.y) y[1] = T(0);
+                if (!mk.z) y[2] = T(0);
+                if (!mk.w) y[3] = T(0);
+            }
+            *reinterpret_cast<v4 *>(out + o) = y;
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_mask_zero(int64_t n, const unsigned char *mask, T *out)
 {
@@ -327,6 +400,34 @@ hipError_t launch_seg_sweep(const SweepOp &op, const SegTable &tab, const DirCoe
         return hipErrorInvalidValue;
     return fp64 ? seg_sweep_t<double>(op, tab, dc, fptr, optr, st)
                 : seg_sweep_t<float>(op, tab, dc, fptr, optr, st);
+}
+
+hipError_t launch_transpose(bool fp64, const void *in, void *out, int64_t R, int64_t C,
+                            const unsigned char *d_mask, hipStream_t st)
+{
+    const dim3 grid((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64));
+    const size_t es = fp64 ? 8 : 4;
+    const bool v4 = (R % 4 == 0) && (C % 4 == 0) && (reinterpret_cast<uintptr_t>(in) % (4 * es) == 0) &&
+                    (reinterpret_cast<uintptr_t>(out) % (4 * es) == 0) &&
+                    (reinterpret_cast<uintptr_t>(d_mask) % 4 == 0);
+    if (v4) {
+        if (fp64)
+            hipLaunchKernelGGL(k_transpose4<double>, grid, dim3(256), 0, st,
+                               static_cast<const double *>(in), static_cast<double *>(out), (int)R,
+                               (int)C, d_mask);
+        else
+            hipLaunchKernelGGL(k_transpose4<float>, grid, dim3(256), 0, st,
+                               static_cast<const float *>(in), static_cast<float *>(out), (int)R,
+                               (int)C, d_mask);
+        return hipGetLastError();
+    }
+    if (fp64)
+        hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, st, static_cast<const double *>(in),
+                           static_cast<double *>(out), (int)R, (int)C, d_mask);
+    else
+        hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, st, static_cast<const float *>(in),
+                           static_cast<float *>(out), (int)R, (int)C, d_mask);
+    return hipGetLastError();
 }
 
 hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, void *out,

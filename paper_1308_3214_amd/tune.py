@@ -25,15 +25,16 @@ DEFAULT_PROBLEMS = [
     dict(shape=(4096, 4096), P=2, dtype="f64"),
     dict(shape=(1024, 1024), P=2, dtype="f32"),
     dict(shape=(1024, 1024), P=2, dtype="f64"),
+    dict(shape=(256, 256, 256), P=2, dtype="f32", bc=1),
 ]
 
 
-def tune_problem(shape, P, dtype, cfl=2.0, reps=10, verbose=True):
+def tune_problem(shape, P, dtype, cfl=2.0, reps=10, verbose=True, bc=0):
     import torch
     from . import molt
     nd = len(shape)
-    h = 1.0 / (shape[-1] - 1)
-    plan = molt.Plan(shape, h, molt.DIRICHLET, P=P, cfl=cfl, dtype=dtype)
+    h = 1.0 / shape[-1] if bc == 1 else 1.0 / (shape[-1] - 1)
+    plan = molt.Plan(shape, h, bc, P=P, cfl=cfl, dtype=dtype)
     td = torch.float64 if dtype == "f64" else torch.float32
     a = torch.rand(shape, dtype=td, device="cuda")
     b = torch.rand(shape, dtype=td, device="cuda")
@@ -84,15 +85,17 @@ def main():
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--P", type=int, default=2)
     ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--ndim", type=int, default=2)
+    ap.add_argument("--bc", type=int, default=0)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--report", default="")
     args = ap.parse_args()
-    probs = DEFAULT_PROBLEMS if args.n == 0 else [dict(shape=(args.n, args.n), P=args.P,
-                                                        dtype=args.dtype)]
+    probs = DEFAULT_PROBLEMS if args.n == 0 else [dict(shape=(args.n,) * args.ndim, P=args.P,
+                                                        dtype=args.dtype, bc=args.bc)]
     allent, allrep = {}, []
     for pr in probs:
         print("tuning", pr, flush=True)
-        ent, rep = tune_problem(pr["shape"], pr["P"], pr["dtype"])
+        ent, rep = tune_problem(pr["shape"], pr["P"], pr["dtype"], bc=pr.get("bc", 0))
         allent.update(ent)
         allrep.append({"problem": {k: list(v) if isinstance(v, tuple) else v
                                    for k, v in pr.items()}, "kernels": rep})

@@ -255,6 +255,40 @@ def test_every_strided_config(torch_cuda, molt, oracle_mod, case, dtype):
     plan.close()
 
 
+# 3D: y lines of 300 nodes carry the two-combination sweeps of the box
+# schedule, z lines of 280 the one-combination sweeps
+BOX_STRIP_CASES = [
+    ((24, 300, 40), (1.0 / 39, 1.0 / 299, 1.0 / 23), 0, 2.0),
+    ((280, 30, 20), (1.0 / 19, 1.0 / 30, 1.0 / 280), (0, 1, 1), 2.0),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(BOX_STRIP_CASES)))
+def test_every_strided_config_3d(torch_cuda, molt, oracle_mod, case, dtype):
+    torch = torch_cuda
+    shape, h, bc, cfl = BOX_STRIP_CASES[case]
+    plan = molt.Plan(shape, h, bc, P=2, cfl=cfl, dtype=dtype)
+    pb = oracle_mod.Problem(shape, h, bc, plan.info["alpha"], precision="ld")
+    u0 = W.random_field(shape, seed=40 + case, dirichlet_axes=_dirichlet_axes(shape, bc))
+    u1 = pb.start(u0, 2, plan.info["beta"])
+    a, b = pb.run(u0, u1, 2, 2, plan.info["beta"])
+    tol = TOL[dtype] * (1 if dtype == "f64" else 2)
+    tried = 0
+    for k in range(plan.info["kernels_per_step"]):
+        ids, cur = plan.kernel_configs(k)
+        for cfg in ids:
+            plan.set_kernel_config(k, cfg)
+            da, db = dev(torch, u0, dtype), dev(torch, u1, dtype)
+            plan.solve(da, db, 2)
+            torch.cuda.synchronize()
+            check("box %s kernel %d cfg %d" % (shape, k, cfg), host(db), b, dtype, tol)
+            tried += 1
+        plan.set_kernel_config(k, cur)
+    assert tried > 0
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_long_z_lines(torch_cuda, molt, oracle_mod, dtype):
     torch = torch_cuda
