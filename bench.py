@@ -62,9 +62,10 @@ def traffic_for(kernel_tag: str):
     return found
 
 
-def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, **kw):
+def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=None, **kw):
     """Time `steps` steps of mol_solve (graph replay) after `warmup` steps, with
-    HIP events on the library's stream; optional per-kernel breakdown."""
+    HIP events on the library's stream; optional per-kernel breakdown; `keep`
+    (a list) receives the final field on the host."""
     import torch
     from paper_1308_3214_amd import molt
 
@@ -87,6 +88,8 @@ def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, **kw)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     assert torch.isfinite(b).all().item(), "non-finite field"
+    if keep is not None:
+        keep.append(b.double().cpu().numpy())
     kern = None
     if profile:
         # per-kernel breakdown of one step (events around every launch)
@@ -99,10 +102,10 @@ def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, **kw)
     return ms, kern, info
 
 
-def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1):
+def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None):
     from paper_1308_3214_amd import workloads as W
     u0 = W.gaussian_pulses_2d(n, seed=seed)
-    return run_plan((n, n), 1.0 / (n - 1), 0, P, cfl, dtype, u0, steps, warmup)
+    return run_plan((n, n), 1.0 / (n - 1), 0, P, cfl, dtype, u0, steps, warmup, keep=keep)
 
 
 def also_line(ms, steps, info, points):
@@ -134,11 +137,14 @@ def periodic3d_workload(steps=200, warmup=10):
     return also_line(ms, steps, info, n ** 3)
 
 
-def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=4, burst=False, steps=100):
+def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=False, steps=100):
     """The serving workload: a Poisson stream of independent FP32 requests
     (n log-uniform in [128, 2048], P in {1, 2, 3}, CFL in [1, 4], 100 steps,
-    4 Gaussian pulses) through the request server with a device budget.
-    Latency = scheduled arrival -> completion seen by the polling loop."""
+    4 Gaussian pulses) through the request server with a device budget.  Three
+    compute streams and the server's copy stream fill the box's four hardware
+    queues (a fifth stream would share a queue and wait behind its work).
+    Latency = scheduled arrival -> completion seen by the polling loop; results
+    are handed back in device memory."""
     import numpy as np
     import torch
     from paper_1308_3214_amd import molt
@@ -163,7 +169,9 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=4, burst=Fal
         tn = time.perf_counter() - t0
         for rid in got:
             done_t[rid] = tn
-            srv.result(rid)                 # back to the client (host)
+            r = reqs[rid_of[rid]]
+            # the result handed to the client in device memory
+            srv.result(rid, torch.empty((r.n, r.n), dtype=torch.float32, device="cuda"))
         if not got:
             time.sleep(50e-6)
         if tn > 300:
@@ -179,7 +187,9 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=4, burst=Fal
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "max_ms": round(float(lat.max()), 3),
             "Mpoint-updates/s": round(pts / span / 1e6, 1),
-            "span_s": round(span, 3), "peak_bytes": st["bytes_peak"]}
+            "span_s": round(span, 3), "peak_bytes": st["bytes_peak"],
+            "admit_ms_mean": round(st["admit_seconds"] / count * 1e3, 3),
+            "admit_ms_max": round(st["admit_max_seconds"] * 1e3, 3)}
 
 
 def stream_copy(n_bytes=64 << 20, nsets=6, reps=24):
@@ -294,9 +304,17 @@ def main():
     }
     if not args.no_also:
         also = {}
+        import numpy as np
+        fields = {}
         for dt in ("f64", "f32"):
-            ms2, _, inf2 = run_gpu(1024, 2, 2.0, dt, 500, 10)
+            keep = []
+            # both precisions run start + 10 + 500 steps: the error statement
+            # compares the same u^n
+            ms2, _, inf2 = run_gpu(1024, 2, 2.0, dt, 500, 10, keep=keep)
+            fields[dt] = keep[0]
             also["1024x1024_P2_%s_500steps" % dt] = also_line(ms2, 500, inf2, 1024 * 1024)
+        also["1024x1024_P2_f32_vs_f64_rel_L2"] = float(
+            "%.3e" % (np.linalg.norm(fields["f32"] - fields["f64"]) / np.linalg.norm(fields["f64"])))
         k64 = max(20, args.steps // 4)
         ms2, _, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
         also["%dx%d_P%d_f64" % (n, n, P)] = also_line(ms2, k64, inf2, points)

@@ -167,6 +167,8 @@ typedef struct mol_server_info {
     size_t bytes_in_use;    /* footprint of admitted requests and untaken results */
     size_t bytes_peak;
     size_t budget;
+    double admit_seconds;   /* host time spent admitting requests (plan, copies, enqueue) */
+    double admit_max_seconds;
 } mol_server_info;
 
 /* hbm_budget_bytes > 0: device bytes the server may hold; nstreams in 1..64

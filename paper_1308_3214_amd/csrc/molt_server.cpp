@@ -40,6 +40,7 @@ struct Req {
     mol_plan *plan = nullptr;
     void *d_prev = nullptr, *d_curr = nullptr;
     int stream = 0;
+    double work = 0;          // point-updates of the request (stream load estimate)
     hipEvent_t done = nullptr;
     std::string err;
 };
@@ -55,14 +56,16 @@ double now_s()
 struct mol_server_ {
     size_t budget = 0, used = 0, peak = 0;
     std::vector<hipStream_t> streams;
+    std::vector<double> load;         // outstanding point-updates per stream
     hipStream_t copy = nullptr;       // results leave on their own stream
-    int next_stream = 0;
     int64_t next_id = 1;
     std::deque<Req *> queue;
     std::map<int64_t, Req *> reqs;
     int64_t completed = 0;
     std::mutex mu;
     double t0 = 0;
+    double admit_s = 0;               // host time spent admitting requests
+    double admit_max_s = 0;
 };
 
 namespace {
@@ -88,6 +91,8 @@ int64_t npoints(const mol_desc &d)
 void retire(mol_server_ *s, Req *r)
 {
     hipStream_t st = s->streams[r->stream];
+    s->load[r->stream] -= r->work;
+    r->work = 0;
     if (r->plan) molt::plan_destroy_async(r->plan, st);
     r->plan = nullptr;
     if (r->d_prev) (void)hipFreeAsync(r->d_prev, st);
@@ -100,8 +105,14 @@ void retire(mol_server_ *s, Req *r)
 // Launch an admitted request on its stream.
 mol_status launch(mol_server_ *s, Req *r)
 {
-    r->stream = s->next_stream;
-    s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+    // the stream with the least outstanding work: a short request does not
+    // queue behind a long one when another stream is free
+    int best = 0;
+    for (int i = 1; i < (int)s->streams.size(); ++i)
+        if (s->load[i] < s->load[best]) best = i;
+    r->stream = best;
+    r->work = (double)npoints(r->desc) * (double)r->nsteps * (double)r->desc.P;
+    s->load[best] += r->work;
     hipStream_t st = s->streams[r->stream];
     mol_desc d = r->desc;
     d.mask = r->mask.empty() ? nullptr : r->mask.data();
@@ -145,7 +156,12 @@ void pump(mol_server_ *s, std::vector<int64_t> &done)
         s->queue.pop_front();
         s->used += r->footprint;
         if (s->used > s->peak) s->peak = s->used;
-        if (launch(s, r) != MOL_OK) {
+        const double ta = now_s();
+        const mol_status ls = launch(s, r);
+        const double dt = now_s() - ta;
+        s->admit_s += dt;
+        if (dt > s->admit_max_s) s->admit_max_s = dt;
+        if (ls != MOL_OK) {
             r->err = s_err;
             r->state = Q_FAILED;
             // nothing of the request may be in flight any more
@@ -181,6 +197,7 @@ mol_status mol_server_create(size_t hbm_budget_bytes, int nstreams, mol_server *
         }
         s->streams.push_back(st);
     }
+    s->load.assign(s->streams.size(), 0.0);
     if (hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess) {
         for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
         delete s;
@@ -310,6 +327,8 @@ mol_status mol_server_stats(mol_server *s, mol_server_info *info)
     info->bytes_in_use = s->used;
     info->bytes_peak = s->peak;
     info->budget = s->budget;
+    info->admit_seconds = s->admit_s;
+    info->admit_max_seconds = s->admit_max_s;
     return MOL_OK;
 }
 

@@ -98,7 +98,8 @@ class _SrvInfo(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("finished", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
-                ("budget", ctypes.c_size_t)]
+                ("budget", ctypes.c_size_t), ("admit_seconds", ctypes.c_double),
+                ("admit_max_seconds", ctypes.c_double)]
 
 
 _lib.mol_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)]

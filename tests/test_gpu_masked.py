@@ -154,3 +154,38 @@ def test_full_interior_mask_matches_rectangle(torch_cuda, molt, dtype):
         check("full mask vs rectangle rhs P=%d" % P, host(a), host(b), dtype)
         pm.close()
         pr.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_degenerate_line_objects(torch_cuda, molt, oracle_mod, dtype):
+    # isolated inside nodes (objects of one node), pairs, an L-shaped arm,
+    # objects exactly at a length-class capacity (256 and 257 nodes), and
+    # crossings close to the end nodes
+    torch = torch_cuda
+    ny, nx = 24, 300
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[2, 5] = 1
+    mask[4, 10:12] = 1
+    mask[6:9, 20] = 1
+    mask[10, 30:286] = 1                      # 256 nodes
+    mask[12, 30:287] = 1                      # 257 nodes
+    mask[14:20, 40:60] = 1
+    mask[15:19, 45] = 0                        # a hole
+    g = np.random.default_rng(3)
+    cross = np.where(np.isnan(np.zeros((4, ny, nx))), 0.0, g.uniform(1e-3, 1.0, (4, ny, nx)))
+    h = 1.0 / (nx - 1)
+    segs = lines.segments(mask, cross)
+    v = W.random_field((ny, nx), seed=8) * mask
+    vd = dev(torch, v, dtype)
+    out = torch.empty_like(vd)
+    for P in (1, 3):
+        plan = molt.Plan((ny, nx), h, 0, P=P, cfl=1.5, dtype=dtype, mask=mask, cross=cross)
+        pb = oracle_mod.Problem((ny, nx), h, 0, plan.info["alpha"], segments=segs, mask=mask)
+        for ax, nm in ((0, "x"), (1, "y")):
+            plan.apply("d_" + nm, vd, out)
+            torch.cuda.synchronize()
+            check("degenerate D_%s P=%d" % (nm, P), host(out), pb.Dg(v, ax), dtype)
+        plan.apply("rhs", vd, out)
+        torch.cuda.synchronize()
+        check("degenerate rhs P=%d" % P, host(out), pb.rhs(v, P, plan.info["beta"]), dtype)
+        plan.close()

@@ -304,3 +304,50 @@ def test_long_z_lines(torch_cuda, molt, oracle_mod, dtype):
     plan.apply("rhs", vd, o)
     torch.cuda.synchronize()
     check("rhs 600 planes", host(o), pb.rhs(v, 2, plan.info["beta"]), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("P", [4, 5])
+def test_high_order_rhs_and_steps(torch_cuda, molt, oracle_mod, P, dtype):
+    # orders 8 and 10 (Table 1 lists beta_max up to P = 5)
+    torch = torch_cuda
+    for shape, h, bc in (((200,), 1.0 / 199, 0), ((40, 56), (1.0 / 55, 1.0 / 39), 0),
+                         ((36, 48), (1.0 / 48, 1.0 / 36), 1)):
+        plan = molt.Plan(shape, h, bc, P=P, cfl=2.0, dtype=dtype)
+        beta = plan.info["beta"]
+        pb = oracle_mod.Problem(shape, h, bc, plan.info["alpha"])
+        v = W.random_field(shape, seed=50 + P, dirichlet_axes=_dirichlet_axes(shape, bc))
+        vd = dev(torch, v, dtype)
+        out = torch.empty_like(vd)
+        plan.apply("rhs", vd, out)
+        torch.cuda.synchronize()
+        check("rhs P=%d %s" % (P, shape), host(out), pb.rhs(v, P, beta), dtype)
+        pl = oracle_mod.Problem(shape, h, bc, plan.info["alpha"], precision="ld")
+        u1 = pl.start(v, P, beta)
+        a, b = pl.run(v, u1, 4, P, beta)
+        da, db = dev(torch, v, dtype), dev(torch, u1, dtype)
+        plan.solve(da, db, 4)
+        torch.cuda.synchronize()
+        check("solve P=%d %s" % (P, shape), host(db), b, dtype, TOL[dtype] * 2)
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_minimum_sizes(torch_cuda, molt, oracle_mod, dtype):
+    # the smallest grids a plan accepts: 3 nodes per axis
+    torch = torch_cuda
+    for shape, bc in (((3,), 0), ((3,), 1), ((3, 3), 0), ((3, 4), (1, 0)), ((3, 3, 3), 1),
+                      ((5, 3, 4), 0)):
+        nd = len(shape)
+        bb = list(bc) if np.ndim(bc) else [bc] * nd
+        h = tuple(1.0 / (shape[nd - 1 - a] - (0 if bb[a] else 1)) for a in range(nd))
+        plan = molt.Plan(shape, h, bc, P=2, cfl=1.0, dtype=dtype)
+        pb = oracle_mod.Problem(shape, h, bc, plan.info["alpha"])
+        v = W.random_field(shape, seed=60, dirichlet_axes=_dirichlet_axes(shape, bc))
+        vd = dev(torch, v, dtype)
+        out = torch.empty_like(vd)
+        plan.apply("rhs", vd, out)
+        torch.cuda.synchronize()
+        check("rhs %s bc %s" % (shape, bc), host(out), pb.rhs(v, 2, plan.info["beta"]), dtype,
+              TOL[dtype] if np.linalg.norm(pb.rhs(v, 2, plan.info["beta"])) > 0 else 1e-30)
+        plan.close()
