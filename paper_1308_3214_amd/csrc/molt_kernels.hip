@@ -50,7 +50,6 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
     k.g = (T)dc.g;
     k.w2 = (T)dc.w2;
     k.gw = (T)(dc.g + dc.w2);
-    for (int j = 0; j < 33; ++j) k.dpow[j] = (T)std::exp(-dc.nu * (double)j);
     k.chain = op.chain;
     k.ochain = op.chain ? static_cast<T *>(optr[op.no]) : nullptr;
     k.nu = dc.nu;

@@ -24,7 +24,6 @@ struct SegArgs {
     int64_t seg0;        // first record of this launch
     int64_t pstride;     // element stride along the line
     T d, g, w2, gw, dS, dBlk;
-    T dpow[33];
     double nu;
 };
 
@@ -200,7 +199,7 @@ k_seg_sweep(const SegArgs<T> a)
         const double A = (-IRa + rec.c[SEG_MU] * ILb) * rec.c[SEG_INV];
         const double B = (-ILb + rec.c[SEG_MU] * IRa) * rec.c[SEG_INV];
         seg_close_fast<T, S>(sum[k], cL[k], cR[k], A * rec.c[SEG_EA], B * rec.c[SEG_EB], p0, m - 1,
-                             a.nu, d, a.dpow, false);
+                             a.nu, d, false);
     }
     __syncthreads();                                 // every read of the swept data is done
 #pragma unroll
@@ -364,7 +363,6 @@ hipError_t seg_sweep_t(const SweepOp &op, const SegTable &tab, const DirCoef &dc
     k.g = (T)dc.g;
     k.w2 = (T)dc.w2;
     k.gw = (T)(dc.g + dc.w2);
-    for (int j = 0; j < 33; ++j) k.dpow[j] = (T)std::exp(-dc.nu * (double)j);
     k.nu = dc.nu;
     const int nsno = op.ns * 10 + op.no;
     for (int c = 0; c < NSEGCLS; ++c) {
