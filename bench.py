@@ -102,10 +102,11 @@ def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=
     return ms, kern, info
 
 
-def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None):
+def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None, flags=0):
     from paper_1308_3214_amd import workloads as W
     u0 = W.gaussian_pulses_2d(n, seed=seed)
-    return run_plan((n, n), 1.0 / (n - 1), 0, P, cfl, dtype, u0, steps, warmup, keep=keep)
+    return run_plan((n, n), 1.0 / (n - 1), 0, P, cfl, dtype, u0, steps, warmup, keep=keep,
+                    flags=flags)
 
 
 def also_line(ms, steps, info, points):
@@ -315,6 +316,15 @@ def main():
             also["1024x1024_P2_%s_500steps" % dt] = also_line(ms2, 500, inf2, 1024 * 1024)
         also["1024x1024_P2_f32_vs_f64_rel_L2"] = float(
             "%.3e" % (np.linalg.norm(fields["f32"] - fields["f64"]) / np.linalg.norm(fields["f64"])))
+        # the same workload with the two y sweeps of a step in separate launches
+        # (v1 = C u written and read back): 11 field passes instead of 9
+        from paper_1308_3214_amd import molt as _m
+        ms2, kern2, inf2 = run_gpu(n, P, args.cfl, args.dtype, args.steps, args.warmup,
+                                   flags=_m.SPLIT_Y)
+        sp = also_line(ms2, args.steps, inf2, points)
+        sp["kernels"] = [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
+                          "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kern2]
+        also["%dx%d_P%d_%s_split_y" % (n, n, P, args.dtype)] = sp
         k64 = max(20, args.steps // 4)
         ms2, _, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
         also["%dx%d_P%d_f64" % (n, n, P)] = also_line(ms2, k64, inf2, points)

@@ -57,7 +57,9 @@ typedef enum { MOL_F64 = 0, MOL_F32 = 1 } mol_dtype;
 enum {
     MOL_ALLOW_UNSTABLE = 1,   /* accept beta > beta_max(P) */
     MOL_INCREMENT_FORM = 2,   /* mol_solve carries du = u^n - u^{n-1} instead of u^{n-1} */
-    MOL_NO_GRAPH = 4          /* mol_solve launches kernels directly instead of a hipGraph */
+    MOL_NO_GRAPH = 4,         /* mol_solve launches kernels directly instead of a hipGraph */
+    MOL_SPLIT_Y = 8           /* mol_solve (2D, P = 2) sweeps y twice in two launches instead of
+                                 one chained launch (same operator; for comparisons) */
 };
 
 /* Problem descriptor (Sec. 2: domain, c, dt, beta; Sec. 3: order P;

@@ -47,6 +47,11 @@ struct SweepOp {
     int proj = 0;        // write 0 on every Dirichlet boundary node of the outputs
     int chain = 0;       // x sweeps: also write D_x(out_0) to buffer ochain
     int ochain = -1;
+    // chained strided sweep (yy = 1): v1 = sum mE1 f + D(sum mS[0] f), y = D v1,
+    // out_o = sum mOF[o] f + mV[o] v1 + mOD[o][0] y
+    int yy = 0;
+    double mE1[MAXF] = {};
+    double mV[MAXO] = {};
 };
 
 // Geometry of a full box grid (x fastest).
@@ -66,11 +71,10 @@ hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, boo
 // Per-direction launch configuration chosen by the plan: cfg[0] = variant id.
 // Strided sweeps: ids below config_count_tiled() are the tile kernel, the
 // rest the pipelined strip kernel.
-int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
-                   int *cfg);
-bool config_valid(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
-                  const int *cfg);
-int config_count(int dir);
+// Chained strided sweeps have their own configuration ids.
+int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64, int *cfg);
+bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64, const int *cfg);
+int config_count(const SweepOp &op);
 
 // Elementwise a*x + b*y -> z on n values (state conversion for the increment form).
 hipError_t launch_axpby(bool fp64, int64_t n, double a, const void *x, double b, const void *y,

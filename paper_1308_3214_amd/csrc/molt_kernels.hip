@@ -30,6 +30,24 @@ int max_lds()
     return g_max_lds;
 }
 
+// strips per line: the configuration's workgroup target over the column
+// groups, at least two sub-tiles per strip
+int64_t strips_for(const PCfg &c, int64_t Tt, int64_t groups)
+{
+    int64_t ns = (c.target + groups - 1) / groups;
+    if (ns > Tt / 2) ns = Tt / 2;
+    if (ns < 1) ns = 1;
+    return ns;
+}
+
+// rows of data next to a strip in a chained walk: K + 5 rounded up to whole
+// waves (roll d^roll below the rounding)
+int yy_roll(const DirCoef &dc, int S)
+{
+    const int64_t r = ((int64_t)dc.halo + 5 + S - 1) / S * S;
+    return r > (int64_t)1 << 30 ? 1 << 30 : (int)r;
+}
+
 template <typename T>
 void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *const *fptr,
                  void *const *optr)
@@ -41,7 +59,9 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
     for (int o = 0; o < MAXO; ++o) {
         for (int f = 0; f < MAXF; ++f) k.mOF[o][f] = (T)op.mOF[o][f];
         for (int s = 0; s < MAXS; ++s) k.mOD[o][s] = (T)op.mOD[o][s];
+        k.mV[o] = (T)op.mV[o];
     }
+    for (int f = 0; f < MAXF; ++f) k.mE1[f] = (T)op.mE1[f];
     k.nf = op.nf;
     k.proj = op.proj;
     k.n = dc.n;
@@ -116,14 +136,31 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
     k.halo = dc.halo;
     const int64_t ncg = (g.n[0] + 63) / 64;
     const bool small = op.nf <= 4;
+    if (op.yy) {
+        if constexpr (sizeof(T) == 4) {
+            const PCfg c = kYCfg[cfg[0]];
+            const int64_t WS = (int64_t)c.S * c.W;
+            const int64_t Tt = (dc.n + WS - 1) / WS;
+            k.ntiles = (int)strips_for(c, Tt, ncg * k.nouter);
+            k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
+            k.dS = (T)exp(-dc.nu * c.S);
+            k.dBlk = k.dS;
+            k.roll = yy_roll(dc, c.S);
+            const double m00 = op.mOD[0][0];
+            k.ykv = (T)(op.mV[0] / m00);
+            k.yk0 = (T)(1.0 / m00);
+            k.ykh = op.no > 1 ? (T)(op.mV[1] - op.mOD[1][0] * op.mV[0] / m00) : T(0);
+            return dispatch_yy_f32(k, op.no, cfg[0], st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (cfg[0] >= NSCFG) {
         // pipelined strips
         const PCfg c = kPCfg[cfg[0] - NSCFG];
         const int64_t WS = (int64_t)c.S * c.W;
         const int64_t Tt = (dc.n + WS - 1) / WS;
-        int64_t ns_ = (c.target + ncg * k.nouter - 1) / (ncg * k.nouter);
-        if (ns_ > Tt / 2) ns_ = Tt / 2;
-        if (ns_ < 1) ns_ = 1;
+        const int64_t ns_ = strips_for(c, Tt, ncg * k.nouter);
         k.ntiles = (int)ns_;
         k.nblocks = ns_ * ncg * k.nouter;
         k.dS = (T)exp(-dc.nu * c.S);
@@ -153,10 +190,31 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
 
 }  // namespace
 
-bool config_valid(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
-                  const int *cfg)
+bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64, const int *cfg)
 {
+    const int dir = op.dir, nf = op.nf, ns = op.ns, no = op.no;
     const size_t es = fp64 ? 8 : 4;
+    if (op.yy) {
+        // chained strided sweeps (FP32): at most 3 fields, one swept
+        // combination, field terms only in the last output, a walk whose
+        // data rows next to a strip fit one sub-tile, lines of at least two
+        // sub-tiles (periodic: rows formed stay within one wrap), 32-bit
+        // buffer offsets over the rows walked
+        if (fp64 || dir == 0 || op.proj || op.chain) return false;
+        if (nf < 1 || nf > 3 || ns != 1 || no < 1 || no > 2) return false;
+        if (op.mOD[0][0] == 0.0) return false;     // output 0 is folded into the y sums
+        for (int o = 0; o + 1 < no; ++o)
+            for (int f = 0; f < MAXF; ++f)
+                if (op.mOF[o][f] != 0.0) return false;
+        if (cfg[0] < 0 || cfg[0] >= NYCFG) return false;
+        const PCfg c = kYCfg[cfg[0]];
+        const int64_t WS = (int64_t)c.S * c.W;
+        if (yy_roll(dc, c.S) > WS) return false;
+        if (dc.n < 2 * WS + (dc.periodic ? 2 : 0)) return false;
+        const int64_t ls = dir == 1 ? g.n[0] : g.n[0] * g.n[1];
+        if ((dc.n + 3 * WS + 8) * ls * (int64_t)es + 64 * (int64_t)es >= ((int64_t)1 << 31)) return false;
+        return true;
+    }
     if (!((ns == 1 && (no == 1 || no == 2)) || (ns == 2 && (no == 2 || no == 3)))) return false;
     if (dir == 0) {
         if (cfg[0] < 0 || cfg[0] >= NXCFG) return false;
@@ -183,9 +241,18 @@ bool config_valid(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, 
     return true;
 }
 
-int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf, int ns, int no,
-                   int *cfg)
+int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64, int *cfg)
 {
+    const int dir = op.dir, nf = op.nf, ns = op.ns, no = op.no;
+    (void)nf;
+    (void)no;
+    if (op.yy) {
+        for (int i = 0; i < NYCFG; ++i) {
+            cfg[0] = i;
+            if (config_valid(g, dc, op, fp64, cfg)) return 0;
+        }
+        return -1;
+    }
     if (dir == 0) {
         const int64_t n = g.n[0];
         // smallest line capacity that holds the line, preferring 16 nodes/lane
@@ -197,7 +264,7 @@ int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf,
         for (int i = 0; i < cnt; ++i) {
             cfg[0] = ord[i];
             const XCfg c = kXCfg[cfg[0]];
-            if (64 * c.WPL * c.S >= n && config_valid(g, dc, dir, fp64, nf, ns, no, cfg)) return 0;
+            if (64 * c.WPL * c.S >= n && config_valid(g, dc, op, fp64, cfg)) return 0;
         }
         return -1;
     }
@@ -210,20 +277,20 @@ int default_config(const Geom &g, const DirCoef &dc, int dir, bool fp64, int nf,
         const PCfg c = kPCfg[cfg[0] - NSCFG];
         const int64_t tiles = (dc.n + (int64_t)c.S * c.W - 1) / ((int64_t)c.S * c.W);
         const int64_t groups = ((g.n[0] + 63) / 64) * (dir == 1 ? g.n[2] : g.n[1]);
-        if (groups * (tiles / 2) >= 256 && config_valid(g, dc, dir, fp64, nf, ns, no, cfg)) return 0;
+        if (groups * (tiles / 2) >= 256 && config_valid(g, dc, op, fp64, cfg)) return 0;
     }
     const int regs = (2 * ns + no) * (fp64 ? 2 : 1);
     cfg[0] = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
-    return config_valid(g, dc, dir, fp64, nf, ns, no, cfg) ? 0 : -1;
+    return config_valid(g, dc, op, fp64, cfg) ? 0 : -1;
 }
 
-int config_count(int dir) { return dir == 0 ? NXCFG : NSCFG + NPCFG; }
+int config_count(const SweepOp &op) { return op.yy ? NYCFG : op.dir == 0 ? NXCFG : NSCFG + NPCFG; }
 
 hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
                         const void *const *fptr, void *const *optr, const int *cfg,
                         hipStream_t st)
 {
-    if (!config_valid(g, dc, op.dir, fp64, op.nf, op.ns, op.no, cfg)) return hipErrorInvalidValue;
+    if (!config_valid(g, dc, op, fp64, cfg)) return hipErrorInvalidValue;
     return fp64 ? launch_t<double>(op, g, dc, fptr, optr, cfg, st)
                 : launch_t<float>(op, g, dc, fptr, optr, cfg, st);
 }

@@ -212,7 +212,7 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
 
         // does a configuration exist? else split two combos into two launches
         int cfg[2] = {0, 0};
-        if (!pl.masked && default_config(pl.geom, pl.dc[dir], dir, pl.fp64, op.nf, ns, no, cfg) != 0) {
+        if (!pl.masked && default_config(pl.geom, pl.dc[dir], op, pl.fp64, cfg) != 0) {
             if (ns == 2) {
                 std::vector<OutSpec> o0, o1;
                 for (const OutSpec &o : outs) {
@@ -242,8 +242,7 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
             const std::string key = tune_op_key(op);
             for (const auto &t : pl.tuned) {
                 int c[2] = {t.second, 0};
-                if (t.first == key &&
-                    config_valid(pl.geom, pl.dc[dir], dir, pl.fp64, op.nf, ns, no, c))
+                if (t.first == key && config_valid(pl.geom, pl.dc[dir], op, pl.fp64, c))
                     cfg[0] = t.second;
             }
         }
@@ -254,6 +253,84 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
         prog.push_back(po);
         return true;
     }
+
+bool Builder::yy_available(int dir, int nf, int no) const
+{
+    if (pl.masked) return false;
+    SweepOp op;
+    op.dir = dir;
+    op.yy = 1;
+    op.nf = nf;
+    op.ns = 1;
+    op.no = no;
+    op.mOD[0][0] = 1.0;
+    int cfg[2] = {0, 0};
+    return default_config(pl.geom, pl.dc[dir], op, pl.fp64, cfg) == 0;
+}
+
+bool Builder::emit_yy(Program &prog, int dir, const Lin &s1, const Lin &e1,
+                      const std::vector<std::pair<int, Lin>> &outs)
+{
+    SweepOp op;
+    op.dir = dir;
+    op.yy = 1;
+    op.ns = 1;
+    op.no = (int)outs.size();
+    if (op.no < 1 || op.no > MAXO) {
+        err = "internal: launch shape";
+        return false;
+    }
+    std::vector<int> fields;
+    auto fid = [&](int b) -> int {
+        for (size_t i = 0; i < fields.size(); ++i)
+            if (fields[i] == b) return (int)i;
+        fields.push_back(b);
+        return (int)fields.size() - 1;
+    };
+    for (auto &t : s1) {
+        const int i = fid(t.first);
+        if (i < MAXF) op.mS[0][i] += t.second;
+    }
+    for (auto &t : e1) {
+        const int i = fid(t.first);
+        if (i < MAXF) op.mE1[i] += t.second;
+    }
+    for (int o = 0; o < op.no; ++o) {
+        op.o[o] = outs[o].first;
+        for (auto &t : outs[o].second) {
+            if (t.first == V1) {
+                op.mV[o] += t.second;
+            } else if (t.first == Y) {
+                op.mOD[o][0] += t.second;
+            } else {
+                const int i = fid(t.first);
+                if (i < MAXF) op.mOF[o][i] += t.second;
+            }
+        }
+    }
+    if ((int)fields.size() > MAXF) {
+        err = "schedule needs more fields per launch than supported (lower P)";
+        return false;
+    }
+    op.nf = (int)fields.size();
+    for (int i = 0; i < op.nf; ++i) op.f[i] = fields[i];
+    int cfg[2] = {0, 0};
+    if (default_config(pl.geom, pl.dc[dir], op, pl.fp64, cfg) != 0) {
+        err = "internal: no chained configuration";
+        return false;
+    }
+    const std::string key = tune_op_key(op);
+    for (const auto &t : pl.tuned) {
+        int c[2] = {t.second, 0};
+        if (t.first == key && config_valid(pl.geom, pl.dc[dir], op, pl.fp64, c)) cfg[0] = t.second;
+    }
+    ProgOp po;
+    po.op = op;
+    po.cfg[0] = cfg[0];
+    po.cfg[1] = cfg[1];
+    prog.push_back(po);
+    return true;
+}
 
 std::vector<OutSpec> finals(const std::vector<FinalOut> &fo, const Lin &rhs_elem, double rhs_dcoef)
 {
@@ -302,6 +379,26 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
     std::vector<int> v{u};      // inputs of the current stage
     int accbuf = -1;            // accumulated earlier-stage terms (stage >= 3)
     int pfirst = 1;
+    if (chain_a >= 0 && P == 2 && nd == 2 && fo.size() == 1 &&
+        !(pl.desc.flags & MOL_SPLIT_Y) && b.yy_available(1, 3, 2)) {
+        // 2D, P = 2: both y sweeps of the step in one launch.  v1 = C u =
+        // D_y(u - 2a) + a and y = D_y v1 stay on chip; the launch writes the
+        // x sweep's combination G = c22 (v1 - 2y) + c21 (v1 - y) and its
+        // elementwise part H = elem + r (c11 v1 + (c22 + c21) y).
+        const int V1 = Builder::V1, Y = Builder::Y;
+        const double c11 = stage_c(1, 1, beta), c22 = stage_c(2, 2, beta), c21 = stage_c(2, 1, beta);
+        const Lin gs = c22 * (lin(V1) + lin(Y, -2.0)) + c21 * (lin(V1) + lin(Y, -1.0));
+        const Lin hs = lin(V1, c11) + c22 * lin(Y) + c21 * lin(Y);
+        const int G = b.new_ws(), H = b.new_ws();
+        if (!b.emit_yy(prog, 1, lin(u) + lin(chain_a, -2.0), lin(chain_a),
+                       {{G, gs}, {H, fo[0].elem + fo[0].r * hs}}))
+            return false;
+        OutSpec o{};
+        o.buf = fo[0].buf;
+        o.elem = lin(H);
+        o.dc[0] = fo[0].r;
+        return b.emit(prog, 0, {lin(G)}, {o}, 1, chain_a);
+    }
     if (chain_a >= 0) {
         // 2D, P >= 2: stage 1 in the order x then y, with a = D_x u written by
         // the previous step's last sweep: C u = D_y(u - 2a) + a
@@ -518,6 +615,7 @@ std::string tune_op_key(const SweepOp &op)
 {
     std::ostringstream o;
     o << "dir" << op.dir << " nf" << op.nf << " ns" << op.ns << " no" << op.no << " ch" << op.chain;
+    if (op.yy) o << " yy";
     return o.str();
 }
 
@@ -1002,7 +1100,7 @@ mol_status mol_profile_step(mol_plan *pl, const void *u_prev, const void *u_curr
         if (ms) ms[i] = tot / reps;
         if (bytes) bytes[i] = (double)(op.nf + op.no + op.chain) * (double)pl->npts * (double)pl->es;
         if (dir) dir[i] = op.dir;
-        if (nsweep) nsweep[i] = op.ns;
+        if (nsweep) nsweep[i] = op.yy ? 2 : op.ns;
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
     return e == hipSuccess ? MOL_OK : dev_err(e, "mol_profile_step");
@@ -1017,9 +1115,9 @@ mol_status mol_plan_kernel_configs(const mol_plan *pl, int kernel, int *ids, int
     const SweepOp &op = sp[kernel].op;
     int cnt = 0;
     if (!pl->masked) {
-        for (int c = 0; c < config_count(op.dir); ++c) {
+        for (int c = 0; c < config_count(op); ++c) {
             int cf[2] = {c, 0};
-            if (!config_valid(pl->geom, pl->dc[op.dir], op.dir, pl->fp64, op.nf, op.ns, op.no, cf))
+            if (!config_valid(pl->geom, pl->dc[op.dir], op, pl->fp64, cf))
                 continue;
             if (ids && cnt < max) ids[cnt] = c;
             ++cnt;
@@ -1038,7 +1136,7 @@ mol_status mol_plan_set_kernel_config(mol_plan *pl, int kernel, int config)
     if (kernel < 0 || kernel >= (int)sp.size()) return fail(MOL_E_INVALID, "kernel index out of range");
     const SweepOp ref = sp[kernel].op;
     int cf[2] = {config, 0};
-    if (!config_valid(pl->geom, pl->dc[ref.dir], ref.dir, pl->fp64, ref.nf, ref.ns, ref.no, cf))
+    if (!config_valid(pl->geom, pl->dc[ref.dir], ref, pl->fp64, cf))
         return fail(MOL_E_INVALID, "configuration not valid for this kernel");
     const std::string key = tune_op_key(ref);
     for (Program *pr : {&pl->step, &pl->start, &pl->inc_step, &pl->solve_pro, &pl->solve_step,

@@ -96,6 +96,13 @@ struct Builder {
     // one directional launch: combos = swept combinations, outs = outputs
     bool emit(Program &prog, int dir, const std::vector<Lin> &combos,
               const std::vector<OutSpec> &outs, int proj, int chain_buf = -1);
+
+    // chained strided launch: v1 = e1 + D s1, y = D v1 along direction dir;
+    // output expressions may name the two results through the ids V1 and Y
+    static constexpr int V1 = -2, Y = -3;
+    bool yy_available(int dir, int nf, int no) const;
+    bool emit_yy(Program &prog, int dir, const Lin &s1, const Lin &e1,
+                 const std::vector<std::pair<int, Lin>> &outs);
 };
 
 // How the right-hand side sum_{p,m} c_{p,m} C^m D^{p-m} u is consumed: each

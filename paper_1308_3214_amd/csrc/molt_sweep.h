@@ -89,6 +89,15 @@ struct KArgs {
     // projection: line index = (i1 in [0,pn1), i2 in [0,pn2)); Dirichlet flags
     int64_t pn1, pn2;
     int pd1, pd2;
+    // chained strided sweeps: field terms of the first-level result v1, weight
+    // of v1 in each output, rows of data next to a strip in its walk
+    T mE1[MAXF];
+    T mV[MAXO];
+    int roll;
+    // fold of output 0 into the second-level sums: ykv = mV[0] / mOD[0][0],
+    // yk0 = 1 / mOD[0][0] (field terms of a single output), ykh = mV[1] -
+    // mOD[1][0] mV[0] / mOD[0][0] (weight of v1 left in output 1)
+    T ykv, yk0, ykh;
 };
 
 // ---------------------------------------------------------------------------
@@ -1368,6 +1377,319 @@ k_sweep_p(const KArgs<T> a)
 }
 
 // ---------------------------------------------------------------------------
+// chained strided sweep: v1 = e1 + D s1 and y = D v1 along the same lines in
+// one strip walk (2D: the two y sweeps of a step, stage 1 and stage 2)
+// ---------------------------------------------------------------------------
+// Level 1 is the strip recurrence above applied to s1 = sum_c mS[0][c] f_c; it
+// yields v1 = sum_c mE1[c] f_c + D s1 one sub-tile at a time.  Level 2 runs the
+// same recurrence on v1 two sub-tiles behind level 1 (its backward carry needs
+// the next sub-tile's aggregate), so v1 never leaves the chip.  The outputs are
+// out_o = fp_o + mV[o] v1 + mOD[o][0] y with fp_o = sum_c mOF[o][c] f_c (only the
+// last output may have field terms).  Output 0 is folded into the level-2 sums
+// (y' = y + (fp_0 +) mV[0] v1 / mOD[0][0], out_0 = mOD[0][0] y'), so a level-2
+// sub-tile keeps two values per row.
+//
+// v1 one row below a sub-tile (needed by the forcing of its last row) is taken
+// before that row's own sub-tile is finished: its forward carry is exact and
+// its backward carry is the look-ahead aggregate, the same truncation
+// (d^WS <= d^K) as the backward carries themselves.  A strip is walked with one
+// sub-tile before and after it where it has neighbours; of those, only `roll`
+// rows next to the strip hold data (the rest read 0), with zero carries at the
+// walk's ends: level 1 is then exact to d^roll at the strip's first and last
+// rows, level 2 to roll * d^roll, both below the rounding (roll >= K + 5).
+// Periodic lines are walked as the periodic continuation (rows wrap on load);
+// they have no end node.
+template <typename T, int S, int NO>
+struct YYLev1 {
+    T sum[S];      // local sums less e1: the closure yields v1 directly
+    T fp[S];       // field terms of the last output
+    T aL, aR, eLM;
+};
+template <typename T, int S, int NO>
+struct YYLev2 {
+    T sum[S];      // local sums less the folded part of output 0
+    T gH[S];       // output 1 without its y term (two outputs)
+    T aL, aR, eLM;
+};
+
+template <typename T, int S, int W, int NO, bool PER, int NFP>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_yy(const KArgs<T> a)
+{
+    static_assert(W >= 4, "the carry scans take waves 0..3");
+    constexpr int WS = W * S;
+    __shared__ T agg1[3][2][W][64], agg2[3][2][W][64];   // aL, aR of every wave
+    __shared__ T cLs1[W][64], cRs1[W][64], cLs2[W][64], cRs2[W][64];
+    __shared__ T vfirst[W][64], vlast[W][64];     // v1 at the first / last row of every wave
+    __shared__ T ctopS1[64], er0S1[64], agS1[64], ctopS2[64], er0S2[64];
+    __shared__ T endv1[64], endv2[64], peekS[2][64];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nstrips = a.ntiles;
+    const int64_t L = blockIdx.x;
+    const int strip = (int)(L % nstrips);
+    const int64_t rest = L / nstrips;
+    const int64_t ncg = (a.nlines + 63) / 64;
+    const int64_t cg = rest % ncg;
+    const int64_t outer = rest / ncg;
+    const int col = (int)(cg * 64) + lane;
+    const bool active = col < a.nlines;
+    const int n = (int)a.n;
+    constexpr bool dir_end = !PER;
+    const int M = PER ? (1 << 30) : n - 1;     // no end node on a periodic line
+    const int64_t ls = a.ls;
+    const int64_t blk = cg * 64 + outer * a.os;
+    const unsigned lo = active ? (unsigned)lane : 0u;
+    const T d = a.d, w2 = a.w2, gw = a.gw, dS = a.dS;
+
+    // output sub-tiles [t0, t0 + R) of this strip inside a walk of Rw sub-tiles
+    const int Tt = (n + WS - 1) / WS;
+    const int base = Tt / nstrips, extra = Tt % nstrips;
+    const int t0 = strip * base + (strip < extra ? strip : extra);
+    const int R = base + (strip < extra ? 1 : 0);
+    const int s0 = t0 * WS, se = (t0 + R) * WS;
+    const int pre = (PER || s0 > 0) ? 1 : 0;
+    const int post = (PER || se < n) ? 1 : 0;
+    const int Rw = pre + R + post;
+    const int wst = s0 - pre * WS;               // first row of the walk
+    const int rlo = pre ? s0 - a.roll : -(1 << 30);
+    const int rhi = post ? se + a.roll : (1 << 30);
+
+    // buffer resources over the n rows of this column group: rows outside the
+    // line (Dirichlet) and rows outside [rlo, rhi) read 0; the host keeps every
+    // offset formed here below 2^31 bytes
+    const int rowb = (int)(ls * (int64_t)sizeof(T));
+    const int lineb = n * rowb;
+    const int vl = (int)lo * (int)sizeof(T);
+    __amdgpu_buffer_rsrc_t rsf[NFP];
+#pragma unroll
+    for (int c = 0; c < NFP; ++c)
+        rsf[c] = make_rsrc(c < a.nf ? a.f[c] + blk : a.f[0] + blk, c < a.nf ? lineb : 0);
+    __amdgpu_buffer_rsrc_t rso[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) rso[o] = make_rsrc(a.o[o] + blk, lineb);
+    auto wrap = [&](int p) -> int {
+        if (PER) {
+            if (p < 0) p += n;
+            if (p >= n) p -= n;
+        }
+        return p;
+    };
+
+    typedef T Raw[NFP][S + 2];
+    Raw xa, xb;
+    // loads of sub-tile t (none beyond the walk).  Issued without a branch: a
+    // load under a branch makes the compiler wait for it where the branch
+    // rejoins, which would serialise the prefetch.
+    auto issue = [&](int t, Raw &xr) {
+        const int p0 = wst + t * WS + wave * S;
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            const int r = p0 - 1 + j;
+            const int off = (t < Rw && r >= rlo && r < rhi) ? vl + wrap(r) * rowb : -16;
+#pragma unroll
+            for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(rsf[c], off);
+        }
+    };
+
+    // local recurrences of one wave's S rows from values v[0..S+1] of rows
+    // p0-1 .. p0+S (Dirichlet end rows already read as 0)
+    auto local = [&](const T (&v)[S + 2], int p0, T (&sum)[S], T &aL, T &aR, T &eLM) {
+        seg_recur_fast<T, S>(v, d, gw, w2, sum, aL, aR);
+        eLM = aL;
+        const int jm = M - p0;
+        if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
+            T vM1 = T(0);
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j)
+                if (j == jm) vM1 = v[j];                  // node M-1
+            seg_fix_dirichlet<T, S>(p0, M, v[2], vM1, d, w2, sum, aL, aR, eLM);
+        }
+    };
+
+    // level 1, sub-tile t: combinations and local recurrences; wave 0 leaves
+    // e1 - F^L at the sub-tile's first row for the look-ahead value of v1
+    auto combine1 = [&](int t, YYLev1<T, S, NO> &st, const Raw &xr) {
+        const int p0 = wst + t * WS + wave * S;
+        T v[S + 2], e1[S];
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            T x = T(0);
+#pragma unroll
+            for (int c = 0; c < NFP; ++c) x += a.mS[0][c] * xr[c][j];
+            const int p = p0 - 1 + j;
+            v[j] = (dir_end && (p == 0 || p == M)) ? T(0) : x;
+            if (j >= 1 && j <= S) {
+                T e = T(0), f = T(0);
+#pragma unroll
+                for (int c = 0; c < NFP; ++c) {
+                    e += a.mE1[c] * xr[c][j];
+                    f += a.mOF[NO - 1][c] * xr[c][j];
+                }
+                e1[j - 1] = e;
+                st.fp[j - 1] = f;
+            }
+        }
+        local(v, p0, st.sum, st.aL, st.aR, st.eLM);
+        // D = -(sum + carries + closure): subtracting e1 here makes the closure
+        // return v1 = e1 + D (0 at Dirichlet end nodes, which level 2 reads as 0)
+#pragma unroll
+        for (int j = 0; j < S; ++j) st.sum[j] -= e1[j];
+        agg1[t % 3][0][wave][lane] = st.aL;
+        agg1[t % 3][1][wave][lane] = st.aR;
+        if (wave == 0) peekS[t & 1][lane] = e1[0] - (w2 * (v[2] - v[1]) - gw * (v[1] - v[0]));
+    };
+
+    // carries entering every wave of sub-tile t, computed once: wave F scans
+    // forward from the running carry ctop, wave F+1 backward from the
+    // look-ahead aggregate of sub-tile t+1 (zero beyond the walk)
+    T ctop1 = T(0), ctop2 = T(0);
+    auto scan = [&](int t, T (&agg)[3][2][W][64], T (&cLs)[W][64], T (&cRs)[W][64], T &ctop,
+                    T *ctopS, T *er0S, T *agS, int F) {
+        if (wave == F) {
+            T c = ctop;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                cLs[w][lane] = c;
+                c = dS * c + agg[t % 3][0][w][lane];
+            }
+            ctop = c;
+            ctopS[lane] = c;
+        } else if (wave == F + 1) {
+            T cb = T(0);
+            if (t + 1 < Rw) {
+#pragma unroll
+                for (int w = W - 1; w >= 0; --w) cb = dS * cb + agg[(t + 1) % 3][1][w][lane];
+            }
+            if (agS) agS[lane] = cb;
+            T cr = cb;
+#pragma unroll
+            for (int w = W - 1; w >= 0; --w) {
+                cRs[w][lane] = cr;
+                cr = dS * cr + agg[t % 3][1][w][lane];
+            }
+            er0S[lane] = cr;
+        }
+    };
+
+    // closure of sub-tile t of one level (in place: sum <- D); returns the
+    // line's B coefficient when node M lies in t + 1 (else 0).  A (B) is taken
+    // only where node 0 (M) is a row of the walk that holds data; elsewhere its
+    // weight on the strip's rows is below d^roll.
+    auto close = [&](int t, T (&sum)[S], T eLMcur, T eLMnext, T (&agg)[3][2][W][64],
+                     T (&cLs)[W][64], T (&cRs)[W][64], const T *ctopS, const T *er0S, T *endv) -> double {
+        const int st0 = wst + t * WS;
+        const int p0 = st0 + wave * S;
+        const T cL = cLs[wave][lane], cR = cRs[wave][lane];
+        const double A = (dir_end && st0 == 0 && pre == 0) ? a.K00 * (double)er0S[lane] : 0.0;
+        double B = 0.0;
+        const bool mhere = dir_end && M < rhi && M >= st0 && M < st0 + WS;
+        const bool mnext = dir_end && M < rhi && t + 1 < Rw && M >= st0 + WS && M < st0 + 2 * WS;
+        if (mhere || mnext) {
+            if (mhere && wave == (M - st0) / S)
+                endv[lane] = eLMcur + expneg<T>(a.nu * (double)(M - p0 + 1)) * cL;
+            if (mnext && wave == (M - st0 - WS) / S) {
+                T c = ctopS[lane];
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (w < wave) c = dS * c + agg[(t + 1) % 3][0][w][lane];
+                endv[lane] = eLMnext + expneg<T>(a.nu * (double)(M - (p0 + WS) + 1)) * c;
+            }
+            __syncthreads();
+            B = a.K11 * (double)endv[lane];
+        }
+        seg_close_fast<T, S>(sum, cL, cR, A, B, p0, M, a.nu, d, dir_end);
+        return mnext ? B : 0.0;
+    };
+
+    YYLev1<T, S, NO> c1, n1;        // level 1: sub-tiles t and t+1
+    YYLev2<T, S, NO> q0, q1, q2;    // level 2: sub-tiles t-2, t-1, t
+    T prevlast = T(0);              // wave 0: v1 at the row above its sub-tile
+
+    issue(0, xa);
+    issue(1, xb);
+    combine1(0, c1, xa);
+    issue(2, xa);
+
+    // step t: level 1 finishes sub-tile t, level 2 combines t and finishes t-2;
+    // xr holds the loads of sub-tile t+1 and receives those of t+3 (loads run
+    // two sub-tiles ahead)
+    auto step = [&](int t, Raw &xr) {
+        if (t + 1 < Rw) combine1(t + 1, n1, xr);
+        issue(t + 3, xr);
+        __syncthreads();
+        if (t < Rw) scan(t, agg1, cLs1, cRs1, ctop1, ctopS1, er0S1, agS1, 0);
+        if (t >= 2 && t - 2 < Rw) scan(t - 2, agg2, cLs2, cRs2, ctop2, ctopS2, er0S2, nullptr, 2);
+        __syncthreads();
+        // level 2 retires sub-tile t-2 before level 1 hands over sub-tile t
+        const int t2 = t - 2;
+        if (t2 >= pre && t2 < pre + R) {
+            (void)close(t2, q0.sum, q0.eLM, q1.eLM, agg2, cLs2, cRs2, ctopS2, er0S2, endv2);
+            if (active) {
+                const int p0 = wst + t2 * WS + wave * S;
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    const int p = p0 + j;
+                    if (p >= n) break;
+                    buf_store<T>(a.mOD[0][0] * q0.sum[j], rso[0], vl + p * rowb);
+                    if (NO == 2) buf_store<T>(q0.gH[j] + a.mOD[NO - 1][0] * q0.sum[j], rso[NO - 1], vl + p * rowb);
+                }
+            }
+        }
+        T pk = T(0);
+        if (t < Rw) {
+            const double Bn = close(t, c1.sum, c1.eLM, n1.eLM, agg1, cLs1, cRs1, ctopS1, er0S1, endv1);
+            vfirst[wave][lane] = c1.sum[0];
+            vlast[wave][lane] = c1.sum[S - 1];
+            // v1 at the first row of sub-tile t+1 (0 beyond the walk, at M and beyond)
+            const int ptop = wst + (t + 1) * WS;
+            if (wave == W - 1 && t + 1 < Rw && !(dir_end && ptop >= M)) {
+                pk = peekS[(t + 1) & 1][lane] - (d * ctopS1[lane] + agS1[lane]);
+                if (Bn != 0.0) pk -= (T)(Bn * exp(-a.nu * (double)(M - ptop)));
+            }
+        }
+        __syncthreads();
+        if (t < Rw) {
+            const int p0 = wst + t * WS + wave * S;
+            T v[S + 2];
+            v[0] = (wave == 0) ? prevlast : vlast[wave > 0 ? wave - 1 : 0][lane];
+#pragma unroll
+            for (int j = 0; j < S; ++j) v[j + 1] = c1.sum[j];            // v1
+            v[S + 1] = (wave == W - 1) ? pk : vfirst[wave < W - 1 ? wave + 1 : W - 1][lane];
+            if (dir_end) {
+#pragma unroll
+                for (int j = 0; j < S + 2; ++j) {
+                    const int p = p0 - 1 + j;
+                    if (p <= 0 || p >= M) v[j] = T(0);
+                }
+            }
+            local(v, p0, q2.sum, q2.aL, q2.aR, q2.eLM);
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const T v1 = c1.sum[j];
+                if (NO == 2) {
+                    q2.sum[j] -= a.ykv * v1;
+                    q2.gH[j] = c1.fp[j] + a.ykh * v1;
+                } else {
+                    q2.sum[j] -= a.ykv * v1 + a.yk0 * c1.fp[j];
+                }
+            }
+            agg2[t % 3][0][wave][lane] = q2.aL;
+            agg2[t % 3][1][wave][lane] = q2.aR;
+            if (wave == 0) prevlast = vlast[W - 1][lane];
+        }
+        c1 = n1;
+        q0 = q1;
+        q1 = q2;
+    };
+    for (int t = 0; t < Rw + 2; t += 2) {
+        step(t, xb);
+        step(t + 1, xa);      // a step past the walk does nothing
+    }
+}
+
+// ---------------------------------------------------------------------------
 // elementwise z = a x + b y
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1396,6 +1718,9 @@ constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);
 struct PCfg { int S, W, target; };
 constexpr PCfg kPCfg[] = {{8, 16, 256}, {16, 8, 512}, {8, 8, 512}, {8, 16, 512}, {16, 8, 256}, {4, 16, 256}};
 constexpr int NPCFG = sizeof(kPCfg) / sizeof(kPCfg[0]);
+// chained strided configurations (same fields as PCfg)
+constexpr PCfg kYCfg[] = {{8, 8, 256}, {4, 16, 256}, {8, 8, 512}, {4, 16, 512}, {4, 8, 256}};
+constexpr int NYCFG = sizeof(kYCfg) / sizeof(kYCfg[0]);
 
 // one per (dtype, direction class): launch a prepared KArgs with config id
 // `id` and (swept, output) counts encoded as nsno = 10*ns + no
@@ -1415,5 +1740,7 @@ hipError_t dispatch_p_f64_p1(const KArgs<double> &k, int nsno, int id, hipStream
 hipError_t dispatch_p_f64_p2(const KArgs<double> &k, int nsno, int id, hipStream_t st);
 hipError_t dispatch_p_f64_p4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
 hipError_t dispatch_s_f64_n16(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+// chained strided kernels (FP32, op.nf <= 3, one or two outputs)
+hipError_t dispatch_yy_f32(const KArgs<float> &k, int no, int id, hipStream_t st);
 
 }  // namespace molt
