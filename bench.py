@@ -138,14 +138,16 @@ def periodic3d_workload(steps=200, warmup=10):
     return also_line(ms, steps, info, n ** 3)
 
 
-def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=False, steps=100):
+def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=False, steps=100,
+          batched=False):
     """The serving workload: a Poisson stream of independent FP32 requests
     (n log-uniform in [128, 2048], P in {1, 2, 3}, CFL in [1, 4], 100 steps,
     4 Gaussian pulses) through the request server with a device budget.  Three
     compute streams and the server's copy stream fill the box's four hardware
     queues (a fifth stream would share a queue and wait behind its work).
     Latency = scheduled arrival -> completion seen by the polling loop; results
-    are handed back in device memory."""
+    are handed back in device memory.  batched: requests advance in rounds
+    whose sweeps of one kernel run as one launch over all of them."""
     import numpy as np
     import torch
     from paper_1308_3214_amd import molt
@@ -153,7 +155,7 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=Fal
     reqs = W.request_stream(count, rate_hz, seed, steps=steps, burst=burst)
     # initial fields in pinned host memory, made before the clock starts
     inits = [torch.from_numpy(W.request_initial(r).astype(np.float32)).pin_memory() for r in reqs]
-    srv = molt.Server(budget, nstreams)
+    srv = molt.Server(budget, nstreams, batched=batched)
     arrival, done_t, rid_of = {}, {}, {}
     t0 = time.perf_counter()
     i = 0
@@ -182,8 +184,9 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=Fal
     lat = np.array([done_t[k] - arrival[k] for k in done_t]) * 1e3
     pts = float(sum(r.n * r.n * r.steps for r in reqs))
     span = max(done_t.values()) - min(r.arrival_s for r in reqs)
-    return {"requests": count, "rate_hz": None if burst else rate_hz, "burst": burst,
-            "budget_bytes": budget, "streams": nstreams,
+    out = {"requests": count, "rate_hz": None if burst else rate_hz, "burst": burst,
+            "budget_bytes": budget, "mode": "batched rounds" if batched else "stream pool",
+            "streams": 1 if batched else nstreams,
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "max_ms": round(float(lat.max()), 3),
@@ -191,6 +194,10 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=Fal
             "span_s": round(span, 3), "peak_bytes": st["bytes_peak"],
             "admit_ms_mean": round(st["admit_seconds"] / count * 1e3, 3),
             "admit_ms_max": round(st["admit_max_seconds"] * 1e3, 3)}
+    if batched:
+        out.update(rounds=st["rounds"], launches=st["launches"], request_sweeps=st["sweeps"],
+                   round_host_ms_mean=round(st["round_seconds"] / max(1, st["rounds"]) * 1e3, 4))
+    return out
 
 
 def stream_copy(n_bytes=64 << 20, nsets=6, reps=24):
@@ -332,7 +339,11 @@ def main():
         also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
         out["also"] = also
     if not args.no_serve:
-        out["serving"] = {"poisson": serve(), "burst": serve(burst=True)}
+        # stream pool (per-request graphs on three streams) and batched rounds
+        # (one launch per kernel across all admitted requests)
+        out["serving"] = {"poisson": serve(), "burst": serve(burst=True),
+                          "batched": {"poisson": serve(batched=True),
+                                      "burst": serve(burst=True, batched=True)}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, P, args.cfl, 1)
     print(json.dumps(out))

@@ -58,8 +58,12 @@ enum {
     MOL_ALLOW_UNSTABLE = 1,   /* accept beta > beta_max(P) */
     MOL_INCREMENT_FORM = 2,   /* mol_solve carries du = u^n - u^{n-1} instead of u^{n-1} */
     MOL_NO_GRAPH = 4,         /* mol_solve launches kernels directly instead of a hipGraph */
-    MOL_SPLIT_Y = 8           /* mol_solve (2D, P = 2) sweeps y twice in two launches instead of
+    MOL_SPLIT_Y = 8,          /* mol_solve (2D, P = 2) sweeps y twice in two launches instead of
                                  one chained launch (same operator; for comparisons) */
+    MOL_UNIFORM_CONFIG = 16   /* launch configurations that do not depend on the grid size where
+                                 the size allows (x: one line capacity up to 2048 nodes; y/z:
+                                 the tile kernel), so that plans of different sizes share
+                                 kernels; no tuning-cache entries (used by the batched server) */
 };
 
 /* Problem descriptor (Sec. 2: domain, c, dt, beta; Sec. 3: order P;
@@ -158,6 +162,18 @@ mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
  * concurrently.  Allocations are stream-ordered: admitting or retiring a
  * request never synchronises the device.  One host thread at a time per
  * server (calls are serialised by a mutex).
+ *
+ * Batched mode (mol_server_create_ex with MOL_SERVER_BATCHED): admitted
+ * requests advance together in rounds of one time step each on one stream.
+ * The k-th launch of every request's step whose kernel instantiation is the
+ * same (same kernel, configuration, dtype and boundary type; sizes, orders and
+ * coefficients may differ) runs as one batched launch over a table of the
+ * requests' argument sets, so many small solves fill the GPU together.
+ * Launches of masked requests run one by one inside the round.  Rounds are
+ * issued by submit and poll, at most three ahead of the GPU.  The server's
+ * plans take MOL_UNIFORM_CONFIG, so requests of different sizes share
+ * kernels; each request's result is bitwise the same as the same descriptor
+ * (with that flag) solved alone.
  */
 typedef struct mol_server_ mol_server;
 
@@ -171,11 +187,20 @@ typedef struct mol_server_info {
     size_t budget;
     double admit_seconds;   /* host time spent admitting requests (plan, copies, enqueue) */
     double admit_max_seconds;
+    double round_seconds;   /* batched mode: host time spent issuing rounds */
+    int64_t rounds;         /* batched mode: rounds issued */
+    int64_t launches;       /* batched mode: kernel launches issued by rounds */
+    int64_t sweeps;         /* batched mode: request sweeps those launches carried */
 } mol_server_info;
+
+enum { MOL_SERVER_BATCHED = 1 };
 
 /* hbm_budget_bytes > 0: device bytes the server may hold; nstreams in 1..64
  * (default-priority, non-blocking streams on the current device). */
 mol_status mol_server_create(size_t hbm_budget_bytes, int nstreams, mol_server **server);
+/* As mol_server_create; flags = MOL_SERVER_BATCHED selects the batched mode
+ * (rounds on the first stream of the pool), 0 the stream pool. */
+mol_status mol_server_create_ex(size_t hbm_budget_bytes, int nstreams, int flags, mol_server **server);
 /* Waits for running requests and frees everything, results not taken included. */
 mol_status mol_server_destroy(mol_server *server);
 /* Queues a request: the solution u^nsteps (nsteps >= 1) from u^0 = u0 with

@@ -69,12 +69,41 @@ hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, boo
                         hipStream_t st);
 
 // Per-direction launch configuration chosen by the plan: cfg[0] = variant id.
-// Strided sweeps: ids below config_count_tiled() are the tile kernel, the
+// Strided sweeps: ids below NSCFG are the tile kernel, the
 // rest the pipelined strip kernel.
 // Chained strided sweeps have their own configuration ids.
 int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64, int *cfg);
 bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64, const int *cfg);
 int config_count(const SweepOp &op);
+// Nodes per lane times waves of x configuration id (line capacity / 64).
+int uniform_x_capacity(int id);
+
+// Kernel instantiation of one sweep launch: launches with equal keys may run
+// as one batched launch over a table of their argument sets.
+struct SweepKey {
+    int fp64 = 0, cls = 0, cfg = 0, nsno = 0, nfb = 0, periodic = 0;
+    bool operator<(const SweepKey &o) const
+    {
+        const int a[6] = {fp64, cls, cfg, nsno, nfb, periodic};
+        const int b[6] = {o.fp64, o.cls, o.cfg, o.nsno, o.nfb, o.periodic};
+        for (int i = 0; i < 6; ++i)
+            if (a[i] != b[i]) return a[i] < b[i];
+        return false;
+    }
+    bool operator==(const SweepKey &o) const { return !(*this < o) && !(o < *this); }
+};
+// Bytes of one argument set (host and device layout are the same).
+size_t sweep_args_bytes(bool fp64);
+// Fills the argument set of one sweep into args (sweep_args_bytes(fp64)
+// bytes), its key and its workgroup count; false when cfg is not valid.
+bool sweep_prepare(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
+                   const void *const *fptr, void *const *optr, const int *cfg, void *args,
+                   SweepKey &key, int64_t &blocks);
+// One launch of nent argument sets sharing key: d_tab holds them in device
+// memory, d_first their first workgroups (nent + 1 values, ascending from 0 to
+// blocks).
+hipError_t launch_sweep_batch(const SweepKey &key, const void *d_tab, const int64_t *d_first, int nent,
+                              int64_t blocks, hipStream_t st);
 
 // Elementwise a*x + b*y -> z on n values (state conversion for the increment form).
 hipError_t launch_axpby(bool fp64, int64_t n, double a, const void *x, double b, const void *y,

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 
 #include "molt_internal.h"
 #include "molt_sweep.h"
@@ -79,22 +80,25 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
     k.K11 = dc.K[1][1];
 }
 
+// Argument set, instantiation key and workgroup count of one launch.
 template <typename T>
-hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
-                    const void *const *fptr, void *const *optr, const int *cfg, hipStream_t st)
+void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *const *fptr,
+            void *const *optr, const int *cfg, KArgs<T> &k, SweepKey &key, int64_t &blocks)
 {
-    KArgs<T> k{};
+    k = KArgs<T>{};
     fill_common<T>(k, op, dc, fptr, optr);
     const int dir = op.dir;
-    const int nsno = op.ns * 10 + op.no;
+    key = SweepKey{};
+    key.fp64 = sizeof(T) == 8 ? 1 : 0;
+    key.cfg = cfg[0];
+    key.nsno = op.ns * 10 + op.no;
+    key.periodic = dc.periodic ? 1 : 0;
     if (dir == 0) {
         const XCfg c = kXCfg[cfg[0]];
         const int64_t nlines = g.n[1] * g.n[2];
         k.nlines = nlines;
         k.lineoff = g.n[0];
-        constexpr int VWT = sizeof(T) == 4 ? 4 : 2;
         const int vw = (sizeof(T) == 4) ? (c.S >= 4 ? 4 : c.S) : (c.S >= 2 ? 2 : 1);
-        (void)VWT;
         k.aligned = (g.n[0] % vw == 0) ? 1 : 0;
         for (int i = 0; i < MAXF; ++i)
             if (i < op.nf && (reinterpret_cast<uintptr_t>(fptr[i]) % (vw * sizeof(T)))) k.aligned = 0;
@@ -107,13 +111,10 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
         k.pd1 = g.ndim > 1 ? g.dirichlet[1] : 0;
         k.pd2 = g.ndim > 2 ? g.dirichlet[2] : 0;
         if (op.chain && (reinterpret_cast<uintptr_t>(optr[op.no]) % (vw * sizeof(T)))) k.aligned = 0;
-        const bool small = op.nf <= 4;
-        if constexpr (sizeof(T) == 4)
-            return small ? dispatch_x_f32_n4(k, nlines, nsno, cfg[0], st)
-                         : dispatch_x_f32_n16(k, nlines, nsno, cfg[0], st);
-        else
-            return small ? dispatch_x_f64_n4(k, nlines, nsno, cfg[0], st)
-                         : dispatch_x_f64_n16(k, nlines, nsno, cfg[0], st);
+        key.cls = 0;
+        key.nfb = op.nf <= 4 ? 4 : 16;
+        blocks = nlines;
+        return;
     }
     k.nlines = g.n[0];
     if (dir == 1) {
@@ -135,25 +136,24 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
     }
     k.halo = dc.halo;
     const int64_t ncg = (g.n[0] + 63) / 64;
-    const bool small = op.nf <= 4;
     if (op.yy) {
-        if constexpr (sizeof(T) == 4) {
-            const PCfg c = kYCfg[cfg[0]];
-            const int64_t WS = (int64_t)c.S * c.W;
-            const int64_t Tt = (dc.n + WS - 1) / WS;
-            k.ntiles = (int)strips_for(c, Tt, ncg * k.nouter);
-            k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
-            k.dS = (T)exp(-dc.nu * c.S);
-            k.dBlk = k.dS;
-            k.roll = yy_roll(dc, c.S);
-            const double m00 = op.mOD[0][0];
-            k.ykv = (T)(op.mV[0] / m00);
-            k.yk0 = (T)(1.0 / m00);
-            k.ykh = op.no > 1 ? (T)(op.mV[1] - op.mOD[1][0] * op.mV[0] / m00) : T(0);
-            return dispatch_yy_f32(k, op.no, cfg[0], st);
-        } else {
-            return hipErrorInvalidValue;
-        }
+        const PCfg c = kYCfg[cfg[0]];
+        const int64_t WS = (int64_t)c.S * c.W;
+        const int64_t Tt = (dc.n + WS - 1) / WS;
+        k.ntiles = (int)strips_for(c, Tt, ncg * k.nouter);
+        k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
+        k.dS = (T)exp(-dc.nu * c.S);
+        k.dBlk = k.dS;
+        k.roll = yy_roll(dc, c.S);
+        const double m00 = op.mOD[0][0];
+        k.ykv = (T)(op.mV[0] / m00);
+        k.yk0 = (T)(1.0 / m00);
+        k.ykh = op.no > 1 ? (T)(op.mV[1] - op.mOD[1][0] * op.mV[0] / m00) : T(0);
+        key.cls = 3;
+        key.nsno = op.no;
+        key.nfb = 3;
+        blocks = k.nblocks;
+        return;
     }
     if (cfg[0] >= NSCFG) {
         // pipelined strips
@@ -165,16 +165,11 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
         k.nblocks = ns_ * ncg * k.nouter;
         k.dS = (T)exp(-dc.nu * c.S);
         k.dBlk = k.dS;
-        const int id = cfg[0] - NSCFG;
-        if constexpr (sizeof(T) == 4) {
-            if (op.nf == 1) return dispatch_p_f32_p1(k, nsno, id, st);
-            if (op.nf == 2) return dispatch_p_f32_p2(k, nsno, id, st);
-            return dispatch_p_f32_p4(k, nsno, id, st);
-        } else {
-            if (op.nf == 1) return dispatch_p_f64_p1(k, nsno, id, st);
-            if (op.nf == 2) return dispatch_p_f64_p2(k, nsno, id, st);
-            return dispatch_p_f64_p4(k, nsno, id, st);
-        }
+        key.cls = 2;
+        key.cfg = cfg[0] - NSCFG;
+        key.nfb = op.nf == 1 ? 1 : op.nf == 2 ? 2 : 4;
+        blocks = k.nblocks;
+        return;
     }
     const SCfg c = kSCfg[cfg[0]];
     const int WS = c.S * c.W;
@@ -182,10 +177,60 @@ hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
     k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
     k.dS = (T)exp(-dc.nu * c.S);
     k.dBlk = k.dS;
-    if constexpr (sizeof(T) == 4)
-        return small ? dispatch_s_f32_n4(k, nsno, cfg[0], st) : dispatch_s_f32_n16(k, nsno, cfg[0], st);
-    else
-        return small ? dispatch_s_f64_n4(k, nsno, cfg[0], st) : dispatch_s_f64_n16(k, nsno, cfg[0], st);
+    key.cls = 1;
+    key.nfb = op.nf <= 4 ? 4 : 16;
+    blocks = k.nblocks;
+}
+
+// Launch of one argument set (bt == nullptr) or of a batched table; k selects
+// the instantiation (its periodic flag) together with the key.
+template <typename T>
+hipError_t dispatch_t(const KArgs<T> &k, const SweepKey &key, int64_t blocks, const BatchTab *bt,
+                      hipStream_t st)
+{
+    const bool small = key.nfb <= 4;
+    switch (key.cls) {
+    case 0:
+        if constexpr (sizeof(T) == 4)
+            return small ? dispatch_x_f32_n4(k, blocks, key.nsno, key.cfg, bt, st)
+                         : dispatch_x_f32_n16(k, blocks, key.nsno, key.cfg, bt, st);
+        else
+            return small ? dispatch_x_f64_n4(k, blocks, key.nsno, key.cfg, bt, st)
+                         : dispatch_x_f64_n16(k, blocks, key.nsno, key.cfg, bt, st);
+    case 1:
+        if constexpr (sizeof(T) == 4)
+            return small ? dispatch_s_f32_n4(k, key.nsno, key.cfg, bt, st)
+                         : dispatch_s_f32_n16(k, key.nsno, key.cfg, bt, st);
+        else
+            return small ? dispatch_s_f64_n4(k, key.nsno, key.cfg, bt, st)
+                         : dispatch_s_f64_n16(k, key.nsno, key.cfg, bt, st);
+    case 2:
+        if constexpr (sizeof(T) == 4) {
+            if (key.nfb == 1) return dispatch_p_f32_p1(k, key.nsno, key.cfg, bt, st);
+            if (key.nfb == 2) return dispatch_p_f32_p2(k, key.nsno, key.cfg, bt, st);
+            return dispatch_p_f32_p4(k, key.nsno, key.cfg, bt, st);
+        } else {
+            if (key.nfb == 1) return dispatch_p_f64_p1(k, key.nsno, key.cfg, bt, st);
+            if (key.nfb == 2) return dispatch_p_f64_p2(k, key.nsno, key.cfg, bt, st);
+            return dispatch_p_f64_p4(k, key.nsno, key.cfg, bt, st);
+        }
+    case 3:
+        if constexpr (sizeof(T) == 4) return dispatch_yy_f32(k, key.nsno, key.cfg, bt, st);
+        else return hipErrorInvalidValue;
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
+                    const void *const *fptr, void *const *optr, const int *cfg, hipStream_t st)
+{
+    KArgs<T> k;
+    SweepKey key;
+    int64_t blocks = 0;
+    prep_t<T>(op, g, dc, fptr, optr, cfg, k, key, blocks);
+    return dispatch_t<T>(k, key, blocks, nullptr, st);
 }
 
 }  // namespace
@@ -284,6 +329,8 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
     return config_valid(g, dc, op, fp64, cfg) ? 0 : -1;
 }
 
+int uniform_x_capacity(int id) { return (id >= 0 && id < NXCFG) ? kXCfg[id].S * kXCfg[id].WPL : 0; }
+
 int config_count(const SweepOp &op) { return op.yy ? NYCFG : op.dir == 0 ? NXCFG : NSCFG + NPCFG; }
 
 hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
@@ -293,6 +340,40 @@ hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, boo
     if (!config_valid(g, dc, op, fp64, cfg)) return hipErrorInvalidValue;
     return fp64 ? launch_t<double>(op, g, dc, fptr, optr, cfg, st)
                 : launch_t<float>(op, g, dc, fptr, optr, cfg, st);
+}
+
+size_t sweep_args_bytes(bool fp64) { return fp64 ? sizeof(KArgs<double>) : sizeof(KArgs<float>); }
+
+bool sweep_prepare(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
+                   const void *const *fptr, void *const *optr, const int *cfg, void *args,
+                   SweepKey &key, int64_t &blocks)
+{
+    if (!config_valid(g, dc, op, fp64, cfg)) return false;
+    if (fp64) {
+        KArgs<double> k;
+        prep_t<double>(op, g, dc, fptr, optr, cfg, k, key, blocks);
+        std::memcpy(args, &k, sizeof k);
+    } else {
+        KArgs<float> k;
+        prep_t<float>(op, g, dc, fptr, optr, cfg, k, key, blocks);
+        std::memcpy(args, &k, sizeof k);
+    }
+    return true;
+}
+
+hipError_t launch_sweep_batch(const SweepKey &key, const void *d_tab, const int64_t *d_first, int nent,
+                              int64_t blocks, hipStream_t st)
+{
+    if (nent < 1 || blocks < 1 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    BatchTab bt{d_tab, d_first, nent, blocks};
+    if (key.fp64) {
+        KArgs<double> k{};
+        k.periodic = key.periodic;
+        return dispatch_t<double>(k, key, blocks, &bt, st);
+    }
+    KArgs<float> k{};
+    k.periodic = key.periodic;
+    return dispatch_t<float>(k, key, blocks, &bt, st);
 }
 
 hipError_t launch_axpby(bool fp64, int64_t n, double a, const void *x, double b, const void *y,

@@ -163,6 +163,34 @@ DirCoef make_dircoef(double nu, int64_t n, bool periodic, bool fp64)
 
 namespace molt {
 
+// MOL_UNIFORM_CONFIG: x sweeps take the smallest line capacity that holds
+// max(n, 2048) nodes, strided sweeps the tall-tile kernel; a choice that is
+// not valid for this op keeps the default.
+void uniform_config(const mol_plan_ &pl, const SweepOp &op, int *cfg)
+{
+    const int dir = op.dir;
+    int c[2] = {0, 0};
+    if (dir == 0) {
+        static const int order32[] = {0, 1, 2, 3, 4, 5, 7};
+        static const int order64[] = {0, 1, 2, 8, 9, 6, 7};
+        const int *ord = pl.fp64 ? order64 : order32;
+        const int64_t need = std::max<int64_t>(pl.geom.n[0], 2048);
+        for (int i = 0; i < 7; ++i) {
+            c[0] = ord[i];
+            const int cap = 64 * uniform_x_capacity(c[0]);
+            if (cap >= need && config_valid(pl.geom, pl.dc[dir], op, pl.fp64, c)) {
+                cfg[0] = c[0];
+                return;
+            }
+        }
+        return;
+    }
+    if (op.yy) return;
+    const int regs = (2 * op.ns + op.no) * (pl.fp64 ? 2 : 1);
+    c[0] = (regs <= 4) ? 0 : 2;
+    if (config_valid(pl.geom, pl.dc[dir], op, pl.fp64, c)) cfg[0] = c[0];
+}
+
 bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
                    const std::vector<OutSpec> &outs, int proj, int chain_buf)
 {
@@ -238,7 +266,9 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
             err = "no kernel configuration fits this line length";
             return false;
         }
-        if (!pl.masked) {
+        if (!pl.masked && (pl.desc.flags & MOL_UNIFORM_CONFIG)) {
+            uniform_config(pl, op, cfg);
+        } else if (!pl.masked) {
             const std::string key = tune_op_key(op);
             for (const auto &t : pl.tuned) {
                 int c[2] = {t.second, 0};
@@ -769,25 +799,31 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
     return MOL_OK;
 }
 
+void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const void *ucurr, void *unext,
+                const void *in, void *out, const void **fp, void **op)
+{
+    auto res = [&](int b) -> void * {
+        switch (b) {
+        case B_UPREV: return const_cast<void *>(uprev);
+        case B_UCURR: return const_cast<void *>(ucurr);
+        case B_UNEXT: return unext;
+        case B_IN: return const_cast<void *>(in);
+        case B_OUT: return out;
+        default: return pl->ws[b - B_WS0];
+        }
+    };
+    for (int i = 0; i < po.op.nf; ++i) fp[i] = res(po.op.f[i]);
+    for (int i = 0; i < po.op.no; ++i) op[i] = res(po.op.o[i]);
+    if (po.op.chain) op[po.op.no] = res(po.op.ochain);
+}
+
 hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
                        void *unext, const void *in, void *out, hipStream_t st)
 {
     for (const ProgOp &po : prog) {
         const void *fp[MAXF];
         void *op[MAXO + 1];
-        auto res = [&](int b) -> void * {
-            switch (b) {
-            case B_UPREV: return const_cast<void *>(uprev);
-            case B_UCURR: return const_cast<void *>(ucurr);
-            case B_UNEXT: return unext;
-            case B_IN: return const_cast<void *>(in);
-            case B_OUT: return out;
-            default: return pl->ws[b - B_WS0];
-            }
-        };
-        for (int i = 0; i < po.op.nf; ++i) fp[i] = res(po.op.f[i]);
-        for (int i = 0; i < po.op.no; ++i) op[i] = res(po.op.o[i]);
-        if (po.op.chain) op[po.op.no] = res(po.op.ochain);
+        resolve_op(pl, po, uprev, ucurr, unext, in, out, fp, op);
         hipError_t e;
         if (pl->masked)
             e = launch_seg_op(po.op, pl, fp, op, st);

@@ -128,6 +128,14 @@ void masked_free(mol_plan_ *pl);
 hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *const *fptr,
                          void *const *optr, hipStream_t st);
 
+// Device pointers of one launch of a program: fields (op.nf) and outputs
+// (op.no, then the chained output) for the given caller fields.
+void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const void *ucurr, void *unext,
+                const void *in, void *out, const void **fp, void **op);
+// Run a program on st (one launch per op).
+hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
+                       void *unext, const void *in, void *out, hipStream_t st);
+
 // plans whose workspace is allocated and freed in stream order on st (no
 // device-wide synchronisation; used by the request server)
 mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out);

@@ -7,8 +7,17 @@
 // hardware queues), and signals completion with an event.  All allocations of
 // a request are stream-ordered, so admitting and retiring requests never
 // synchronises the device.
+//
+// Batched mode: admitted requests advance in rounds of one step each on one
+// stream.  A round gathers the launches of every running request's step,
+// groups them by position in the step and kernel instantiation, writes the
+// argument sets of each group into one table (pinned staging, one copy per
+// round) and runs each group as one batched launch; masked requests' launches
+// run one by one in their position.  Three staging slots bound the rounds in
+// flight.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -41,6 +50,18 @@ struct Req {
     void *d_prev = nullptr, *d_curr = nullptr;
     int stream = 0;
     double work = 0;          // point-updates of the request (stream load estimate)
+    int64_t left = 0;         // batched mode: steps still to run
+    int par = 0;              // batched mode: buffer roles of the next step
+    bool recorded = false;    // batched mode: completion event recorded
+    // batched mode: argument sets of the step's launches for both buffer roles
+    struct Cached {
+        int k;
+        molt::SweepKey key;
+        int64_t blocks;
+        size_t off, bytes;
+    };
+    std::vector<Cached> ops[2];
+    std::vector<unsigned char> args[2];
     hipEvent_t done = nullptr;
     std::string err;
 };
@@ -66,6 +87,19 @@ struct mol_server_ {
     double t0 = 0;
     double admit_s = 0;               // host time spent admitting requests
     double admit_max_s = 0;
+    // batched mode
+    bool batched = false;
+    struct Slot {
+        void *h = nullptr;                // pinned staging
+        void *d = nullptr;                // device table
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;          // after the slot's copy
+        bool used = false;
+    };
+    static constexpr int NSLOT = 3;
+    Slot slots[NSLOT];
+    int64_t rounds = 0, launches = 0, sweeps = 0;
+    double round_s = 0;               // host time spent issuing rounds
 };
 
 namespace {
@@ -135,13 +169,218 @@ mol_status launch(mol_server_ *s, Req *r)
     return MOL_OK;
 }
 
+// Batched mode: allocations, initial field, start step and (fused solves) the
+// first D_x of the solve on the round stream; the request then joins the
+// rounds.
+mol_status admit_batched(mol_server_ *s, Req *r)
+{
+    r->stream = 0;
+    hipStream_t st = s->streams[0];
+    mol_desc d = r->desc;
+    d.mask = r->mask.empty() ? nullptr : r->mask.data();
+    d.cross = r->cross.empty() ? nullptr : r->cross.data();
+    mol_status ms = molt::plan_create_async(&d, st, &r->plan);
+    if (ms != MOL_OK) return sfail(ms, mol_last_error());
+    if (hipMallocAsync(&r->d_prev, r->field, st) != hipSuccess ||
+        hipMallocAsync(&r->d_curr, r->field, st) != hipSuccess)
+        return sfail(MOL_E_NOMEM, "stream-ordered allocation of the state fields failed");
+    if (hipMemcpyAsync(r->d_prev, r->u0, r->field,
+                       r->u0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return sfail(MOL_E_DEVICE, "copy of the initial field failed");
+    ms = mol_start(r->plan, r->d_prev, nullptr, r->d_curr, st);
+    if (ms != MOL_OK) return sfail(ms, mol_last_error());
+    mol_plan_ *pl = r->plan;
+    if (!pl->solve_step.empty() &&
+        molt::run_program(pl, pl->solve_pro, r->d_prev, r->d_curr, nullptr, nullptr, nullptr, st) != hipSuccess)
+        return sfail(MOL_E_DEVICE, "launch failed");
+    if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess)
+        return sfail(MOL_E_DEVICE, "completion event failed");
+    // argument sets of the step for both buffer roles (masked plans run their
+    // launches directly)
+    if (!pl->masked) {
+        const molt::Program &prog = pl->solve_step.empty() ? pl->step : pl->solve_step;
+        const size_t asz = molt::sweep_args_bytes(pl->fp64);
+        for (int par = 0; par < 2; ++par) {
+            void *A = par ? r->d_curr : r->d_prev, *B = par ? r->d_prev : r->d_curr;
+            r->args[par].resize(prog.size() * asz);
+            for (int k = 0; k < (int)prog.size(); ++k) {
+                const void *fp[molt::MAXF];
+                void *op[molt::MAXO + 1];
+                // three-level step: u_next overwrites u_prev
+                molt::resolve_op(pl, prog[k], A, B, A, nullptr, nullptr, fp, op);
+                Req::Cached c{k, molt::SweepKey{}, 0, k * asz, asz};
+                if (!molt::sweep_prepare(prog[k].op, pl->geom, pl->dc[prog[k].op.dir], pl->fp64, fp, op,
+                                         prog[k].cfg, r->args[par].data() + c.off, c.key, c.blocks))
+                    return sfail(MOL_E_DEVICE, "no launch configuration for a step launch");
+                r->ops[par].push_back(c);
+            }
+        }
+    }
+    r->left = r->nsteps - 1;
+    if (r->left == 0) {
+        if (hipEventRecord(r->done, st) != hipSuccess) return sfail(MOL_E_DEVICE, "completion event failed");
+        r->recorded = true;
+    }
+    return MOL_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Batched mode: issue one round (one step of every running request) if a
+// staging slot is free.  Returns false when nothing was issued.
+bool issue_round(mol_server_ *s)
+{
+    std::vector<Req *> act;
+    for (auto &kv : s->reqs)
+        if (kv.second->state == Q_RUNNING && kv.second->left > 0) act.push_back(kv.second);
+    if (act.empty()) return false;
+    mol_server_::Slot &sl = s->slots[s->rounds % mol_server_::NSLOT];
+    if (sl.used && hipEventQuery(sl.ev) == hipErrorNotReady) return false;
+    hipStream_t st = s->streams[0];
+
+    struct Ent {
+        int64_t blocks;
+        const unsigned char *args;    // argument set (cached by the request)
+        size_t bytes;
+    };
+    struct Direct {
+        int k;
+        Req *r;
+        const molt::ProgOp *po;
+    };
+    std::map<std::pair<int, molt::SweepKey>, std::vector<Ent>> groups;
+    std::vector<Direct> direct;
+    int maxk = 0;
+    for (Req *r : act) {
+        mol_plan_ *pl = r->plan;
+        const molt::Program &prog = pl->solve_step.empty() ? pl->step : pl->solve_step;
+        maxk = std::max(maxk, (int)prog.size());
+        if (pl->masked) {
+            for (int k = 0; k < (int)prog.size(); ++k) direct.push_back({k, r, &prog[k]});
+            continue;
+        }
+        for (const Req::Cached &c : r->ops[r->par])
+            groups[{c.k, c.key}].push_back({c.blocks, r->args[r->par].data() + c.off, c.bytes});
+    }
+    // table layout: per group, first[] (nent + 1) then the argument sets
+    size_t total = 0;
+    for (auto &g : groups) {
+        total += align256((g.second.size() + 1) * sizeof(int64_t));
+        for (const Ent &e : g.second) total += e.bytes;
+        total = align256(total);
+    }
+    if (total > sl.cap) {
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.d) (void)hipFreeAsync(sl.d, st);
+        sl.h = sl.d = nullptr;
+        sl.cap = 0;
+        const size_t cap = std::max(total * 2, (size_t)1 << 20);
+        if (hipHostMalloc(&sl.h, cap, hipHostMallocDefault) != hipSuccess ||
+            hipMallocAsync(&sl.d, cap, st) != hipSuccess) {
+            s_err = "round table allocation failed";
+            for (Req *r : act) {
+                r->err = s_err;
+                r->state = Q_FAILED;
+            }
+            return false;
+        }
+        sl.cap = cap;
+    }
+    struct Launch {
+        int k;
+        molt::SweepKey key;
+        size_t tab, first;
+        int nent;
+        int64_t blocks;
+    };
+    std::vector<Launch> ls;
+    unsigned char *h = static_cast<unsigned char *>(sl.h);
+    size_t pos = 0;
+    for (auto &g : groups) {
+        const size_t nent = g.second.size();
+        int64_t *first = reinterpret_cast<int64_t *>(h + pos);
+        const size_t fpos = pos;
+        pos += align256((nent + 1) * sizeof(int64_t));
+        const size_t tpos = pos;
+        int64_t b = 0;
+        for (size_t i = 0; i < nent; ++i) {
+            const Ent &e = g.second[i];
+            first[i] = b;
+            b += e.blocks;
+            std::memcpy(h + pos, e.args, e.bytes);
+            pos += e.bytes;
+        }
+        first[nent] = b;
+        pos = align256(pos);
+        ls.push_back({g.first.first, g.first.second, tpos, fpos, (int)nent, b});
+    }
+    if (pos > 0 && (hipMemcpyAsync(sl.d, sl.h, pos, hipMemcpyHostToDevice, st) != hipSuccess ||
+                    hipEventRecord(sl.ev, st) != hipSuccess)) {
+        s_err = "round table copy failed";
+        for (Req *r : act) {
+            r->err = s_err;
+            r->state = Q_FAILED;
+        }
+        return false;
+    }
+    if (pos > 0) sl.used = true;
+    // launches in step order: position k of every request after position k-1
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < maxk && e == hipSuccess; ++k) {
+        for (const Direct &dr : direct) {
+            if (dr.k != k || e != hipSuccess) continue;
+            const molt::Program one(1, *dr.po);
+            e = molt::run_program(dr.r->plan, one, dr.r->d_prev, dr.r->d_curr, dr.r->d_prev, nullptr,
+                                  nullptr, st);
+            ++s->launches;
+            ++s->sweeps;
+        }
+        for (const Launch &l : ls) {
+            if (l.k != k || e != hipSuccess) continue;
+            unsigned char *d = static_cast<unsigned char *>(sl.d);
+            e = molt::launch_sweep_batch(l.key, d + l.tab, reinterpret_cast<const int64_t *>(d + l.first),
+                                         l.nent, l.blocks, st);
+            ++s->launches;
+            s->sweeps += l.nent;
+        }
+    }
+    for (Req *r : act) {
+        if (e != hipSuccess) {
+            r->err = hipGetErrorString(e);
+            r->state = Q_FAILED;
+            continue;
+        }
+        std::swap(r->d_prev, r->d_curr);     // the new field is u^n
+        r->par ^= 1;
+        if (--r->left == 0) {
+            if (hipEventRecord(r->done, st) == hipSuccess) r->recorded = true;
+            else {
+                r->err = "completion event failed";
+                r->state = Q_FAILED;
+            }
+        }
+    }
+    ++s->rounds;
+    return true;
+}
+
 // Retire finished requests, then admit from the head of the queue while the
 // budget allows.  Appends the ids that finished to done.
 void pump(mol_server_ *s, std::vector<int64_t> &done)
 {
     for (auto &kv : s->reqs) {
         Req *r = kv.second;
+        if (s->batched && r->state == Q_FAILED && r->plan) {
+            // failed inside a round: nothing of it may be in flight any more
+            (void)hipStreamSynchronize(s->streams[0]);
+            retire(s, r);
+            ++s->completed;
+            done.push_back(r->id);
+            continue;
+        }
         if (r->state != Q_RUNNING) continue;
+        if (s->batched && !r->recorded) continue;
         const hipError_t e = hipEventQuery(r->done);
         if (e == hipErrorNotReady) continue;
         r->state = (e == hipSuccess) ? Q_DONE : Q_FAILED;
@@ -157,7 +396,7 @@ void pump(mol_server_ *s, std::vector<int64_t> &done)
         s->used += r->footprint;
         if (s->used > s->peak) s->peak = s->used;
         const double ta = now_s();
-        const mol_status ls = launch(s, r);
+        const mol_status ls = s->batched ? admit_batched(s, r) : launch(s, r);
         const double dt = now_s() - ta;
         s->admit_s += dt;
         if (dt > s->admit_max_s) s->admit_max_s = dt;
@@ -171,6 +410,12 @@ void pump(mol_server_ *s, std::vector<int64_t> &done)
             continue;
         }
         r->state = Q_RUNNING;
+    }
+    if (s->batched) {
+        const double tr = now_s();
+        while (issue_round(s)) {
+        }
+        s->round_s += now_s() - tr;
     }
 }
 
@@ -207,6 +452,23 @@ mol_status mol_server_create(size_t hbm_budget_bytes, int nstreams, mol_server *
     return MOL_OK;
 }
 
+mol_status mol_server_create_ex(size_t hbm_budget_bytes, int nstreams, int flags, mol_server **out)
+{
+    if (flags & ~MOL_SERVER_BATCHED) return sfail(MOL_E_INVALID, "unknown server flags");
+    mol_status ms = mol_server_create(hbm_budget_bytes, nstreams, out);
+    if (ms != MOL_OK || !(flags & MOL_SERVER_BATCHED)) return ms;
+    mol_server_ *s = *out;
+    s->batched = true;
+    for (auto &sl : s->slots) {
+        if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+            *out = nullptr;
+            (void)mol_server_destroy(s);
+            return sfail(MOL_E_DEVICE, "event creation failed");
+        }
+    }
+    return MOL_OK;
+}
+
 mol_status mol_server_destroy(mol_server *s)
 {
     if (!s) return MOL_OK;
@@ -229,6 +491,11 @@ mol_status mol_server_destroy(mol_server *s)
     }
     (void)hipStreamSynchronize(s->copy);
     (void)hipStreamDestroy(s->copy);
+    for (auto &sl : s->slots) {
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.d) (void)hipFree(sl.d);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+    }
     delete s;
     return MOL_OK;
 }
@@ -243,6 +510,7 @@ mol_status mol_server_submit(mol_server *s, const mol_desc *desc, const void *u0
     Req *r = new (std::nothrow) Req();
     if (!r) return sfail(MOL_E_NOMEM, "host allocation failed");
     r->desc = *desc;
+    if (s->batched) r->desc.flags |= MOL_UNIFORM_CONFIG;     // plans of different sizes share kernels
     const int64_t np = npoints(*desc);
     if (desc->mask) r->mask.assign(desc->mask, desc->mask + np);
     if (desc->cross) r->cross.assign(desc->cross, desc->cross + 4 * np);
@@ -329,6 +597,10 @@ mol_status mol_server_stats(mol_server *s, mol_server_info *info)
     info->budget = s->budget;
     info->admit_seconds = s->admit_s;
     info->admit_max_seconds = s->admit_max_s;
+    info->round_seconds = s->round_s;
+    info->rounds = s->rounds;
+    info->launches = s->launches;
+    info->sweeps = s->sweeps;
     return MOL_OK;
 }
 

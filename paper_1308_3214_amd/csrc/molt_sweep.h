@@ -114,6 +114,20 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t N)
     return x * per + (x < rem ? x : rem) + local;
 }
 
+// Batched launches: the workgroups of entry e of a table of argument sets are
+// [first[e], first[e+1]); first[0] = 0, ascending.  Returns the entry of
+// workgroup b (the last e with first[e] <= b; always in [0, nent)).
+__device__ __forceinline__ int batch_entry(const int64_t *__restrict__ first, int nent, int64_t b)
+{
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int C>
 struct ic {
     static constexpr int value = C;
@@ -511,8 +525,7 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
 }
 
 template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
-__global__ void __launch_bounds__(64 * WPL)
-k_sweep_x(const KArgs<T> a)
+__device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bid)
 {
     constexpr int NT = 64 * WPL;
     constexpr int NPAD = NT * (S + 1);
@@ -524,7 +537,7 @@ k_sweep_x(const KArgs<T> a)
     __shared__ T ends[2][MAXS];
 
     const int t = threadIdx.x;
-    const int64_t line = blockIdx.x;
+    const int64_t line = bid;
     const int n = (int)a.n;
     const int M = n - 1;
     const int64_t base = line * a.lineoff;            // uniform per workgroup
@@ -684,13 +697,25 @@ k_sweep_x(const KArgs<T> a)
         }
     }
 }
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
+__global__ void __launch_bounds__(64 * WPL)
+k_sweep_x(const KArgs<T> a)
+{
+    sweep_x_body<T, S, WPL, NS, NO, VW, PER, NFMAX>(a, blockIdx.x);
+}
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
+__global__ void __launch_bounds__(64 * WPL)
+k_sweep_x_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first, int nent)
+{
+    const int e = batch_entry(first, nent, blockIdx.x);
+    sweep_x_body<T, S, WPL, NS, NO, VW, PER, NFMAX>(tab[e], (int64_t)blockIdx.x - first[e]);
+}
 
 // ---------------------------------------------------------------------------
 // strided sweep (y or z): lanes = 64 consecutive columns, W waves x S nodes
 // ---------------------------------------------------------------------------
 template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX>
-__global__ void __launch_bounds__(64 * W)
-k_sweep_s(const KArgs<T> a)
+__device__ __forceinline__ void sweep_s_body(const KArgs<T> &a, const int64_t bid)
 {
     constexpr int WS = W * S;
     __shared__ T red[2][NS][W][64];      // cooperative sums, then wave aggregates
@@ -700,7 +725,7 @@ k_sweep_s(const KArgs<T> a)
     // wave index as a scalar: row numbers, row pointers and every per-row
     // decision below are wave-uniform (scalar registers, one shared lane offset)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t L = xcd_remap(blockIdx.x, a.nblocks);
+    const int64_t L = xcd_remap(bid, a.nblocks);
     const int tile = (int)(L % a.ntiles);
     const int64_t rest = L / a.ntiles;
     const int64_t ncg = (a.nlines + 63) / 64;
@@ -1001,6 +1026,19 @@ k_sweep_s(const KArgs<T> a)
         }
     }
 }
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_s(const KArgs<T> a)
+{
+    sweep_s_body<T, S, W, NS, NO, PER, NFMAX>(a, blockIdx.x);
+}
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_s_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first, int nent)
+{
+    const int e = batch_entry(first, nent, blockIdx.x);
+    sweep_s_body<T, S, W, NS, NO, PER, NFMAX>(tab[e], (int64_t)blockIdx.x - first[e]);
+}
 
 // ---------------------------------------------------------------------------
 // pipelined strided sweep (y or z): a workgroup walks a strip of R sub-tiles
@@ -1024,8 +1062,7 @@ struct SubTile {
 };
 
 template <typename T, int S, int W, int NS, int NO, bool PER, int NFP>
-__global__ void __launch_bounds__(64 * W)
-k_sweep_p(const KArgs<T> a)
+__device__ __forceinline__ void sweep_p_body(const KArgs<T> &a, const int64_t bid)
 {
     static_assert(W >= 2, "the carry scans take waves 0 and 1");
     constexpr int WS = W * S;
@@ -1038,7 +1075,7 @@ k_sweep_p(const KArgs<T> a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nstrips = a.ntiles;
-    const int64_t L = blockIdx.x;
+    const int64_t L = bid;
     const int strip = (int)(L % nstrips);
     const int64_t rest = L / nstrips;
     const int64_t ncg = (a.nlines + 63) / 64;
@@ -1375,6 +1412,19 @@ k_sweep_p(const KArgs<T> a)
         if (t + 1 < R) finish(t + 1, xb);
     }
 }
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFP>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_p(const KArgs<T> a)
+{
+    sweep_p_body<T, S, W, NS, NO, PER, NFP>(a, blockIdx.x);
+}
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFP>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_p_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first, int nent)
+{
+    const int e = batch_entry(first, nent, blockIdx.x);
+    sweep_p_body<T, S, W, NS, NO, PER, NFP>(tab[e], (int64_t)blockIdx.x - first[e]);
+}
 
 // ---------------------------------------------------------------------------
 // chained strided sweep: v1 = e1 + D s1 and y = D v1 along the same lines in
@@ -1413,8 +1463,7 @@ struct YYLev2 {
 };
 
 template <typename T, int S, int W, int NO, bool PER, int NFP>
-__global__ void __launch_bounds__(64 * W)
-k_sweep_yy(const KArgs<T> a)
+__device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t bid)
 {
     static_assert(W >= 4, "the carry scans take waves 0..3");
     constexpr int WS = W * S;
@@ -1427,7 +1476,7 @@ k_sweep_yy(const KArgs<T> a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nstrips = a.ntiles;
-    const int64_t L = blockIdx.x;
+    const int64_t L = bid;
     const int strip = (int)(L % nstrips);
     const int64_t rest = L / nstrips;
     const int64_t ncg = (a.nlines + 63) / 64;
@@ -1688,6 +1737,19 @@ k_sweep_yy(const KArgs<T> a)
         step(t + 1, xa);      // a step past the walk does nothing
     }
 }
+template <typename T, int S, int W, int NO, bool PER, int NFP>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_yy(const KArgs<T> a)
+{
+    sweep_yy_body<T, S, W, NO, PER, NFP>(a, blockIdx.x);
+}
+template <typename T, int S, int W, int NO, bool PER, int NFP>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_yy_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first, int nent)
+{
+    const int e = batch_entry(first, nent, blockIdx.x);
+    sweep_yy_body<T, S, W, NO, PER, NFP>(tab[e], (int64_t)blockIdx.x - first[e]);
+}
 
 // ---------------------------------------------------------------------------
 // elementwise z = a x + b y
@@ -1722,25 +1784,37 @@ constexpr int NPCFG = sizeof(kPCfg) / sizeof(kPCfg[0]);
 constexpr PCfg kYCfg[] = {{8, 8, 256}, {4, 16, 256}, {8, 8, 512}, {4, 16, 512}, {4, 8, 256}};
 constexpr int NYCFG = sizeof(kYCfg) / sizeof(kYCfg[0]);
 
+// A batched launch: entry e of the device table tab (KArgs<T>[nent]) runs on
+// workgroups [first[e], first[e+1]) of a grid of `blocks` workgroups
+// (first[0] = 0, first[nent] = blocks; device memory).  Every entry shares the
+// kernel instantiation chosen by the dispatch arguments.
+struct BatchTab {
+    const void *tab;
+    const int64_t *first;
+    int nent;
+    int64_t blocks;
+};
+
 // one per (dtype, direction class): launch a prepared KArgs with config id
-// `id` and (swept, output) counts encoded as nsno = 10*ns + no
+// `id` and (swept, output) counts encoded as nsno = 10*ns + no, or a batched
+// table (bt != nullptr; k then only selects the instantiation)
 // _n4: field loop unrolled with static indices (op.nf <= 4); _n16: runtime loop
-hipError_t dispatch_x_f32_n4(const KArgs<float> &k, int64_t nlines, int nsno, int id, hipStream_t st);
-hipError_t dispatch_x_f64_n4(const KArgs<double> &k, int64_t nlines, int nsno, int id, hipStream_t st);
-hipError_t dispatch_s_f32_n4(const KArgs<float> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_s_f64_n4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_x_f32_n16(const KArgs<float> &k, int64_t nlines, int nsno, int id, hipStream_t st);
-hipError_t dispatch_x_f64_n16(const KArgs<double> &k, int64_t nlines, int nsno, int id, hipStream_t st);
-hipError_t dispatch_s_f32_n16(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_x_f32_n4(const KArgs<float> &k, int64_t nlines, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_x_f64_n4(const KArgs<double> &k, int64_t nlines, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_x_f32_n16(const KArgs<float> &k, int64_t nlines, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_x_f64_n16(const KArgs<double> &k, int64_t nlines, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_s_f32_n4(const KArgs<float> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_s_f64_n4(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_s_f32_n16(const KArgs<float> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_s_f64_n16(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
 // pipelined strided kernels: _p<NFP>, fields loaded per sub-tile (op.nf <= NFP)
-hipError_t dispatch_p_f32_p1(const KArgs<float> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_p_f32_p2(const KArgs<float> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_p_f32_p4(const KArgs<float> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_p_f64_p1(const KArgs<double> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_p_f64_p2(const KArgs<double> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_p_f64_p4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
-hipError_t dispatch_s_f64_n16(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_p_f32_p1(const KArgs<float> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_p_f32_p2(const KArgs<float> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_p_f32_p4(const KArgs<float> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_p_f64_p1(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_p_f64_p2(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+hipError_t dispatch_p_f64_p4(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
 // chained strided kernels (FP32, op.nf <= 3, one or two outputs)
-hipError_t dispatch_yy_f32(const KArgs<float> &k, int no, int id, hipStream_t st);
+hipError_t dispatch_yy_f32(const KArgs<float> &k, int no, int id, const BatchTab *bt, hipStream_t st);
 
 }  // namespace molt

@@ -1,3 +1,5 @@
-// strided-sweep kernels, float, field loop bound 16.
+// Strided tile-sweep kernels, float, field loop bound 16.
+#define MOLT_T float
+#define MOLT_TAG f32
 #define MOLT_NFMAX 16
-#include "molt_sweep_s32.inc"
+#include "molt_sweep_xs.inc"

@@ -1,3 +1,5 @@
-// strided-sweep kernels, float, field loop bound 4.
+// Strided tile-sweep kernels, float, field loop bound 4.
+#define MOLT_T float
+#define MOLT_TAG f32
 #define MOLT_NFMAX 4
-#include "molt_sweep_s32.inc"
+#include "molt_sweep_xs.inc"

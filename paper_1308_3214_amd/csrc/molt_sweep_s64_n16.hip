@@ -1,3 +1,5 @@
-// strided-sweep kernels, double, field loop bound 16.
+// Strided tile-sweep kernels, double, field loop bound 16.
+#define MOLT_T double
+#define MOLT_TAG f64
 #define MOLT_NFMAX 16
-#include "molt_sweep_s64.inc"
+#include "molt_sweep_xs.inc"

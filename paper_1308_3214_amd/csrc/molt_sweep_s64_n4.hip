@@ -1,3 +1,5 @@
-// strided-sweep kernels, double, field loop bound 4.
+// Strided tile-sweep kernels, double, field loop bound 4.
+#define MOLT_T double
+#define MOLT_TAG f64
 #define MOLT_NFMAX 4
-#include "molt_sweep_s64.inc"
+#include "molt_sweep_xs.inc"

@@ -1,3 +1,6 @@
 // x-sweep kernels, float, field loop bound 4.
+#define MOLT_KIND_X
+#define MOLT_T float
+#define MOLT_TAG f32
 #define MOLT_NFMAX 4
-#include "molt_sweep_x32.inc"
+#include "molt_sweep_xs.inc"

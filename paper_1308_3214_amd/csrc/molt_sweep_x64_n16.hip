@@ -1,3 +1,6 @@
 // x-sweep kernels, double, field loop bound 16.
+#define MOLT_KIND_X
+#define MOLT_T double
+#define MOLT_TAG f64
 #define MOLT_NFMAX 16
-#include "molt_sweep_x64.inc"
+#include "molt_sweep_xs.inc"

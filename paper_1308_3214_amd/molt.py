@@ -24,7 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 MOL_OK, MOL_E_INVALID, MOL_E_UNSUPPORTED, MOL_E_UNSTABLE, MOL_E_NOMEM, MOL_E_DEVICE = range(6)
 DIRICHLET, PERIODIC = 0, 1
 F64, F32 = 0, 1
-ALLOW_UNSTABLE, INCREMENT_FORM, NO_GRAPH, SPLIT_Y = 1, 2, 4, 8
+ALLOW_UNSTABLE, INCREMENT_FORM, NO_GRAPH, SPLIT_Y, UNIFORM_CONFIG = 1, 2, 4, 8, 16
 OPS = {"linv_x": 0, "linv_y": 1, "linv_z": 2, "d_x": 3, "d_y": 4, "d_z": 5, "C": 6, "D": 7, "rhs": 8}
 _STATUS = {1: "MOL_E_INVALID", 2: "MOL_E_UNSUPPORTED", 3: "MOL_E_UNSTABLE", 4: "MOL_E_NOMEM",
            5: "MOL_E_DEVICE"}
@@ -99,10 +99,16 @@ class _SrvInfo(ctypes.Structure):
                 ("finished", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
                 ("budget", ctypes.c_size_t), ("admit_seconds", ctypes.c_double),
-                ("admit_max_seconds", ctypes.c_double)]
+                ("admit_max_seconds", ctypes.c_double), ("round_seconds", ctypes.c_double),
+                ("rounds", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("sweeps", ctypes.c_int64)]
+
+
+SERVER_BATCHED = 1
 
 
 _lib.mol_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.mol_server_create_ex.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]
 _lib.mol_server_destroy.argtypes = [_vp]
 _lib.mol_server_submit.argtypes = [_vp, ctypes.POINTER(_Desc), _vp, ctypes.c_int, ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int64)]
@@ -113,16 +119,16 @@ _lib.mol_server_stats.argtypes = [_vp, ctypes.POINTER(_SrvInfo)]
 _lib.mol_server_last_error.restype = ctypes.c_char_p
 for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
            "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
-           "mol_solve", "mol_apply", "mol_step_batch", "mol_server_create", "mol_server_destroy",
-           "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
+           "mol_solve", "mol_apply", "mol_step_batch", "mol_server_create", "mol_server_create_ex",
+           "mol_server_destroy", "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
            "mol_workspace_bytes", "mol_start", "mol_step", "mol_solve", "mol_step_batch",
            "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
            "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error",
-           "mol_server_create", "mol_server_destroy", "mol_server_submit", "mol_server_poll",
-           "mol_server_result", "mol_server_stats", "mol_server_last_error")
+           "mol_server_create", "mol_server_create_ex", "mol_server_destroy", "mol_server_submit",
+           "mol_server_poll", "mol_server_result", "mol_server_stats", "mol_server_last_error")
 
 
 def _check(st):
@@ -286,13 +292,16 @@ class Plan:
 
 class Server:
     """Request server (continuous batching of independent solves, admitted by
-    device footprint).  submit() takes the initial field as a host numpy array
-    or a device tensor; the server keeps a reference until the result is
-    taken."""
+    device footprint).  batched=True: requests advance in rounds whose sweeps
+    of the same kernel run as one batched launch; else every request replays
+    its own graph on a stream of the pool.  submit() takes the initial field as
+    a host numpy array or a device tensor; the server keeps a reference until
+    the result is taken."""
 
-    def __init__(self, budget_bytes, nstreams=4):
+    def __init__(self, budget_bytes, nstreams=4, batched=False):
         h = _vp()
-        st = _lib.mol_server_create(int(budget_bytes), int(nstreams), ctypes.byref(h))
+        st = _lib.mol_server_create_ex(int(budget_bytes), int(nstreams),
+                                       SERVER_BATCHED if batched else 0, ctypes.byref(h))
         if st != MOL_OK:
             raise MolError(st, _lib.mol_server_last_error().decode())
         self._h = h

@@ -1,4 +1,5 @@
-"""GPU tests of the request server (serving many independent solves): every
+"""GPU tests of the request server (serving many independent solves), in both
+modes (stream pool; batched rounds whose launches carry many requests): every
 result of a mixed, queued workload equals the same request solved alone
 (bitwise: the same kernels on the same data), one small request matches the
 80-bit oracle, admission respects the device budget, and failures are
@@ -45,7 +46,7 @@ def _mix():
     rng = np.random.default_rng(5)
     for i, (n, P, dt) in enumerate([(100, 1, "f32"), (257, 2, "f32"), (600, 3, "f32"),
                                     (130, 2, "f64"), (300, 3, "f64"), (420, 1, "f32"),
-                                    (77, 3, "f32"), (513, 2, "f64")]):
+                                    (77, 3, "f32"), (513, 2, "f64"), (257, 2, "f32")]):
         cfl = float(rng.uniform(1.0, 4.0))
         u0 = W.gaussian_pulses_2d(n, seed=30 + i, npulses=4)
         reqs.append(dict(u0=u0, shape=(n, n), h=1.0 / (n - 1), nsteps=5 + i,
@@ -56,7 +57,8 @@ def _mix():
     return reqs
 
 
-def test_mixed_requests_equal_alone(torch_cuda, molt):
+@pytest.mark.parametrize("batched", [False, True])
+def test_mixed_requests_equal_alone(torch_cuda, molt, batched):
     torch = torch_cuda
     reqs = _mix()
     # a budget that holds only a few requests at a time: admission queues
@@ -66,7 +68,7 @@ def test_mixed_requests_equal_alone(torch_cuda, molt):
                 + 2 * es * int(np.prod(r["shape"])))
     budget = int(1.1 * max(foot(r) for r in reqs))
     assert sum(foot(r) for r in reqs) > 1.4 * budget      # admission must queue
-    srv = molt.Server(budget, nstreams=4)
+    srv = molt.Server(budget, nstreams=4, batched=batched)
     ids = [srv.submit(r["u0"], r["shape"], r["h"], r["nsteps"], **r["kw"]) for r in reqs]
     done = set()
     import time
@@ -77,9 +79,15 @@ def test_mixed_requests_equal_alone(torch_cuda, molt):
         time.sleep(0.001)
     st = srv.stats()
     assert st["bytes_peak"] <= budget and st["completed"] == len(ids)
+    if batched:
+        # some launches carried the sweeps of several requests
+        print("rounds", st["rounds"], "launches", st["launches"], "request sweeps", st["sweeps"])
+        assert st["rounds"] > 0 and st["sweeps"] > st["launches"]
     for rid, r in zip(ids, reqs):
         got = srv.result(rid)
-        ref = _alone(torch, molt, r["u0"], r["shape"], r["h"], r["nsteps"], **r["kw"])
+        # the batched server's plans take the size-independent configurations
+        kw = dict(r["kw"], flags=molt.UNIFORM_CONFIG) if batched else r["kw"]
+        ref = _alone(torch, molt, r["u0"], r["shape"], r["h"], r["nsteps"], **kw)
         print("request", rid, r["shape"], r["kw"].get("P"), r["kw"].get("dtype"),
               "max |mix - alone| =", float(np.abs(got - ref).max()))
         assert np.array_equal(got, ref), rid
@@ -87,11 +95,12 @@ def test_mixed_requests_equal_alone(torch_cuda, molt):
     srv.close()
 
 
-def test_server_result_matches_oracle(torch_cuda, molt, oracle_mod):
+@pytest.mark.parametrize("batched", [False, True])
+def test_server_result_matches_oracle(torch_cuda, molt, oracle_mod, batched):
     n, P, nsteps = 96, 2, 8
     h = 1.0 / (n - 1)
     u0 = W.gaussian_pulses_2d(n, seed=8, npulses=3, sigma=0.05)
-    srv = molt.Server(1 << 30, nstreams=2)
+    srv = molt.Server(1 << 30, nstreams=2, batched=batched)
     rid = srv.submit(u0, (n, n), h, nsteps, P=P, cfl=2.0, dtype="f64")
     import time
     t0 = time.time()
@@ -108,12 +117,43 @@ def test_server_result_matches_oracle(torch_cuda, molt, oracle_mod):
     srv.close()
 
 
-def test_server_budget_and_errors(torch_cuda, molt):
-    srv = molt.Server(1 << 20, nstreams=1)
+@pytest.mark.parametrize("batched", [False, True])
+def test_server_budget_and_errors(torch_cuda, molt, batched):
+    srv = molt.Server(1 << 20, nstreams=1, batched=batched)
     u0 = np.zeros((512, 512))
     with pytest.raises(molt.MolError):
         srv.submit(u0, (512, 512), 1 / 511, 3, P=2, cfl=2.0, dtype="f64")     # > budget
     with pytest.raises(molt.MolError):
         srv.submit(np.zeros((8, 8)), (8, 8), 1 / 7, 3, P=9, cfl=2.0)           # invalid P
     assert srv.stats()["queued"] == 0
+    srv.close()
+
+
+def test_batched_serving_stream_equals_alone(torch_cuda, molt):
+    # a burst of requests drawn like the serving workload (smaller sides and
+    # fewer steps): in batched rounds, each result is bitwise the solve alone
+    torch = torch_cuda
+    reqs = W.request_stream(24, 50.0, seed=3, steps=12, nmax=512, burst=True)
+    srv = molt.Server(1 << 30, nstreams=1, batched=True)
+    ids = []
+    for r in reqs:
+        n = r.n
+        u0 = W.request_initial(r).astype(np.float32)
+        ids.append((srv.submit(u0, (n, n), 1.0 / (n - 1), r.steps, P=r.P, cfl=r.cfl, dtype="f32"),
+                    u0, n, r))
+    done = set()
+    import time
+    t0 = time.time()
+    while len(done) < len(ids):
+        done.update(srv.poll())
+        assert time.time() - t0 < 60, "server did not finish"
+        time.sleep(0.001)
+    st = srv.stats()
+    print("rounds", st["rounds"], "launches", st["launches"], "request sweeps", st["sweeps"])
+    assert st["sweeps"] > st["launches"]
+    for rid, u0, n, r in ids:
+        got = srv.result(rid)
+        ref = _alone(torch, molt, u0, (n, n), 1.0 / (n - 1), r.steps, P=r.P, cfl=r.cfl, dtype="f32",
+                     flags=molt.UNIFORM_CONFIG)
+        assert np.array_equal(got, ref), (rid, n, r.P)
     srv.close()
