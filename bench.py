@@ -255,7 +255,13 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 64 MiB buffer 5 times (reference for the HBM byte counters)")
+    ap.add_argument("--only", choices=["star", "periodic3d"], default=None,
+                    help="only run one secondary workload for --steps steps (for profiling)")
     args = ap.parse_args()
+    if args.only:
+        fn = star_workload if args.only == "star" else periodic3d_workload
+        print(json.dumps({args.only: fn(steps=args.steps, warmup=args.warmup)}))
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")

@@ -1518,27 +1518,30 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
     __amdgpu_buffer_rsrc_t rso[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) rso[o] = make_rsrc(a.o[o] + blk, lineb);
+    // periodic lines wrap once (|p| < 2n); branch-free, so that no load sits
+    // under a branch
     auto wrap = [&](int p) -> int {
-        if (PER) {
-            if (p < 0) p += n;
-            if (p >= n) p -= n;
-        }
+        if (PER) p += n * ((int)(p < 0) - (int)(p >= n));
         return p;
     };
 
     typedef T Raw[NFP][S + 2];
     Raw xa, xb;
-    // loads of sub-tile t (none beyond the walk).  Issued without a branch: a
-    // load under a branch makes the compiler wait for it where the branch
-    // rejoins, which would serialise the prefetch.
+    // loads of sub-tile t (none beyond the walk, none outside [rlo, rhi)).
+    // Issued without a branch or a per-lane select: a load under a branch makes
+    // the compiler wait for every load in flight where the branch rejoins,
+    // which would serialise the prefetch.  A row without data is read through
+    // an empty resource (no memory access, value 0), chosen by a scalar select.
+    const __amdgpu_buffer_rsrc_t rnone = make_rsrc(a.f[0] + blk, 0);
     auto issue = [&](int t, Raw &xr) {
         const int p0 = wst + t * WS + wave * S;
 #pragma unroll
         for (int j = 0; j < S + 2; ++j) {
             const int r = p0 - 1 + j;
-            const int off = (t < Rw && r >= rlo && r < rhi) ? vl + wrap(r) * rowb : -16;
+            const bool ok = t < Rw && r >= rlo && r < rhi;
+            const int off = vl + wrap(r) * rowb;
 #pragma unroll
-            for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(rsf[c], off);
+            for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(ok ? rsf[c] : rnone, off);
         }
     };
 
@@ -1652,19 +1655,24 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
         return mnext ? B : 0.0;
     };
 
-    YYLev1<T, S, NO> c1, n1;        // level 1: sub-tiles t and t+1
-    YYLev2<T, S, NO> q0, q1, q2;    // level 2: sub-tiles t-2, t-1, t
+    // sub-tile states in two-slot rings indexed by the parity of the sub-tile
+    // (static: the step loop is unrolled by two), so no state is copied
+    YYLev1<T, S, NO> L1[2];         // level 1: sub-tiles t and t+1
+    YYLev2<T, S, NO> L2[2];         // level 2: sub-tiles t-1 and t (t-2 until it retires)
     T prevlast = T(0);              // wave 0: v1 at the row above its sub-tile
 
     issue(0, xa);
     issue(1, xb);
-    combine1(0, c1, xa);
+    combine1(0, L1[0], xa);
     issue(2, xa);
 
     // step t: level 1 finishes sub-tile t, level 2 combines t and finishes t-2;
     // xr holds the loads of sub-tile t+1 and receives those of t+3 (loads run
     // two sub-tiles ahead)
-    auto step = [&](int t, Raw &xr) {
+    auto step = [&](int t, Raw &xr, auto parity) {
+        constexpr int P0 = decltype(parity)::value, P1 = 1 - P0;   // parities of t and t+1
+        YYLev1<T, S, NO> &c1 = L1[P0], &n1 = L1[P1];
+        YYLev2<T, S, NO> &q0 = L2[P0], &q1 = L2[P1], &q2 = L2[P0];   // t-2, t-1, t
         if (t + 1 < Rw) combine1(t + 1, n1, xr);
         issue(t + 3, xr);
         __syncthreads();
@@ -1728,13 +1736,10 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
             agg2[t % 3][1][wave][lane] = q2.aR;
             if (wave == 0) prevlast = vlast[W - 1][lane];
         }
-        c1 = n1;
-        q0 = q1;
-        q1 = q2;
     };
     for (int t = 0; t < Rw + 2; t += 2) {
-        step(t, xb);
-        step(t + 1, xa);      // a step past the walk does nothing
+        step(t, xb, ic<0>{});
+        step(t + 1, xa, ic<1>{});      // a step past the walk does nothing
     }
 }
 template <typename T, int S, int W, int NO, bool PER, int NFP>
