@@ -41,12 +41,16 @@ int64_t strips_for(const PCfg &c, int64_t Tt, int64_t groups)
     return ns;
 }
 
-// rows of data next to a strip in a chained walk: K + 5 rounded up to whole
-// waves (roll d^roll below the rounding)
+// rows of data next to a strip in a chained walk: the smallest r with
+// (r + 1) d^r <= 2^-(24 + 4) (level 2 is exact to about roll d^roll at the
+// strip's ends; FP32 rounding with four bits to spare), in whole waves
 int yy_roll(const DirCoef &dc, int S)
 {
-    const int64_t r = ((int64_t)dc.halo + 5 + S - 1) / S * S;
-    return r > (int64_t)1 << 30 ? 1 << 30 : (int)r;
+    const double lim = std::ldexp(1.0, -28);
+    int64_t r = 1;
+    while (r < ((int64_t)1 << 20) && (double)(r + 1) * std::exp(-dc.nu * (double)r) > lim) ++r;
+    r = (r + S - 1) / S * S;
+    return (int)r;
 }
 
 template <typename T>
@@ -292,11 +296,24 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
     (void)nf;
     (void)no;
     if (op.yy) {
-        for (int i = 0; i < NYCFG; ++i) {
+        // the first valid configuration whose strips fill the chip (>= 256
+        // workgroups), else the first valid one
+        static const int order[] = {0, 4, 1, 2, 3};
+        static_assert(NYCFG == 5, "chained configuration order out of step");
+        const int64_t groups = ((g.n[0] + 63) / 64) * (dir == 1 ? g.n[2] : g.n[1]);
+        int first = -1;
+        for (int i : order) {
             cfg[0] = i;
-            if (config_valid(g, dc, op, fp64, cfg)) return 0;
+            if (!config_valid(g, dc, op, fp64, cfg)) continue;
+            if (first < 0) first = i;
+            const PCfg c = kYCfg[i];
+            const int64_t WS = (int64_t)c.S * c.W;
+            const int64_t Tt = (dc.n + WS - 1) / WS;
+            if (strips_for(c, Tt, groups) * groups >= 256) return 0;
         }
-        return -1;
+        if (first < 0) return -1;
+        cfg[0] = first;
+        return 0;
     }
     if (dir == 0) {
         const int64_t n = g.n[0];

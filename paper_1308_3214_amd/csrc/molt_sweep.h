@@ -1446,7 +1446,8 @@ k_sweep_p_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first,
 // sub-tile before and after it where it has neighbours; of those, only `roll`
 // rows next to the strip hold data (the rest read 0), with zero carries at the
 // walk's ends: level 1 is then exact to d^roll at the strip's first and last
-// rows, level 2 to roll * d^roll, both below the rounding (roll >= K + 5).
+// rows, level 2 to about roll * d^roll, both below the rounding (the host
+// takes the smallest roll with (roll + 1) d^roll <= 2^-28).
 // Periodic lines are walked as the periodic continuation (rows wrap on load);
 // they have no end node.
 template <typename T, int S, int NO>

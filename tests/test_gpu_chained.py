@@ -44,7 +44,7 @@ def dev(torch, a):
 # (shape (ny, nx), h (hx, hy), bc (x, y), cfl); dt = cfl h_x / c, so nu_y =
 # beta h_y / (cfl h_x) sets the halo of the y lines
 CASES = [
-    ((128, 64), (1.0 / 63, 1.0 / 127), 0, 2.0),        # two sub-tiles: one strip, no walk ends
+    ((128, 64), 1.0 / 127, 0, 2.0),                    # two sub-tiles: one strip, no walk ends
     ((129, 65), (1.0 / 64, 1.0 / 128), 0, 2.0),        # ragged last sub-tile and column group
     ((1100, 70), 1.0 / 1099, 0, 2.0),                  # several strips per line
     ((1100, 70), 1.0 / 1099, (0, 1), 2.0),             # periodic y
