@@ -138,6 +138,63 @@ def periodic3d_workload(steps=200, warmup=10):
     return also_line(ms, steps, info, n ** 3)
 
 
+# Table 3 of the paper (ADI refinement study, 641^2 on [-1, 1]^2, T = 1.2,
+# dt = 0.025, beta = beta_max(P)): printed max-over-steps L2 error and run time
+# in seconds; the paper states no hardware or precision.
+PAPER_TABLE3_DT0025 = {1: (4.84e-3, 30.0), 2: (4.97e-5, 94.2), 3: (2.29e-6, 186.2)}
+
+
+def table3_workload(P, dt=0.025, T=1.2, dtype="f64", reps=5):
+    """The paper's ADI refinement workload on the GPU: sin(pi x) sin(pi y) on
+    641^2 nodes, analytic u^1, steps to T; wall time of the whole run (graph
+    replay, fields resident) and the max-over-steps L2 error against the exact
+    standing mode (an untimed second pass)."""
+    import numpy as np
+    import torch
+    from paper_1308_3214_amd import molt
+    from paper_1308_3214_amd import workloads as W
+    u0, h = W.table3_mode(641)
+    om = np.sqrt(2.0) * np.pi
+    nsteps = int(round(T / dt))
+    plan = molt.Plan(u0.shape, h, 0, P=P, dt=dt, dtype=dtype)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    a0 = torch.tensor(u0, dtype=td, device="cuda")
+    b0 = torch.tensor(u0 * np.cos(om * dt), dtype=td, device="cuda")
+    a, b = a0.clone(), b0.clone()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan.solve(a, b, nsteps - 1)            # warm: graph capture
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a.copy_(a0)
+        b.copy_(b0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(st):
+            e0.record(st)
+            plan.solve(a, b, nsteps - 1)
+            e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    # error pass: one step at a time
+    ex = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    a.copy_(a0)
+    b.copy_(b0)
+    err = float(torch.sqrt(h * h * ((b.double() - ex * np.cos(om * dt)) ** 2).sum()))
+    for s_ in range(2, nsteps + 1):
+        plan.solve(a, b, 1)
+        torch.cuda.synchronize()
+        err = max(err, float(torch.sqrt(h * h * ((b.double() - ex * np.cos(om * s_ * dt)) ** 2).sum())))
+    plan.close()
+    run_ms = min(times)
+    pe, pt = PAPER_TABLE3_DT0025.get(P, (None, None)) if abs(dt - 0.025) < 1e-12 else (None, None)
+    return {"P": P, "dtype": dtype, "steps": nsteps, "run_ms": round(run_ms, 4),
+            "ms_per_step": round(run_ms / (nsteps - 1), 5), "max_L2_error": float("%.3e" % err),
+            "paper_max_L2_error": pe, "paper_run_s": pt}
+
+
 def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=False, steps=100,
           batched=False):
     """The serving workload: a Poisson stream of independent FP32 requests
@@ -255,9 +312,12 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 64 MiB buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["star", "periodic3d"], default=None,
+    ap.add_argument("--only", choices=["star", "periodic3d", "table3"], default=None,
                     help="only run one secondary workload for --steps steps (for profiling)")
     args = ap.parse_args()
+    if args.only == "table3":
+        print(json.dumps({"table3": [table3_workload(P) for P in (1, 2, 3)]}))
+        return
     if args.only:
         fn = star_workload if args.only == "star" else periodic3d_workload
         print(json.dumps({args.only: fn(steps=args.steps, warmup=args.warmup)}))
@@ -341,6 +401,7 @@ def main():
         k64 = max(20, args.steps // 4)
         ms2, _, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
         also["%dx%d_P%d_f64" % (n, n, P)] = also_line(ms2, k64, inf2, points)
+        also["paper_table3_641_dt0.025"] = [table3_workload(P) for P in (1, 2, 3)]
         also["star2048_P3_f32_300steps"] = star_workload()
         also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
         out["also"] = also
