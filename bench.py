@@ -116,6 +116,16 @@ def also_line(ms, steps, info, points):
             "model_hbm_frac": round(info["bytes_per_step"] / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def line1d_workload(steps=200, warmup=10):
+    """1D, N = 1024, Dirichlet, P = 1, CFL 2, FP64, two sine modes with seeded
+    amplitudes (the 1D configuration): one line of 1024 nodes per step."""
+    from paper_1308_3214_amd import workloads as W
+    n = 1024
+    _, u0, _ = W.sine_modes_1d(n, seed=1)
+    ms, _, info = run_plan((n,), 1.0 / (n - 1), 0, 1, 2.0, "f64", u0, steps, warmup, profile=False)
+    return also_line(ms, steps, info, n)
+
+
 def star_workload(steps=300, warmup=10):
     """2048^2 star cavity, P = 3, CFL 1.5, FP32 (line objects, Sec. 4.3)."""
     from paper_1308_3214_amd import workloads as W
@@ -401,6 +411,7 @@ def main():
         k64 = max(20, args.steps // 4)
         ms2, _, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
         also["%dx%d_P%d_f64" % (n, n, P)] = also_line(ms2, k64, inf2, points)
+        also["line1d_1024_P1_f64_200steps"] = line1d_workload()
         also["paper_table3_641_dt0.025"] = [table3_workload(P) for P in (1, 2, 3)]
         also["star2048_P3_f32_300steps"] = star_workload()
         also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
