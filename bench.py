@@ -419,9 +419,13 @@ def main():
     if not args.no_serve:
         # stream pool (per-request graphs on three streams) and batched rounds
         # (one launch per kernel across all admitted requests)
+        # admission-limited (2 GiB) and with the whole burst admitted (32 GiB)
         out["serving"] = {"poisson": serve(), "burst": serve(burst=True),
                           "batched": {"poisson": serve(batched=True),
-                                      "burst": serve(burst=True, batched=True)}}
+                                      "burst": serve(burst=True, batched=True)},
+                          "budget_32GiB": {"burst_pool": serve(burst=True, budget=32 << 30),
+                                           "burst_batched": serve(burst=True, batched=True,
+                                                                  budget=32 << 30)}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, P, args.cfl, 1)
     print(json.dumps(out))
