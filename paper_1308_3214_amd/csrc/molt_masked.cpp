@@ -306,8 +306,10 @@ bool transverse(Builder &b, Program &prog, const std::vector<int> &cw, int dw,
         if (!b.emit(prog, 0, cmb, outs, 0)) return false;
     }
     // y sweeps: b_k = D_y w_k and la_k = a_k - D_y a_k in one launch per k
+    std::vector<int> bv(cw.size());
     for (size_t k = 0; k < cw.size(); ++k) {
         const int bb = b.new_ws(), la = b.new_ws();
+        bv[k] = bb;
         OutSpec o1{}, o2{};
         o1.buf = bb;
         o1.dc[0] = 1.0;
@@ -318,6 +320,14 @@ bool transverse(Builder &b, Program &prog, const std::vector<int> &cw, int dw,
         terms.push_back({lin(la) + lin(bb), lin(bb), -1.0});
     }
     if (dw >= 0) {
+        // D w = w - L_x^{-1}(L_y^{-1} w) with L_y^{-1} w = w - D_y w: when w
+        // is also an input of C, its D_y w is b_k above and no sweep is needed
+        for (size_t k = 0; k < cw.size(); ++k) {
+            if (cw[k] == dw) {
+                terms.push_back({lin(bv[k]), lin(dw) + lin(bv[k], -1.0), 1.0});
+                return true;
+            }
+        }
         const int tt = b.new_ws();
         OutSpec o{};
         o.buf = tt;
