@@ -17,6 +17,8 @@ Contents
 * ``scheme.py``: A_p(beta) (Sec. 3, the A_p equation), c_{p,m} (eq. Full_2D),
   beta_max(P) (Theorem of Sec. 3.1, eq. Stab_cond).
 * ``lines.py``: line objects of an embedded boundary (Sec. 4.3).
+* ``Problem.step_source``: the step with a source term (Sec. 4, inclusion of
+  source terms), P = 1 and 2, composed from the oracle's own step and C.
 """
 from __future__ import annotations
 
@@ -199,6 +201,35 @@ class Problem:
         c = self._coef(P, beta)
         _check(self._lib().or_step(self.ref, P, _p(c), _p(u_prev), _p(u_curr), _p(out)))
         return self._out(out)
+
+    def source_terms(self, s_prev, s_curr, s_next, P, beta):
+        """Source part of one step for u_tt / c^2 = laplacian(u) + S (Sec. 4,
+        inclusion of source terms), with (c dt)^2 = (beta / alpha)^2.
+
+        P = 1: (c dt)^2 S^n, the source part of the dt^2 term of the even
+        Taylor series of u^{n+1} - 2 u^n + u^{n-1}.
+        P = 2: (c dt)^2 / 12 (S^{n+1} + 10 S^n + S^{n-1})
+               - beta^2 (c dt)^2 / 12 C[S^n].
+        The second term is the dt^4 / 12 c^4 laplacian(S) term of the expansion
+        with the laplacian replaced by -alpha^2 C, as the convolution operators
+        replace it in the homogeneous part.  (The printed coefficient of
+        C[S^n] has the dimension of the first term times a length^2; with it
+        the scheme is second-order.)  FP64; s_prev and s_next are unused for
+        P = 1."""
+        if P not in (1, 2):
+            raise ValueError("source terms are given for P = 1 and 2")
+        a2 = (float(beta) / self.alpha) ** 2
+        s_curr = np.asarray(s_curr, dtype=np.float64)
+        if P == 1:
+            return a2 * s_curr
+        s_prev = np.asarray(s_prev, dtype=np.float64)
+        s_next = np.asarray(s_next, dtype=np.float64)
+        sig = a2 / 12.0
+        return sig * (s_next + 10.0 * s_curr + s_prev) - float(beta) ** 2 * sig * self.C(s_curr)
+
+    def step_source(self, u_prev, u_curr, s_prev, s_curr, s_next, P, beta):
+        """u^{n+1} = 2 u^n - u^{n-1} + rhs(u^n) + source_terms (P = 1, 2)."""
+        return self.step(u_prev, u_curr, P, beta) + self.source_terms(s_prev, s_curr, s_next, P, beta)
 
     def start(self, u0, P, beta):
         u0, out = self._io(u0)

@@ -86,6 +86,18 @@ def table3_mode(n: int = 641):
     return np.outer(s, s), 2.0 / (n - 1)
 
 
+def sine_mode(n: int, ndim: int):
+    """prod_k sin(pi x_k) on [-1, 1]^ndim with n nodes per direction (zero on
+    the boundary nodes); returns (field, h)."""
+    x = -1.0 + 2.0 * np.arange(n, dtype=np.float64) / (n - 1)
+    s = np.sin(np.pi * x)
+    s[0] = s[-1] = 0.0
+    f = s
+    for _ in range(ndim - 1):
+        f = np.multiply.outer(s, f)
+    return np.ascontiguousarray(f), 2.0 / (n - 1)
+
+
 # --------------------------------------------------------------------------
 # 3D plane waves on the periodic unit cube
 # --------------------------------------------------------------------------

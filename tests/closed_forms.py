@@ -9,6 +9,8 @@
   digits: no closed-form weight is shared with the oracle.
 * ``mode_max_error``: the three-level scheme acting on one eigenmode is a
   scalar recurrence a_{n+1} = (2 + r) a_n - a_{n-1}.
+* ``forced_mode_*``: the same with a source S = g(t) phi on the mode phi:
+  a_{n+1} = (2 + r) a_n - a_{n-1} + (source of the step acting on g).
 """
 from __future__ import annotations
 
@@ -75,3 +77,54 @@ def table3_error(P, dt, beta, n=641, T=1.2):
     ns = int(mp.nint(mp.mpf(T) / dt))
     seq = mode_sequence(r, 1, mp.cos(om * dt), ns)
     return max(abs(seq[k] - mp.cos(om * k * dt)) for k in range(1, ns + 1))
+
+
+def mode_symbols(h, alpha, ndim):
+    """(Chat, Dhat) of the sine mode sin(pi x) ... on [-1, 1]^ndim with spacing
+    h in every direction: directional symbol d = 1 - khat(pi h, alpha h);
+    1D: C = D = d; 2D: C = 2d - 2d^2, D = 2d - d^2; 3D: C = 3d - 6d^2 + 3d^3,
+    D = 3d - 3d^2 + d^3 (the ADI compositions of equal directional symbols)."""
+    d = 1 - khat(mp.pi * h, alpha * h)
+    if ndim == 1:
+        return d, d
+    if ndim == 2:
+        return 2 * d - 2 * d ** 2, 2 * d - d ** 2
+    return 3 * d - 6 * d ** 2 + 3 * d ** 3, 3 * d - 3 * d ** 2 + d ** 3
+
+
+def forced_source(P, beta, alpha, Chat, g_prev, g, g_next, coef="derived"):
+    """Source part of one step acting on S = g phi.  coef = "derived":
+    -beta^2 (c dt)^2 / 12 C[S^n]; coef = "printed": +beta^2 / (12 alpha^4) C[S^n]."""
+    beta = mp.mpf(beta)
+    a2 = (beta / alpha) ** 2
+    if P == 1:
+        return a2 * g
+    s = a2 / 12 * (g_next + 10 * g + g_prev)
+    if coef == "derived":
+        return s - beta ** 2 * a2 / 12 * Chat * g
+    return s + beta ** 2 / (12 * alpha ** 4) * Chat * g
+
+
+def forced_mode_sequence(P, beta, dt, h, ndim, gfun, a0, a1, nsteps, coef="derived"):
+    """a_0 .. a_nsteps of the scheme with source g(t) phi on the sine mode."""
+    dt = mp.mpf(dt)
+    alpha = mp.mpf(beta) / dt
+    Chat, Dhat = mode_symbols(mp.mpf(h), alpha, ndim)
+    r = rhs_symbol(P, beta, Chat, Dhat)
+    out = [mp.mpf(a0), mp.mpf(a1)]
+    for k in range(1, nsteps):
+        t = k * dt
+        src = forced_source(P, beta, alpha, Chat, gfun(t - dt), gfun(t), gfun(t + dt), coef)
+        out.append((2 + r) * out[-1] - out[-2] + src)
+    return out
+
+
+def forced_mode_error(P, dt, beta, coef="derived", n=641, T=1.2, w0=2):
+    """Max over steps of |a_n - A(t_n)| for the forced mode A(t) = cos(w0 t) of
+    u_tt = laplacian(u) + S on [-1, 1]^2 (c = 1): S = (2 pi^2 - w0^2) cos(w0 t)
+    sin(pi x) sin(pi y), u^0, u^1 exact, n^2 nodes (the Table 3 grid)."""
+    h = mp.mpf(2) / (n - 1)
+    g = lambda t: (2 * mp.pi ** 2 - w0 ** 2) * mp.cos(w0 * t)
+    ns = int(mp.nint(mp.mpf(T) / dt))
+    seq = forced_mode_sequence(P, beta, dt, h, 2, g, 1, mp.cos(w0 * mp.mpf(dt)), ns, coef)
+    return max(abs(seq[k] - mp.cos(w0 * k * mp.mpf(dt))) for k in range(1, ns + 1))
