@@ -136,6 +136,26 @@ mol_status mol_start(mol_plan *plan, const void *u0, const void *g, void *u1, vo
 mol_status mol_step(mol_plan *plan, const void *u_prev, const void *u_curr, void *u_next,
                     void *stream);
 
+/* One step with a source term (Sec. 4, inclusion of source terms) for
+ * u_tt / c^2 = laplacian(u) + S, with (c dt)^2 = (beta / alpha)^2:
+ *   P = 1: u_next = 2 u_curr - u_prev + rhs(u_curr) + (c dt)^2 s_curr
+ *   P = 2: u_next = 2 u_curr - u_prev + rhs(u_curr)
+ *                   + (c dt)^2 / 12 (s_next + 10 s_curr + s_prev)
+ *                   - beta^2 (c dt)^2 / 12 C[s_curr]
+ * s_prev, s_curr, s_next: device fields of S at t_{n-1}, t_n, t_{n+1}, the
+ * plan's dtype and shape (read only; S in the units of laplacian(u)).  The
+ * C[S^n] coefficient is the dt^4 c^4 laplacian(S) / 12 term of the Taylor
+ * expansion with the laplacian replaced by -alpha^2 C; the coefficient as
+ * printed is not dimensionally consistent and gives a second-order scheme.
+ * Dirichlet boundary nodes of u_next are 0 whatever S is there.  A source that
+ * depends on u (S^{n+1} through u^{n+1}) needs the caller's iteration.
+ * s_prev and s_next are not read for P = 1 (may be NULL).  Box plans with
+ * P = 1 or 2 only, else MOL_E_UNSUPPORTED.  Aliasing as mol_step; u_next must
+ * not overlap a source field.  Asynchronous on stream. */
+mol_status mol_step_source(mol_plan *plan, const void *u_prev, const void *u_curr, void *u_next,
+                           const void *s_prev, const void *s_curr, const void *s_next,
+                           void *stream);
+
 /* nsteps >= 0 steps in place: on entry (u_prev_io, u_curr_io) = (u^{n-1}, u^n),
  * on return (u^{n+nsteps-1}, u^{n+nsteps}).  Unless MOL_NO_GRAPH is set, the
  * step sequence is captured once in a hipGraph and replayed.  Asynchronous. */

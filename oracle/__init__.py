@@ -228,8 +228,19 @@ class Problem:
         return sig * (s_next + 10.0 * s_curr + s_prev) - float(beta) ** 2 * sig * self.C(s_curr)
 
     def step_source(self, u_prev, u_curr, s_prev, s_curr, s_next, P, beta):
-        """u^{n+1} = 2 u^n - u^{n-1} + rhs(u^n) + source_terms (P = 1, 2)."""
-        return self.step(u_prev, u_curr, P, beta) + self.source_terms(s_prev, s_curr, s_next, P, beta)
+        """u^{n+1} = 2 u^n - u^{n-1} + rhs(u^n) + source_terms (P = 1, 2), and
+        u^{n+1} = 0 on the nodes of a Dirichlet boundary (homogeneous data,
+        Sec. 2), as the homogeneous step gives there whatever S is."""
+        out = self.step(u_prev, u_curr, P, beta) + self.source_terms(s_prev, s_curr, s_next, P, beta)
+        for d in range(self.ndim):
+            if self._s.bc[d] == 0:
+                ax = self.ndim - 1 - d          # grid axis d (x = 0) is array axis ndim-1-d
+                idx = [slice(None)] * self.ndim
+                idx[ax] = 0
+                out[tuple(idx)] = 0.0
+                idx[ax] = -1
+                out[tuple(idx)] = 0.0
+        return out
 
     def start(self, u0, P, beta):
         u0, out = self._io(u0)

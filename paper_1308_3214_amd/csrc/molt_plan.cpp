@@ -572,6 +572,8 @@ bool build_rhs(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo
 }
 
 // single operators
+bool emit_CD(Builder &b, Program &prog, bool isC, int in, int out);
+
 bool build_apply(Builder &b, Program &prog, int op)
 {
     mol_plan_ &pl = b.pl;
@@ -591,45 +593,76 @@ bool build_apply(Builder &b, Program &prog, int op)
     }
     if (pl.masked) return build_apply_masked(b, prog, op);
     if (op == MOL_OP_RHS) return build_rhs(b, prog, B_IN, {{B_OUT, Lin{}, 1.0}});
-    const bool isC = (op == MOL_OP_C);
+    return emit_CD(b, prog, op == MOL_OP_C, B_IN, B_OUT);
+}
+
+// out = C in or D in on a box (eqs. C_def_ADI, D_def_ADI and their 3D forms).
+bool emit_CD(Builder &b, Program &prog, bool isC, int in, int out)
+{
+    const int nd = b.pl.geom.ndim;
     if (nd == 1) {
         OutSpec o{};
-        o.buf = B_OUT;
+        o.buf = out;
         o.dc[0] = 1.0;
-        return b.emit(prog, 0, {lin(B_IN)}, {o}, 1);
+        return b.emit(prog, 0, {lin(in)}, {o}, 1);
     }
     if (nd == 2) {
         const int y = b.new_ws();
         OutSpec o{};
         o.buf = y;
         o.dc[0] = 1.0;
-        if (!b.emit(prog, 1, {lin(B_IN)}, {o}, 0)) return false;
+        if (!b.emit(prog, 1, {lin(in)}, {o}, 0)) return false;
         OutSpec f{};
-        f.buf = B_OUT;
+        f.buf = out;
         f.elem = lin(y);
         f.dc[0] = 1.0;
-        return b.emit(prog, 0, {lin(B_IN) + lin(y, isC ? -2.0 : -1.0)}, {f}, 1);
+        return b.emit(prog, 0, {lin(in) + lin(y, isC ? -2.0 : -1.0)}, {f}, 1);
     }
     const int z = b.new_ws(), y = b.new_ws(), yz = b.new_ws();
     OutSpec oz{};
     oz.buf = z;
     oz.dc[0] = 1.0;
-    if (!b.emit(prog, 2, {lin(B_IN)}, {oz}, 0)) return false;
+    if (!b.emit(prog, 2, {lin(in)}, {oz}, 0)) return false;
     OutSpec o1{}, o2{};
     o1.buf = y;
     o1.dc[0] = 1.0;
     o2.buf = yz;
     o2.dc[1] = 1.0;
-    if (!b.emit(prog, 1, {lin(B_IN), lin(z)}, {o1, o2}, 0)) return false;
+    if (!b.emit(prog, 1, {lin(in), lin(z)}, {o1, o2}, 0)) return false;
     OutSpec f{};
-    f.buf = B_OUT;
+    f.buf = out;
     f.dc[0] = 1.0;
     if (isC) {
         f.elem = lin(y) + lin(z) + lin(yz, -2.0);
-        return b.emit(prog, 0, {lin(B_IN) + lin(y, -2.0) + lin(z, -2.0) + lin(yz, 3.0)}, {f}, 1);
+        return b.emit(prog, 0, {lin(in) + lin(y, -2.0) + lin(z, -2.0) + lin(yz, 3.0)}, {f}, 1);
     }
     f.elem = lin(y) + lin(z) + lin(yz, -1.0);
-    return b.emit(prog, 0, {lin(B_IN) + lin(y, -1.0) + lin(z, -1.0) + lin(yz)}, {f}, 1);
+    return b.emit(prog, 0, {lin(in) + lin(y, -1.0) + lin(z, -1.0) + lin(yz)}, {f}, 1);
+}
+
+// Step with a source term for u_tt / c^2 = laplacian(u) + S (Sec. 4, inclusion
+// of source terms), (c dt)^2 = (beta / alpha)^2:
+//   P = 1: u^{n+1} = 2 u^n - u^{n-1} + rhs(u^n) + (c dt)^2 S^n
+//   P = 2: ... + (c dt)^2 / 12 (S^{n+1} + 10 S^n + S^{n-1}) - beta^2 (c dt)^2 / 12 C[S^n]
+// The C[S^n] coefficient is the dt^4 c^4 laplacian(S) / 12 term of the Taylor
+// expansion with the laplacian replaced by -alpha^2 C, as in the homogeneous
+// part.  C[S^n] goes to a workspace field; the other source terms join the
+// elementwise part of the step's last sweep.
+bool build_step_source(Builder &b, Program &prog)
+{
+    mol_plan_ &pl = b.pl;
+    const double a2 = (pl.beta / pl.alpha) * (pl.beta / pl.alpha);
+    Lin elem = lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0);
+    if (pl.desc.P == 1) {
+        elem = elem + lin(B_IN, a2);
+    } else {
+        const double sg = a2 / 12.0;
+        const int cs = b.new_ws();
+        if (!emit_CD(b, prog, true, B_IN, cs)) return false;
+        elem = elem + lin(B_SPREV, sg) + lin(B_IN, 10.0 * sg) + lin(B_SNEXT, sg) +
+               lin(cs, -pl.beta * pl.beta * sg);
+    }
+    return build_rhs(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}});
 }
 
 std::string tune_problem_key(const mol_plan_ *pl)
@@ -787,6 +820,15 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
                                   {B_UPREV, lin(B_UPREV), 1.0}},
                                  pl->chain_a);
     }
+    // step with a source term: its workspace ids start again from the first
+    // field (the other programs keep nothing there between calls)
+    if (ok && !pl->masked && d->P <= 2) {
+        const int n0 = pl->nws;
+        pl->nws = 0;
+        pl->has_src = build_step_source(b, pl->step_src);
+        if (!pl->has_src) pl->step_src.clear();
+        pl->nws = std::max(n0, pl->nws);
+    }
     // start: u1 = u0 + rhs(u0)/2
     ok = ok && build_rhs(b, pl->start, B_IN, {{B_OUT, lin(B_IN), 0.5}});
     for (int op = 0; op <= MOL_OP_RHS && ok; ++op) {
@@ -800,7 +842,8 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
 }
 
 void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const void *ucurr, void *unext,
-                const void *in, void *out, const void **fp, void **op)
+                const void *in, void *out, const void **fp, void **op, const void *sprev,
+                const void *snext)
 {
     auto res = [&](int b) -> void * {
         switch (b) {
@@ -809,6 +852,8 @@ void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const 
         case B_UNEXT: return unext;
         case B_IN: return const_cast<void *>(in);
         case B_OUT: return out;
+        case B_SPREV: return const_cast<void *>(sprev);
+        case B_SNEXT: return const_cast<void *>(snext);
         default: return pl->ws[b - B_WS0];
         }
     };
@@ -818,12 +863,13 @@ void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const 
 }
 
 hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
-                       void *unext, const void *in, void *out, hipStream_t st)
+                       void *unext, const void *in, void *out, hipStream_t st, const void *sprev,
+                       const void *snext)
 {
     for (const ProgOp &po : prog) {
         const void *fp[MAXF];
         void *op[MAXO + 1];
-        resolve_op(pl, po, uprev, ucurr, unext, in, out, fp, op);
+        resolve_op(pl, po, uprev, ucurr, unext, in, out, fp, op, sprev, snext);
         hipError_t e;
         if (pl->masked)
             e = launch_seg_op(po.op, pl, fp, op, st);
@@ -996,6 +1042,22 @@ mol_status mol_step(mol_plan *pl, const void *u_prev, const void *u_curr, void *
     hipError_t e = run_program(pl, pl->step, u_prev, u_curr, u_next, nullptr, nullptr,
                                (hipStream_t)stream);
     return e == hipSuccess ? MOL_OK : dev_err(e, "mol_step");
+}
+
+mol_status mol_step_source(mol_plan *pl, const void *u_prev, const void *u_curr, void *u_next,
+                           const void *s_prev, const void *s_curr, const void *s_next, void *stream)
+{
+    if (!pl || !u_prev || !u_curr || !u_next || !s_curr) return fail(MOL_E_INVALID, "NULL argument");
+    if (!pl->has_src)
+        return fail(MOL_E_UNSUPPORTED, "source terms are given for box grids with P = 1 and 2");
+    if (pl->desc.P == 2 && (!s_prev || !s_next))
+        return fail(MOL_E_INVALID, "P = 2 needs the source at three time levels");
+    if (u_next == u_curr) return fail(MOL_E_INVALID, "u_next must not overlap u_curr");
+    if (u_next == s_curr || (pl->desc.P == 2 && (u_next == s_prev || u_next == s_next)))
+        return fail(MOL_E_INVALID, "u_next must not overlap a source field");
+    hipError_t e = run_program(pl, pl->step_src, u_prev, u_curr, u_next, s_curr, nullptr,
+                               (hipStream_t)stream, s_prev, s_next);
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_step_source");
 }
 
 mol_status mol_apply(mol_plan *pl, int op, const void *in, void *out, void *stream)

@@ -11,7 +11,10 @@
 namespace molt {
 
 // buffer ids inside a program: caller fields, then plan workspace fields
-enum { B_UPREV = 0, B_UCURR = 1, B_UNEXT = 2, B_IN = 3, B_OUT = 4, B_WS0 = 5 };
+// Buffers of a program: caller fields, then workspace fields from B_WS0.  The
+// step with a source term reads S^n as B_IN and S^{n-1}, S^{n+1} as B_SPREV,
+// B_SNEXT.
+enum { B_UPREV = 0, B_UCURR = 1, B_UNEXT = 2, B_IN = 3, B_OUT = 4, B_SPREV = 5, B_SNEXT = 6, B_WS0 = 7 };
 
 struct ProgOp {
     SweepOp op;
@@ -37,6 +40,10 @@ struct mol_plan_ {
     molt::Program solve_pro, solve_step, solve_inc_step;
     int chain_a = -1;
     molt::Program apply[9];
+    // step with a source term (box plans, P <= 2; workspace shared with the
+    // other programs: it holds nothing between calls)
+    molt::Program step_src;
+    bool has_src = false;
     int dev = 0;
     // graph cache for mol_solve
     hipGraphExec_t gexec = nullptr;
@@ -131,10 +138,12 @@ hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *con
 // Device pointers of one launch of a program: fields (op.nf) and outputs
 // (op.no, then the chained output) for the given caller fields.
 void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const void *ucurr, void *unext,
-                const void *in, void *out, const void **fp, void **op);
+                const void *in, void *out, const void **fp, void **op, const void *sprev = nullptr,
+                const void *snext = nullptr);
 // Run a program on st (one launch per op).
 hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
-                       void *unext, const void *in, void *out, hipStream_t st);
+                       void *unext, const void *in, void *out, hipStream_t st,
+                       const void *sprev = nullptr, const void *snext = nullptr);
 
 // plans whose workspace is allocated and freed in stream order on st (no
 // device-wide synchronisation; used by the request server)

@@ -82,3 +82,16 @@ def test_source_free_step_is_the_plain_step(oracle_mod):
         assert np.array_equal(pb.step_source(up, uc, z, z, z, P, b), pb.step(up, uc, P, b))
     with pytest.raises(ValueError):
         pb.step_source(up, uc, z, z, z, 3, scheme.beta_max(3))
+
+
+def test_source_step_keeps_dirichlet_nodes_zero(oracle_mod):
+    # a source that is nonzero on the boundary does not move a Dirichlet node
+    # (x Dirichlet, y periodic here)
+    rng = np.random.default_rng(4)
+    shape = (24, 17)
+    pb = oracle_mod.Problem(shape, (1.0 / 16, 1.0 / 24), (0, 1), 25.0)
+    f = [rng.standard_normal(shape) for _ in range(5)]
+    for P in (1, 2):
+        out = pb.step_source(*f, P, scheme.beta_max(P))
+        assert np.all(out[:, 0] == 0) and np.all(out[:, -1] == 0)
+        assert np.all(out[0, 1:-1] != 0)
