@@ -148,6 +148,54 @@ def periodic3d_workload(steps=200, warmup=10):
     return also_line(ms, steps, info, n ** 3)
 
 
+def source_workload(n=4096, steps=200, warmup=10):
+    """The 4096^2 P = 2 FP32 CFL 2 step with a source term (mol_step_source):
+    a Gaussian point source (width 3 h, centre of the square) times a
+    sinusoid switched on smoothly, its fields at t_{n-1}, t_n, t_{n+1}
+    resident in HBM; against plain mol_step on the same buffers (both
+    eager, one launch per sweep)."""
+    import numpy as np
+    import torch
+    from paper_1308_3214_amd import molt
+    from paper_1308_3214_amd import workloads as W
+    h = 1.0 / (n - 1)
+    plan = molt.Plan((n, n), h, 0, P=2, cfl=2.0, dtype="f32")
+    info = plan.info
+    dt = 2.0 * h
+    x = np.arange(n) * h - 0.5
+    g = np.exp(-x ** 2 / (2 * (3 * h) ** 2))
+    G = torch.tensor(np.outer(g, g) / (2 * np.pi * (3 * h) ** 2), dtype=torch.float32, device="cuda")
+    w = 2 * np.pi / (40 * h)
+    f = lambda t: np.sin(w * t) * (1 - np.exp(-(t / (200 * h)) ** 2))
+    t0 = 100 * dt
+    sp, sc, sn = G * f(t0 - dt), G * f(t0), G * f(t0 + dt)
+    u = [torch.tensor(W.gaussian_pulses_2d(n, seed=1), dtype=torch.float32, device="cuda")
+         for _ in range(3)]
+    stream = torch.cuda.Stream()
+    out = {}
+    for name, call in (("step_source", lambda a, b, c: plan.step_source(a, b, c, sp, sc, sn, stream=stream)),
+                       ("step", lambda a, b, c: plan.step(a, b, c, stream=stream))):
+        with torch.cuda.stream(stream):
+            for k in range(warmup):
+                call(u[k % 3], u[(k + 1) % 3], u[(k + 2) % 3])
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for k in range(steps):
+                call(u[k % 3], u[(k + 1) % 3], u[(k + 2) % 3])
+            e1.record(stream)
+            stream.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+    torch.cuda.synchronize()
+    assert all(torch.isfinite(x).all().item() for x in u), "non-finite field"
+    plan.close()
+    ms = out["step_source"]
+    return {"Mpoint-updates/s": round(n * n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 5),
+            "kernels": info["kernels_per_source_step"],
+            "model_hbm_frac": round(info["bytes_per_source_step"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "plain_step_ms": round(out["step"], 5)}
+
+
 # Table 3 of the paper (ADI refinement study, 641^2 on [-1, 1]^2, T = 1.2,
 # dt = 0.025, beta = beta_max(P)): printed max-over-steps L2 error and run time
 # in seconds; the paper states no hardware or precision.
@@ -322,14 +370,15 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 64 MiB buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["star", "periodic3d", "table3"], default=None,
+    ap.add_argument("--only", choices=["star", "periodic3d", "table3", "source"], default=None,
                     help="only run one secondary workload for --steps steps (for profiling)")
     args = ap.parse_args()
     if args.only == "table3":
         print(json.dumps({"table3": [table3_workload(P) for P in (1, 2, 3)]}))
         return
     if args.only:
-        fn = star_workload if args.only == "star" else periodic3d_workload
+        fn = {"star": star_workload, "periodic3d": periodic3d_workload,
+              "source": source_workload}[args.only]
         print(json.dumps({args.only: fn(steps=args.steps, warmup=args.warmup)}))
         return
     if args.copy_calibration:
@@ -415,6 +464,7 @@ def main():
         also["paper_table3_641_dt0.025"] = [table3_workload(P) for P in (1, 2, 3)]
         also["star2048_P3_f32_300steps"] = star_workload()
         also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
+        also["source_4096_P2_f32_200steps"] = source_workload()
         out["also"] = also
     if not args.no_serve:
         # stream pool (per-request graphs on three streams) and batched rounds

@@ -102,6 +102,8 @@ typedef struct mol_plan_info {
     int kernels_per_step;   /* kernel launches in one mol_step */
     double bytes_per_step;  /* algorithmic HBM bytes of one step (fields read + written) */
     size_t workspace_bytes; /* device workspace held by the plan */
+    int kernels_per_source_step;   /* launches of one mol_step_source, 0 if unsupported */
+    double bytes_per_source_step;  /* its algorithmic HBM bytes */
 } mol_plan_info;
 
 /* beta_max(P): first positive root of -sum_{p<=P} A_p(beta) = 4

@@ -1023,6 +1023,10 @@ mol_status mol_plan_get_info(const mol_plan *pl, mol_plan_info *info)
     info->kernels_per_step = (int)sp.size();
     info->bytes_per_step = program_bytes(pl, sp);
     info->workspace_bytes = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes;
+    if (pl->has_src) {
+        info->kernels_per_source_step = (int)pl->step_src.size();
+        info->bytes_per_source_step = program_bytes(pl, pl->step_src);
+    }
     return MOL_OK;
 }
 

@@ -65,6 +65,8 @@ class _Info(ctypes.Structure):
         ("kernels_per_step", ctypes.c_int),
         ("bytes_per_step", ctypes.c_double),
         ("workspace_bytes", ctypes.c_size_t),
+        ("kernels_per_source_step", ctypes.c_int),
+        ("bytes_per_source_step", ctypes.c_double),
     ]
 
 
@@ -220,6 +222,8 @@ class Plan:
             "nu": tuple(info.nu), "points": info.points, "unknowns": info.unknowns,
             "segments": tuple(info.segments), "kernels_per_step": info.kernels_per_step,
             "bytes_per_step": info.bytes_per_step, "workspace_bytes": info.workspace_bytes,
+            "kernels_per_source_step": info.kernels_per_source_step,
+            "bytes_per_source_step": info.bytes_per_source_step,
         }
 
     def close(self):
