@@ -19,6 +19,10 @@ Contents
 * ``lines.py``: line objects of an embedded boundary (Sec. 4.3).
 * ``Problem.step_source``: the step with a source term (Sec. 4, inclusion of
   source terms), P = 1 and 2, composed from the oracle's own step and C.
+* ``Problem.D_avg``, ``rhs_with``, ``step_avg``: D averaged over both orders of
+  the directional inverses (Sec. 4, operation count: averaging the sweep
+  permutations against the anisotropy) and the Table 2 schedule with a given
+  D, in plain Python over the oracle's own L_gamma^{-1} and C.
 """
 from __future__ import annotations
 
@@ -138,11 +142,13 @@ class Problem:
                 s.nseg[d] = idx.shape[0]
                 s.seg_idx[d] = idx.ctypes.data
                 s.seg_th[d] = th.ctypes.data
+        self._mask = None
         if mask is not None:
             m = np.ascontiguousarray(mask, dtype=np.uint8)
             assert m.shape == shape
             self._keep.append(m)
             s.mask = m.ctypes.data
+            self._mask = m.astype(np.float64)
         self._s = s
         self.alpha = float(alpha)
 
@@ -241,6 +247,39 @@ class Problem:
                 idx[ax] = -1
                 out[tuple(idx)] = 0.0
         return out
+
+    def _proj(self, v):
+        """Zero outside nodes of a mask (they read and are written as 0)."""
+        v = np.asarray(v, dtype=np.float64)
+        return v * self._mask if self._mask is not None else v
+
+    def D_avg(self, v):
+        """v - (L_x^{-1} L_y^{-1} v + L_y^{-1} L_x^{-1} v) / 2 (2D): the D of
+        eq. D_def_ADI averaged over the two orders of the inverses."""
+        if self.ndim != 2:
+            raise ValueError("the averaged D is defined here for 2D grids")
+        v = self._proj(v)
+        xy = self.linv(self.linv(v, 1), 0)
+        yx = self.linv(self.linv(v, 0), 1)
+        return self._proj(v - 0.5 * (self._proj(xy) + self._proj(yx)))
+
+    def rhs_with(self, u, P, beta, D):
+        """sum_p sum_m c_{p,m} C^{m-1} D^{p-m} C u in the order of Table 2
+        (stage p: C on every earlier term, D on the newest one), with the
+        operator D given; C is the oracle's."""
+        c = stage_coefficients(P, beta)
+        v = [self.C(self._proj(u))]
+        out = c[0, 0] * v[0]
+        for p in range(2, P + 1):
+            v = [self.C(x) for x in v] + [D(v[-1])]
+            for k, x in enumerate(v):            # term k carries p - k factors of C
+                out = out + c[p - 1, p - k - 1] * x
+        return self._proj(out)
+
+    def step_avg(self, u_prev, u_curr, P, beta):
+        """u^{n+1} = 2 u^n - u^{n-1} + rhs with the averaged D."""
+        return self._proj(2.0 * np.asarray(u_curr, dtype=np.float64) - np.asarray(u_prev, dtype=np.float64)
+                          + self.rhs_with(u_curr, P, beta, self.D_avg))
 
     def start(self, u0, P, beta):
         u0, out = self._io(u0)
