@@ -126,14 +126,15 @@ def line1d_workload(steps=200, warmup=10):
     return also_line(ms, steps, info, n)
 
 
-def star_workload(steps=300, warmup=10):
-    """2048^2 star cavity, P = 3, CFL 1.5, FP32 (line objects, Sec. 4.3)."""
+def star_workload(steps=300, warmup=10, flags=0):
+    """2048^2 star cavity, P = 3, CFL 1.5, FP32 (line objects, Sec. 4.3);
+    flags = MOL_SYMMETRIC_D averages D over both sweep orders."""
     from paper_1308_3214_amd import workloads as W
     n = 2048
     dom, mask, cross = W.star_domain(n, seed=1)
     u0 = W.star_pulses(dom, mask, seed=1)
     ms, _, info = run_plan((n, n), 1.0 / (n - 1), 0, 3, 1.5, "f32", u0, steps, warmup,
-                           profile=False, mask=mask, cross=cross)
+                           profile=False, mask=mask, cross=cross, flags=flags)
     out = also_line(ms, steps, info, info["unknowns"])
     out["points"] = "inside nodes (%d)" % info["unknowns"]
     return out
@@ -463,6 +464,7 @@ def main():
         also["line1d_1024_P1_f64_200steps"] = line1d_workload()
         also["paper_table3_641_dt0.025"] = [table3_workload(P) for P in (1, 2, 3)]
         also["star2048_P3_f32_300steps"] = star_workload()
+        also["star2048_P3_f32_300steps_averaged_D"] = star_workload(flags=_m.SYMMETRIC_D)
         also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
         also["source_4096_P2_f32_200steps"] = source_workload()
         out["also"] = also

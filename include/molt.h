@@ -60,10 +60,16 @@ enum {
     MOL_NO_GRAPH = 4,         /* mol_solve launches kernels directly instead of a hipGraph */
     MOL_SPLIT_Y = 8,          /* mol_solve (2D, P = 2) sweeps y twice in two launches instead of
                                  one chained launch (same operator; for comparisons) */
-    MOL_UNIFORM_CONFIG = 16   /* launch configurations that do not depend on the grid size where
+    MOL_UNIFORM_CONFIG = 16,  /* launch configurations that do not depend on the grid size where
                                  the size allows (x: one line capacity up to 2048 nodes; y/z:
                                  the tile kernel), so that plans of different sizes share
                                  kernels; no tuning-cache entries (used by the batched server) */
+    MOL_SYMMETRIC_D = 32      /* masked plans: D = 1 - (L_x^-1 L_y^-1 + L_y^-1 L_x^-1) / 2, the
+                                 mean over both orders of the directional inverses, in place of
+                                 1 - L_x^-1 L_y^-1 (averaging the sweep orders against the
+                                 anisotropy of ADI, Sec. 4, operation count); no extra sweep.
+                                 A mask symmetric under x <-> y then gives solutions that are.
+                                 Box plans: no effect (the directional operators commute). */
 };
 
 /* Problem descriptor (Sec. 2: domain, c, dt, beta; Sec. 3: order P;

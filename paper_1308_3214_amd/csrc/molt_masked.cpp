@@ -286,18 +286,23 @@ struct Term {
 };
 
 // the transverse work of C on the inputs cw and of D on dw (dw < 0: none);
-// returns one Term per C input (in order) and then the D term
+// returns one Term per C input (in order) and then the D term.  With avg,
+// D is the mean over the two orders of the directional inverses.
 bool transverse(Builder &b, Program &prog, const std::vector<int> &cw, int dw,
-                std::vector<Term> &terms)
+                std::vector<Term> &terms, bool avg)
 {
+    // the averaged D of an input that C does not take needs that input's
+    // D_x w, D_y w and L_y^{-1} D_x w too: sweep it with the C inputs
+    std::vector<int> w = cw;
+    if (avg && dw >= 0 && std::find(cw.begin(), cw.end(), dw) == cw.end()) w.push_back(dw);
     // x sweeps a_k = D_x w_k, two per launch
-    std::vector<int> av(cw.size());
-    for (size_t k = 0; k < cw.size(); k += 2) {
+    std::vector<int> av(w.size());
+    for (size_t k = 0; k < w.size(); k += 2) {
         std::vector<Lin> cmb;
         std::vector<OutSpec> outs;
-        for (size_t j = k; j < std::min(cw.size(), k + 2); ++j) {
+        for (size_t j = k; j < std::min(w.size(), k + 2); ++j) {
             av[j] = b.new_ws();
-            cmb.push_back(lin(cw[j]));
+            cmb.push_back(lin(w[j]));
             OutSpec o{};
             o.buf = av[j];
             o.dc[j - k] = 1.0;
@@ -305,28 +310,36 @@ bool transverse(Builder &b, Program &prog, const std::vector<int> &cw, int dw,
         }
         if (!b.emit(prog, 0, cmb, outs, 0)) return false;
     }
-    // y sweeps: b_k = D_y w_k and la_k = a_k - D_y a_k in one launch per k
-    std::vector<int> bv(cw.size());
-    for (size_t k = 0; k < cw.size(); ++k) {
+    // y sweeps: b_k = D_y w_k and la_k = a_k - D_y a_k = L_y^{-1} D_x w_k in
+    // one launch per k
+    std::vector<int> bv(w.size()), lv(w.size());
+    for (size_t k = 0; k < w.size(); ++k) {
         const int bb = b.new_ws(), la = b.new_ws();
         bv[k] = bb;
+        lv[k] = la;
         OutSpec o1{}, o2{};
         o1.buf = bb;
         o1.dc[0] = 1.0;
         o2.buf = la;
         o2.elem = lin(av[k]);
         o2.dc[1] = -1.0;
-        if (!b.emit(prog, 1, {lin(cw[k]), lin(av[k])}, {o1, o2}, 0)) return false;
-        terms.push_back({lin(la) + lin(bb), lin(bb), -1.0});
+        if (!b.emit(prog, 1, {lin(w[k]), lin(av[k])}, {o1, o2}, 0)) return false;
+        if (k < cw.size()) terms.push_back({lin(la) + lin(bb), lin(bb), -1.0});
     }
     if (dw >= 0) {
-        // D w = w - L_x^{-1}(L_y^{-1} w) with L_y^{-1} w = w - D_y w: when w
-        // is also an input of C, its D_y w is b_k above and no sweep is needed
-        for (size_t k = 0; k < cw.size(); ++k) {
-            if (cw[k] == dw) {
+        // D w = w - L_x^{-1}(L_y^{-1} w) = D_y w + D_x(w - D_y w) with
+        // L_y^{-1} w = w - D_y w: when w is also an input of C, its D_y w is
+        // b_k above and no sweep is needed.  The other order,
+        // w - L_y^{-1}(L_x^{-1} w) = D_y w + L_y^{-1} D_x w, needs no sweep
+        // either, so the mean of the two is
+        //   D_y w + (L_y^{-1} D_x w) / 2 + D_x(w - D_y w) / 2.
+        for (size_t k = 0; k < w.size(); ++k) {
+            if (w[k] != dw) continue;
+            if (avg)
+                terms.push_back({lin(bv[k]) + lin(lv[k], 0.5), lin(dw, 0.5) + lin(bv[k], -0.5), 1.0});
+            else
                 terms.push_back({lin(bv[k]), lin(dw) + lin(bv[k], -1.0), 1.0});
-                return true;
-            }
+            return true;
         }
         const int tt = b.new_ws();
         OutSpec o{};
@@ -347,6 +360,7 @@ bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalO
     mol_plan_ &pl = b.pl;
     const int P = pl.desc.P;
     const double beta = pl.beta;
+    const bool avg = (pl.desc.flags & MOL_SYMMETRIC_D) != 0;
     std::vector<int> v{u};
     int accbuf = -1;
     for (int p = 1; p <= P; ++p) {
@@ -354,7 +368,7 @@ bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalO
         std::vector<Term> terms;
         // stage p: C on every input, D on the newest (p >= 2); term k carries
         // m = p - k factors of C (Table 2)
-        if (!transverse(b, prog, v, p >= 2 ? v[nin - 1] : -1, terms)) return false;
+        if (!transverse(b, prog, v, p >= 2 ? v[nin - 1] : -1, terms, avg)) return false;
         const int nt = (int)terms.size();
         Lin acc_in;
         if (p == 2) acc_in = lin(v[0], stage_c(1, 1, beta));
@@ -418,10 +432,11 @@ bool build_apply_masked(Builder &b, Program &prog, int op)
     }
     if (op == MOL_OP_RHS) return build_rhs_masked(b, prog, B_IN, {{B_OUT, Lin{}, 1.0}});
     std::vector<Term> terms;
+    const bool avg = (b.pl.desc.flags & MOL_SYMMETRIC_D) != 0;
     if (op == MOL_OP_C) {
-        if (!transverse(b, prog, {B_IN}, -1, terms)) return false;
+        if (!transverse(b, prog, {B_IN}, -1, terms, avg)) return false;
     } else if (op == MOL_OP_D) {
-        if (!transverse(b, prog, {}, B_IN, terms)) return false;
+        if (!transverse(b, prog, {}, B_IN, terms, avg)) return false;
     } else {
         b.err = "operator not available on a masked plan";
         return false;

@@ -24,7 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 MOL_OK, MOL_E_INVALID, MOL_E_UNSUPPORTED, MOL_E_UNSTABLE, MOL_E_NOMEM, MOL_E_DEVICE = range(6)
 DIRICHLET, PERIODIC = 0, 1
 F64, F32 = 0, 1
-ALLOW_UNSTABLE, INCREMENT_FORM, NO_GRAPH, SPLIT_Y, UNIFORM_CONFIG = 1, 2, 4, 8, 16
+ALLOW_UNSTABLE, INCREMENT_FORM, NO_GRAPH, SPLIT_Y, UNIFORM_CONFIG, SYMMETRIC_D = 1, 2, 4, 8, 16, 32
 OPS = {"linv_x": 0, "linv_y": 1, "linv_z": 2, "d_x": 3, "d_y": 4, "d_z": 5, "C": 6, "D": 7, "rhs": 8}
 _STATUS = {1: "MOL_E_INVALID", 2: "MOL_E_UNSUPPORTED", 3: "MOL_E_UNSTABLE", 4: "MOL_E_NOMEM",
            5: "MOL_E_DEVICE"}
