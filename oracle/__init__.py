@@ -19,6 +19,8 @@ Contents
 * ``lines.py``: line objects of an embedded boundary (Sec. 4.3).
 * ``Problem.step_source``: the step with a source term (Sec. 4, inclusion of
   source terms), P = 1 and 2, composed from the oracle's own step and C.
+* ``Problem.start_g``: u^1 with an initial velocity (Sec. 3.2), the odd
+  Taylor terms through the same schedule with the weights b_{p,m}.
 * ``Problem.D_avg``, ``rhs_with``, ``step_avg``: D averaged over both orders of
   the directional inverses (Sec. 4, operation count: averaging the sweep
   permutations against the anisotropy) and the Table 2 schedule with a given
@@ -238,6 +240,12 @@ class Problem:
         u^{n+1} = 0 on the nodes of a Dirichlet boundary (homogeneous data,
         Sec. 2), as the homogeneous step gives there whatever S is."""
         out = self.step(u_prev, u_curr, P, beta) + self.source_terms(s_prev, s_curr, s_next, P, beta)
+        return self._project_field(out)
+
+    def _project_field(self, out):
+        """A field of the solution: 0 on Dirichlet boundary nodes (homogeneous
+        data) and on outside nodes of a mask."""
+        out = np.array(out, dtype=np.float64)
         for d in range(self.ndim):
             if self._s.bc[d] == 0:
                 ax = self.ndim - 1 - d          # grid axis d (x = 0) is array axis ndim-1-d
@@ -246,7 +254,24 @@ class Problem:
                 out[tuple(idx)] = 0.0
                 idx[ax] = -1
                 out[tuple(idx)] = 0.0
-        return out
+        return self._proj(out)
+
+    def rhs_coef(self, u, coef):
+        """The Table 2 schedule of the oracle's rhs with a given P x P weight
+        matrix coef[p-1, m-1]."""
+        u, out = self._io(u)
+        c = np.ascontiguousarray(coef, dtype=self.rt)
+        _check(self._lib().or_rhs(self.ref, c.shape[0], _p(c), _p(u), _p(out)))
+        return self._out(out)
+
+    def start_g(self, u0, g, P, beta, c=1.0):
+        """u^1 with an initial velocity g (Sec. 3.2): the even Taylor terms
+        u0 + rhs(u0)/2 and the odd ones dt (g + sum_{p<=P} sum_m b_{p,m}
+        C^{m-1} D^{p-m} C g), dt = beta / (alpha c)."""
+        dt = float(beta) / (self.alpha * c)
+        g = np.asarray(g, dtype=np.float64)
+        odd = dt * (g + self.rhs_coef(g, scheme.start_coefficients(P, beta)))
+        return self._project_field(self.start(u0, P, beta) + odd)
 
     def _proj(self, v):
         """Zero outside nodes of a mask (they read and are written as 0)."""

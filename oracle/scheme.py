@@ -5,6 +5,8 @@ package docstring).
   (Sec. 3, the A_p equation following eq. update_P).
 * ``stage_coefficients(P, beta)``: c_{p,m} = (-1)^m 2 beta^{2m}/(2m)! binom(p-1, m-1),
   the weight of C^m D^{p-m} in eq. Full_2D (Sec. 4); sum_m c_{p,m} = A_p.
+* ``start_coefficients(P, beta)``: b_{p,m} of the odd part of the start
+  (Sec. 3.2 with the operator expansion of Sec. 4).
 * ``beta_max(P)``: the first positive root of -sum_{p<=P} A_p(beta) = 4
   (Theorem of Sec. 3.1, eq. Stab_cond), i.e. S(beta, 1) = 4 with S from
   eq. Stab_sum.
@@ -32,6 +34,25 @@ def c_pm(p: int, m: int, beta):
     return Fraction(2 * (-1) ** m * comb(p - 1, m - 1), factorial(2 * m)) * beta ** (2 * m) \
         if isinstance(beta, Fraction) else \
         2.0 * (-1) ** m * comb(p - 1, m - 1) / factorial(2 * m) * float(beta) ** (2 * m)
+
+
+def b_pm(p: int, m: int, beta):
+    """Weight of C^m D^{p-m} in the odd part of the start (Sec. 3.2): the
+    series sum_m beta^{2m}/(2m+1)! (laplacian/alpha^2)^m with
+    (laplacian/alpha^2)^m = (-1)^m C^m (1 - D)^{-m} (the expansion behind
+    eq. Full_2D): b_{p,m} = (-1)^m beta^{2m}/(2m+1)! binom(p-1, m-1)."""
+    if isinstance(beta, Fraction):
+        return Fraction((-1) ** m * comb(p - 1, m - 1), factorial(2 * m + 1)) * beta ** (2 * m)
+    return (-1) ** m * comb(p - 1, m - 1) / factorial(2 * m + 1) * float(beta) ** (2 * m)
+
+
+def start_coefficients(P: int, beta: float) -> np.ndarray:
+    """P x P matrix, entry [p-1, m-1] = b_{p,m} (zero for m > p)."""
+    c = np.zeros((P, P), dtype=np.float64)
+    for p in range(1, P + 1):
+        for m in range(1, p + 1):
+            c[p - 1, m - 1] = b_pm(p, m, beta)
+    return c
 
 
 def stage_coefficients(P: int, beta: float) -> np.ndarray:

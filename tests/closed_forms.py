@@ -128,3 +128,31 @@ def forced_mode_error(P, dt, beta, coef="derived", n=641, T=1.2, w0=2):
     ns = int(mp.nint(mp.mpf(T) / dt))
     seq = forced_mode_sequence(P, beta, dt, h, 2, g, 1, mp.cos(w0 * mp.mpf(dt)), ns, coef)
     return max(abs(seq[k] - mp.cos(w0 * k * mp.mpf(dt))) for k in range(1, ns + 1))
+
+
+def start_symbol_b(P, beta, Chat, Dhat):
+    """sum_{p<=P} sum_{m<=p} (-1)^m beta^{2m}/(2m+1)! binom(p-1,m-1) Chat^m Dhat^{p-m}:
+    the odd part of the start (Sec. 3.2) on a mode, exact integers."""
+    beta = mp.mpf(beta)
+    s = mp.mpf(0)
+    for p in range(1, P + 1):
+        for m in range(1, p + 1):
+            s += (-1) ** m * beta ** (2 * m) / factorial(2 * m + 1) * comb(p - 1, m - 1) \
+                * Chat ** m * Dhat ** (p - m)
+    return s
+
+
+def started_mode_error(P, dt, beta, n=641, T=1.2):
+    """Max over steps of the error of the 2D scheme for u = (cos(w t) + sin(w t))
+    sin(pi x) sin(pi y) on the Table 3 grid (w = sqrt(2) pi, g = w phi) with u^1
+    from the start formula instead of the exact value."""
+    h = mp.mpf(2) / (n - 1)
+    dt = mp.mpf(dt)
+    alpha = mp.mpf(beta) / dt
+    Chat, Dhat = mode_symbols(h, alpha, 2)
+    r = rhs_symbol(P, beta, Chat, Dhat)
+    w = mp.sqrt(2) * mp.pi
+    a1 = 1 + r / 2 + dt * w * (1 + start_symbol_b(P, beta, Chat, Dhat))
+    ns = int(mp.nint(mp.mpf(T) / dt))
+    seq = mode_sequence(r, 1, a1, ns)
+    return max(abs(seq[k] - mp.cos(w * k * dt) - mp.sin(w * k * dt)) for k in range(1, ns + 1))
