@@ -132,10 +132,15 @@ mol_status mol_plan_get_info(const mol_plan *plan, mol_plan_info *info);
  * invalid.  For admission by footprint. */
 size_t mol_workspace_bytes(const mol_desc *desc);
 
-/* Starting value (Sec. 3.2).  g == NULL (zero initial velocity):
- * u1 = u0 + rhs(u0)/2, the even Taylor terms to order 2P with the spatial
- * derivatives from the convolution operators.  g != NULL: MOL_E_UNSUPPORTED.
- * u0 and u1 must not overlap. */
+/* Starting value u1 = u(dt) (Sec. 3.2) from u0 = u(0) and g = u_t(0): the
+ * Taylor series of u(dt) with every time derivative turned into powers of the
+ * laplacian.  The even terms give u0 + rhs(u0)/2 (the step's weights); the odd
+ * terms give dt sum_m beta^{2m} / (2m+1)! (laplacian / alpha^2)^m g, taken with
+ * the same schedule and weights b_{p,m} = (-1)^m beta^{2m} / (2m+1)!
+ * binom(p-1, m-1) for p <= P:  u1 = u0 + rhs(u0)/2 + dt (g + rhs_b(g)).
+ * g == NULL: zero initial velocity.  g is a device field like u0 (read only);
+ * u1 is 0 on Dirichlet and outside nodes.  u0 and u1 must not overlap, nor g
+ * and u1. */
 mol_status mol_start(mol_plan *plan, const void *u0, const void *g, void *u1, void *stream);
 
 /* One step of the three-level scheme: u_next = 2 u_curr - u_prev + rhs(u_curr).

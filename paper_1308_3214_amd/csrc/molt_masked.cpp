@@ -371,13 +371,13 @@ bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalO
         if (!transverse(b, prog, v, p >= 2 ? v[nin - 1] : -1, terms, avg)) return false;
         const int nt = (int)terms.size();
         Lin acc_in;
-        if (p == 2) acc_in = lin(v[0], stage_c(1, 1, beta));
+        if (p == 2) acc_in = lin(v[0], b.coef(1, 1));
         else if (p >= 3) acc_in = lin(accbuf);
         if (p == P) {
             // one x sweep of the weighted sum of this stage's terms
             Lin es = acc_in, cs;
             for (int k = 0; k < nt; ++k) {
-                const double c = stage_c(p, p - k, beta);
+                const double c = b.coef(p, p - k);
                 es = es + c * terms[k].elem;
                 cs = cs + (c * terms[k].s) * terms[k].comb;
             }
@@ -405,14 +405,14 @@ bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalO
                 o.buf = newacc;
                 o.elem = acc_done;
                 for (int j = k; j < k1; ++j) {
-                    const double c = stage_c(p, p - j, beta);
+                    const double c = b.coef(p, p - j);
                     o.elem = o.elem + c * terms[j].elem;
                     o.dc[j - k] = c * terms[j].s;
                 }
                 outs.push_back(o);
             }
             if (!b.emit(prog, 0, cmb, outs, 0)) return false;
-            for (int j = k; j < k1; ++j) acc_done = acc_done + lin(nv[j], stage_c(p, p - j, beta));
+            for (int j = k; j < k1; ++j) acc_done = acc_done + lin(nv[j], b.coef(p, p - j));
         }
         v = nv;
         accbuf = newacc;

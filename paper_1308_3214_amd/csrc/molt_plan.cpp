@@ -70,6 +70,15 @@ double molt::stage_c(int p, int m, double beta)
     return ((m % 2) ? -2.0 : 2.0) * std::pow(beta, 2 * m) / fact(2 * m) * binom(p - 1, m - 1);
 }
 
+// Weight of C^m D^{p-m} in the odd part of the start (Sec. 3.2): the series
+// sum_m beta^{2m} / (2m+1)! (laplacian / alpha^2)^m g with (laplacian /
+// alpha^2)^m = (-1)^m C^m (1 - D)^{-m} expanded as for eq. Full_2D:
+// b_{p,m} = (-1)^m beta^{2m} / (2m+1)! binom(p-1, m-1).
+double molt::start_b(int p, int m, double beta)
+{
+    return ((m % 2) ? -1.0 : 1.0) * std::pow(beta, 2 * m) / fact(2 * m + 1) * binom(p - 1, m - 1);
+}
+
 // A_p = sum_m c_{p,m}: the 1D weights (eq. update_P)
 double molt::A_p(int p, double beta)
 {
@@ -389,9 +398,9 @@ bool build_rhs_1d(Builder &b, Program &prog, int u, const std::vector<FinalOut> 
         o.buf = w[p];
         o.dc[0] = 1.0;
         if (!b.emit(prog, 0, {lin(w[p - 1])}, {o}, 0)) return false;
-        acc = acc + lin(w[p], A_p(p, pl.beta));
+        acc = acc + lin(w[p], b.Ap(p));
     }
-    return b.emit(prog, 0, {lin(w[P - 1])}, finals(fo, acc, A_p(P, pl.beta)), 1);
+    return b.emit(prog, 0, {lin(w[P - 1])}, finals(fo, acc, b.Ap(P)), 1);
 }
 
 // 2D / 3D rectangles and boxes: stage schedule of Table 2; each application of
@@ -416,7 +425,7 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
         // x sweep's combination G = c22 (v1 - 2y) + c21 (v1 - y) and its
         // elementwise part H = elem + r (c11 v1 + (c22 + c21) y).
         const int V1 = Builder::V1, Y = Builder::Y;
-        const double c11 = stage_c(1, 1, beta), c22 = stage_c(2, 2, beta), c21 = stage_c(2, 1, beta);
+        const double c11 = b.coef(1, 1), c22 = b.coef(2, 2), c21 = b.coef(2, 1);
         const Lin gs = c22 * (lin(V1) + lin(Y, -2.0)) + c21 * (lin(V1) + lin(Y, -1.0));
         const Lin hs = lin(V1, c11) + c22 * lin(Y) + c21 * lin(Y);
         const int G = b.new_ws(), H = b.new_ws();
@@ -509,13 +518,13 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
         const int nt = (int)g.size();          // == p
         // earlier-stage terms carried into this stage
         Lin acc_in;
-        if (p == 2) acc_in = lin(v[0], stage_c(1, 1, beta));   // v_1 = C u
+        if (p == 2) acc_in = lin(v[0], b.coef(1, 1));   // v_1 = C u
         else if (p >= 3) acc_in = lin(accbuf);
         if (p == P) {
             // one sweep of the weighted sum of this stage's terms
             Lin gs, hs = acc_in;
             for (int k = 0; k < nt; ++k) {
-                const double c = stage_c(p, p - k, beta);
+                const double c = b.coef(p, p - k);
                 gs = gs + c * g[k];
                 hs = hs + c * h[k];
             }
@@ -546,14 +555,14 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
                 o.buf = newacc;
                 o.elem = acc_done;
                 for (int j = k; j < k1; ++j) {
-                    const double c = stage_c(p, p - j, beta);
+                    const double c = b.coef(p, p - j);
                     o.elem = o.elem + c * h[j];
                     o.dc[j - k] = c;
                 }
                 outs.push_back(o);
             }
             if (!b.emit(prog, 0, cmb, outs, 0)) return false;
-            for (int j = k; j < k1; ++j) acc_done = acc_done + lin(nv[j], stage_c(p, p - j, beta));
+            for (int j = k; j < k1; ++j) acc_done = acc_done + lin(nv[j], b.coef(p, p - j));
         }
         // stage p+1 inputs: terms in Table 2 order (m = p, p-1, ..., 1)
         v = nv;
@@ -659,10 +668,25 @@ bool build_step_source(Builder &b, Program &prog)
         const double sg = a2 / 12.0;
         const int cs = b.new_ws();
         if (!emit_CD(b, prog, true, B_IN, cs)) return false;
-        elem = elem + lin(B_SPREV, sg) + lin(B_IN, 10.0 * sg) + lin(B_SNEXT, sg) +
+        elem = elem + lin(B_AUX0, sg) + lin(B_IN, 10.0 * sg) + lin(B_AUX1, sg) +
                lin(cs, -pl.beta * pl.beta * sg);
     }
     return build_rhs(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}});
+}
+
+// Start with an initial velocity g (Sec. 3.2): the even terms of the Taylor
+// series of u(dt) give u0 + rhs(u0)/2 as without g; the odd ones give
+// dt sum_m beta^{2m} / (2m+1)! (laplacian / alpha^2)^m g, taken with Table 2's
+// schedule and weights b_{p,m} (p <= P):  t = dt (g + rhs_b(g)), then
+// u1 = u0 + t + rhs(u0) / 2.
+bool build_start_g(Builder &b, Program &prog)
+{
+    const double dt = b.pl.desc.dt;
+    const int t = b.new_ws();
+    b.series = 1;
+    const bool ok = build_rhs(b, prog, B_AUX0, {{t, lin(B_AUX0, dt), dt}});
+    b.series = 0;
+    return ok && build_rhs(b, prog, B_IN, {{B_OUT, lin(B_IN) + lin(t), 0.5}});
 }
 
 std::string tune_problem_key(const mol_plan_ *pl)
@@ -829,6 +853,13 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
         if (!pl->has_src) pl->step_src.clear();
         pl->nws = std::max(n0, pl->nws);
     }
+    if (ok) {
+        const int n0 = pl->nws;
+        pl->nws = 0;
+        pl->has_start_g = build_start_g(b, pl->start_g);
+        if (!pl->has_start_g) pl->start_g.clear();
+        pl->nws = std::max(n0, pl->nws);
+    }
     // start: u1 = u0 + rhs(u0)/2
     ok = ok && build_rhs(b, pl->start, B_IN, {{B_OUT, lin(B_IN), 0.5}});
     for (int op = 0; op <= MOL_OP_RHS && ok; ++op) {
@@ -842,8 +873,8 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
 }
 
 void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const void *ucurr, void *unext,
-                const void *in, void *out, const void **fp, void **op, const void *sprev,
-                const void *snext)
+                const void *in, void *out, const void **fp, void **op, const void *aux0,
+                const void *aux1)
 {
     auto res = [&](int b) -> void * {
         switch (b) {
@@ -852,8 +883,8 @@ void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const 
         case B_UNEXT: return unext;
         case B_IN: return const_cast<void *>(in);
         case B_OUT: return out;
-        case B_SPREV: return const_cast<void *>(sprev);
-        case B_SNEXT: return const_cast<void *>(snext);
+        case B_AUX0: return const_cast<void *>(aux0);
+        case B_AUX1: return const_cast<void *>(aux1);
         default: return pl->ws[b - B_WS0];
         }
     };
@@ -863,13 +894,13 @@ void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const 
 }
 
 hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
-                       void *unext, const void *in, void *out, hipStream_t st, const void *sprev,
-                       const void *snext)
+                       void *unext, const void *in, void *out, hipStream_t st, const void *aux0,
+                       const void *aux1)
 {
     for (const ProgOp &po : prog) {
         const void *fp[MAXF];
         void *op[MAXO + 1];
-        resolve_op(pl, po, uprev, ucurr, unext, in, out, fp, op, sprev, snext);
+        resolve_op(pl, po, uprev, ucurr, unext, in, out, fp, op, aux0, aux1);
         hipError_t e;
         if (pl->masked)
             e = launch_seg_op(po.op, pl, fp, op, st);
@@ -1033,9 +1064,11 @@ mol_status mol_plan_get_info(const mol_plan *pl, mol_plan_info *info)
 mol_status mol_start(mol_plan *pl, const void *u0, const void *g, void *u1, void *stream)
 {
     if (!pl || !u0 || !u1) return fail(MOL_E_INVALID, "NULL argument");
-    if (g) return fail(MOL_E_UNSUPPORTED, "non-zero initial velocity is not provided");
     if (u0 == u1) return fail(MOL_E_INVALID, "u0 and u1 must not overlap");
-    hipError_t e = run_program(pl, pl->start, nullptr, nullptr, nullptr, u0, u1, (hipStream_t)stream);
+    if (g && !pl->has_start_g) return fail(MOL_E_UNSUPPORTED, "initial velocity not available for this plan");
+    if (g && g == u1) return fail(MOL_E_INVALID, "g and u1 must not overlap");
+    hipError_t e = g ? run_program(pl, pl->start_g, nullptr, nullptr, nullptr, u0, u1, (hipStream_t)stream, g)
+                     : run_program(pl, pl->start, nullptr, nullptr, nullptr, u0, u1, (hipStream_t)stream);
     return e == hipSuccess ? MOL_OK : dev_err(e, "mol_start");
 }
 

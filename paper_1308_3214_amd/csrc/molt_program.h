@@ -11,10 +11,11 @@
 namespace molt {
 
 // buffer ids inside a program: caller fields, then plan workspace fields
-// Buffers of a program: caller fields, then workspace fields from B_WS0.  The
-// step with a source term reads S^n as B_IN and S^{n-1}, S^{n+1} as B_SPREV,
-// B_SNEXT.
-enum { B_UPREV = 0, B_UCURR = 1, B_UNEXT = 2, B_IN = 3, B_OUT = 4, B_SPREV = 5, B_SNEXT = 6, B_WS0 = 7 };
+// Buffers of a program: caller fields, then workspace fields from B_WS0.  Two
+// more caller fields: the step with a source term reads S^n as B_IN and
+// S^{n-1}, S^{n+1} as B_AUX0, B_AUX1; the start with an initial velocity reads
+// g as B_AUX0.
+enum { B_UPREV = 0, B_UCURR = 1, B_UNEXT = 2, B_IN = 3, B_OUT = 4, B_AUX0 = 5, B_AUX1 = 6, B_WS0 = 7 };
 
 struct ProgOp {
     SweepOp op;
@@ -44,6 +45,9 @@ struct mol_plan_ {
     // other programs: it holds nothing between calls)
     molt::Program step_src;
     bool has_src = false;
+    // start with an initial velocity (workspace shared in the same way)
+    molt::Program start_g;
+    bool has_start_g = false;
     int dev = 0;
     // graph cache for mol_solve
     hipGraphExec_t gexec = nullptr;
@@ -86,6 +90,11 @@ inline Lin operator*(double s, Lin a)
     return a;
 }
 
+// weights of the schemes (eq. Full_2D, eq. update_P) and of the start's odd series
+double stage_c(int p, int m, double beta);
+double A_p(int p, double beta);
+double start_b(int p, int m, double beta);
+
 struct OutSpec {
     int buf;
     Lin elem;
@@ -96,7 +105,17 @@ struct Builder {
     mol_plan_ &pl;
     bool dry;
     std::string err;
+    // weights of the terms C^{m-1} D^{p-m} C of Table 2's schedule: the step's
+    // c_{p,m} (series 0) or the odd series of the start, b_{p,m} (series 1)
+    int series = 0;
     explicit Builder(mol_plan_ &p, bool d) : pl(p), dry(d) {}
+    double coef(int p, int m) const { return series ? start_b(p, m, pl.beta) : stage_c(p, m, pl.beta); }
+    double Ap(int p) const
+    {
+        double s = 0.0;
+        for (int m = 1; m <= p; ++m) s += coef(p, m);
+        return s;
+    }
 
     int new_ws() { return B_WS0 + pl.nws++; }
 
@@ -124,8 +143,6 @@ std::string tune_problem_key(const mol_plan_ *pl);
 std::string tune_op_key(const SweepOp &op);
 
 std::vector<OutSpec> finals(const std::vector<FinalOut> &fo, const Lin &rhs_elem, double rhs_dcoef);
-double stage_c(int p, int m, double beta);
-double A_p(int p, double beta);
 
 // masked (embedded boundary) plans
 bool build_rhs_masked(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo);
@@ -138,12 +155,12 @@ hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *con
 // Device pointers of one launch of a program: fields (op.nf) and outputs
 // (op.no, then the chained output) for the given caller fields.
 void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const void *ucurr, void *unext,
-                const void *in, void *out, const void **fp, void **op, const void *sprev = nullptr,
-                const void *snext = nullptr);
+                const void *in, void *out, const void **fp, void **op, const void *aux0 = nullptr,
+                const void *aux1 = nullptr);
 // Run a program on st (one launch per op).
 hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
                        void *unext, const void *in, void *out, hipStream_t st,
-                       const void *sprev = nullptr, const void *snext = nullptr);
+                       const void *aux0 = nullptr, const void *aux1 = nullptr);
 
 // plans whose workspace is allocated and freed in stream order on st (no
 // device-wide synchronisation; used by the request server)

@@ -249,8 +249,10 @@ class Plan:
             raise ValueError("expected a contiguous %s CUDA tensor of shape %s" % (want, self.shape))
         return ctypes.c_void_p(x.data_ptr())
 
-    def start(self, u0, u1, stream=None):
-        _check(_lib.mol_start(self._h, self._t(u0), None, self._t(u1), _stream(stream)))
+    def start(self, u0, u1, stream=None, g=None):
+        """u1 = u(dt) from u0 and the initial velocity g (None: zero)."""
+        _check(_lib.mol_start(self._h, self._t(u0), None if g is None else self._t(g), self._t(u1),
+                              _stream(stream)))
 
     def step(self, u_prev, u_curr, u_next, stream=None):
         _check(_lib.mol_step(self._h, self._t(u_prev), self._t(u_curr), self._t(u_next),
