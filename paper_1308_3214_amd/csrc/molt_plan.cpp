@@ -409,8 +409,11 @@ bool build_rhs_1d(Builder &b, Program &prog, int u, const std::vector<FinalOut> 
 //   3D: C v = D_x(v - 2y - 2z + 3yz) + (y + z - 2yz),
 //       D v = D_x(v - y - z + yz) + (y + z - yz),  z = D_z v, y = D_y v, yz = D_y z
 bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo,
-                   int chain_a = -1)
+                   int chain_a = -1, int csrc = -1, double ksrc = 0.0)
 {
+    // csrc >= 0 (2D, no chaining, one output): the output also gets
+    // ksrc C[csrc]; csrc is swept with u in the first y launch and
+    // C csrc = D_x(csrc - 2 y_s) + y_s joins the last x sweep
     mol_plan_ &pl = b.pl;
     const int P = pl.desc.P;
     const int nd = pl.geom.ndim;
@@ -418,6 +421,11 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
     std::vector<int> v{u};      // inputs of the current stage
     int accbuf = -1;            // accumulated earlier-stage terms (stage >= 3)
     int pfirst = 1;
+    int ys = -1;                // D_y csrc
+    if (csrc >= 0 && (nd != 2 || chain_a >= 0 || fo.size() != 1 || P < 2)) {
+        b.err = "internal: folded C term needs a 2D unchained program with P >= 2";
+        return false;
+    }
     if (chain_a >= 0 && P == 2 && nd == 2 && fo.size() == 1 &&
         !(pl.desc.flags & MOL_SPLIT_Y) && b.yy_available(1, 3, 2)) {
         // 2D, P = 2: both y sweeps of the step in one launch.  v1 = C u =
@@ -466,6 +474,14 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
                     OutSpec o{};
                     o.buf = y[j];
                     o.dc[j - k] = 1.0;
+                    outs.push_back(o);
+                }
+                if (p == 1 && csrc >= 0 && nin == 1) {
+                    ys = b.new_ws();
+                    cmb.push_back(lin(csrc));
+                    OutSpec o{};
+                    o.buf = ys;
+                    o.dc[1] = 1.0;
                     outs.push_back(o);
                 }
                 if (!b.emit(prog, 1, cmb, outs, 0)) return false;
@@ -527,6 +543,11 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
                 const double c = b.coef(p, p - k);
                 gs = gs + c * g[k];
                 hs = hs + c * h[k];
+            }
+            if (csrc >= 0) {
+                const double w = ksrc / fo[0].r;
+                gs = gs + w * (lin(csrc) + lin(ys, -2.0));
+                hs = hs + w * lin(ys);
             }
             return b.emit(prog, 0, {gs}, finals(fo, hs, 1.0), 1, chain_a);
         }
@@ -655,8 +676,10 @@ bool emit_CD(Builder &b, Program &prog, bool isC, int in, int out)
 //   P = 2: ... + (c dt)^2 / 12 (S^{n+1} + 10 S^n + S^{n-1}) - beta^2 (c dt)^2 / 12 C[S^n]
 // The C[S^n] coefficient is the dt^4 c^4 laplacian(S) / 12 term of the Taylor
 // expansion with the laplacian replaced by -alpha^2 C, as in the homogeneous
-// part.  C[S^n] goes to a workspace field; the other source terms join the
-// elementwise part of the step's last sweep.
+// part.  In 2D, S^n is swept with u^n in the step's first y launch and C[S^n]
+// joins the step's last x sweep; in 1D and 3D C[S^n] goes to a workspace
+// field first.  The other source terms join the elementwise part of the last
+// sweep.
 bool build_step_source(Builder &b, Program &prog)
 {
     mol_plan_ &pl = b.pl;
@@ -666,10 +689,14 @@ bool build_step_source(Builder &b, Program &prog)
         elem = elem + lin(B_IN, a2);
     } else {
         const double sg = a2 / 12.0;
+        elem = elem + lin(B_AUX0, sg) + lin(B_IN, 10.0 * sg) + lin(B_AUX1, sg);
+        if (pl.geom.ndim == 2)
+            // C[S^n] folded into the step's own sweeps
+            return build_rhs_box(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}}, -1, B_IN,
+                                 -pl.beta * pl.beta * sg);
         const int cs = b.new_ws();
         if (!emit_CD(b, prog, true, B_IN, cs)) return false;
-        elem = elem + lin(B_AUX0, sg) + lin(B_IN, 10.0 * sg) + lin(B_AUX1, sg) +
-               lin(cs, -pl.beta * pl.beta * sg);
+        elem = elem + lin(cs, -pl.beta * pl.beta * sg);
     }
     return build_rhs(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}});
 }
