@@ -317,14 +317,14 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
     }
     if (dir == 0) {
         const int64_t n = g.n[0];
-        // smallest line capacity that holds the line, preferring 16 nodes/lane
-        // FP64 keeps 8 nodes per lane (16 spill registers)
-        static const int order32[] = {0, 1, 2, 3, 4, 5, 7};
-        static const int order64[] = {0, 1, 2, 8, 9, 6, 7};
-        const int *ord = fp64 ? order64 : order32;
+        // smallest line capacity that holds the line, with 8 nodes per lane
+        // and more waves where two capacities tie (the choice the tuner makes
+        // on MI355X for FP32 and FP64 at 1024 and 4096 nodes; 16 nodes per
+        // lane spill in FP64)
+        static const int order[] = {0, 1, 2, 8, 9, 6, 7};
         const int cnt = 7;
         for (int i = 0; i < cnt; ++i) {
-            cfg[0] = ord[i];
+            cfg[0] = order[i];
             const XCfg c = kXCfg[cfg[0]];
             if (64 * c.WPL * c.S >= n && config_valid(g, dc, op, fp64, cfg)) return 0;
         }
