@@ -357,6 +357,20 @@ def cpu_baseline(n, P, cfl, nsteps=1, seed=1):
             "sample": "%d step(s) of the %dx%d P=%d FP64 workload, %.1f s" % (nsteps, n, n, P, dt)}
 
 
+def cpu_single_thread(n=1024, P=2, cfl=2.0, nsteps=2):
+    """The same oracle on one thread (OMP_NUM_THREADS=1 in a child process, so
+    this process keeps its thread pool), on a bounded sample."""
+    import subprocess
+    code = ("import json, bench; print(json.dumps(bench.cpu_baseline(%d, %d, %r, %d)))"
+            % (n, P, cfl, nsteps))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("single-thread oracle run failed: " + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -480,6 +494,7 @@ def main():
                                                                   budget=32 << 30)}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, P, args.cfl, 1)
+        out["cpu_baseline"]["single_thread"] = cpu_single_thread(1024, P, args.cfl, 2)
     print(json.dumps(out))
 
 
