@@ -175,6 +175,23 @@ mol_status mol_step_source(mol_plan *plan, const void *u_prev, const void *u_cur
 mol_status mol_solve(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
                      void *stream);
 
+/* nsteps steps in place like mol_solve with a separable source
+ * S(x, t) = f(t) G(x), a point source switched on in time for instance (Sec. 4,
+ * inclusion of source terms; the step of mol_step_source with S^m = f_m G):
+ * the source part of a step is a_n G + b_n C[G] with
+ *   P = 1: a_n = (c dt)^2 f_n,                                  b_n = 0
+ *   P = 2: a_n = (c dt)^2 / 12 (f_{n+1} + 10 f_n + f_{n-1}),    b_n = -beta^2 (c dt)^2 / 12 f_n.
+ * On entry (u_prev_io, u_curr_io) = (u^{n-1}, u^n), on return
+ * (u^{n+nsteps-1}, u^{n+nsteps}).  G: device field (read only).  CG: device
+ * field C[G], e.g. from mol_apply(plan, MOL_OP_C, G, CG) (read only; not read
+ * for P = 1, may be NULL).  f: host array of nsteps + 2 values f(t_{n-1}),
+ * f(t_n), ..., f(t_{n+nsteps}), read before the call returns.  In 2D with
+ * P = 2 the steps are mol_solve's fused ones with G and C[G] read by their last
+ * launch; launched directly (no graph).  Box plans with P = 1 or 2 in the
+ * three-level form, else MOL_E_UNSUPPORTED.  Asynchronous on stream. */
+mol_status mol_solve_source(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
+                            const void *G, const void *CG, const double *f, void *stream);
+
 /* One step for each of count independent plans: equivalent to
  * mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream) for every i, in
  * order, on one stream.  Plans must be distinct.  (Concurrent serving of many

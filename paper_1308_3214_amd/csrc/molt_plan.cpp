@@ -437,12 +437,17 @@ bool build_rhs_box(Builder &b, Program &prog, int u, const std::vector<FinalOut>
         const Lin gs = c22 * (lin(V1) + lin(Y, -2.0)) + c21 * (lin(V1) + lin(Y, -1.0));
         const Lin hs = lin(V1, c11) + c22 * lin(Y) + c21 * lin(Y);
         const int G = b.new_ws(), H = b.new_ws();
+        // elementwise terms on caller fields other than u^n, u^{n-1} (a
+        // separable source) go to the x sweep: the walk takes three fields
+        Lin he, xe;
+        for (const auto &t : fo[0].elem)
+            (t.first == B_AUX0 || t.first == B_AUX1 ? xe : he).push_back(t);
         if (!b.emit_yy(prog, 1, lin(u) + lin(chain_a, -2.0), lin(chain_a),
-                       {{G, gs}, {H, fo[0].elem + fo[0].r * hs}}))
+                       {{G, gs}, {H, he + fo[0].r * hs}}))
             return false;
         OutSpec o{};
         o.buf = fo[0].buf;
-        o.elem = lin(H);
+        o.elem = lin(H) + xe;
         o.dc[0] = fo[0].r;
         return b.emit(prog, 0, {lin(G)}, {o}, 1, chain_a);
     }
@@ -716,6 +721,33 @@ bool build_start_g(Builder &b, Program &prog)
     return ok && build_rhs(b, prog, B_IN, {{B_OUT, lin(B_IN) + lin(t), 0.5}});
 }
 
+// Step for a separable source S = f(t) G(x) (Sec. 4, inclusion of source
+// terms): the source part a_n G + b_n C[G] joins the last launch of the step
+// as two elementwise fields, G (B_AUX0) and C[G] (B_AUX1, P = 2 only), with
+// unit weights that mol_solve_source replaces every step.  Fused (chained) in
+// 2D like mol_solve's own program.
+bool build_solve_source(Builder &b, Program &prog, int chain_a)
+{
+    mol_plan_ &pl = b.pl;
+    Lin elem = lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0) + lin(B_AUX0, 1.0);
+    if (pl.desc.P == 2) elem = elem + lin(B_AUX1, 1.0);
+    const bool ok = chain_a >= 0
+                        ? build_rhs_box(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}}, chain_a)
+                        : build_rhs(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}});
+    if (!ok || prog.empty()) return false;
+    const SweepOp &last = prog.back().op;
+    pl.src_fg = pl.src_fcg = -1;
+    for (int i = 0; i < last.nf; ++i) {
+        if (last.f[i] == B_AUX0) pl.src_fg = i;
+        if (last.f[i] == B_AUX1) pl.src_fcg = i;
+    }
+    // every other launch must not read them
+    for (size_t k = 0; k + 1 < prog.size(); ++k)
+        for (int i = 0; i < prog[k].op.nf; ++i)
+            if (prog[k].op.f[i] == B_AUX0 || prog[k].op.f[i] == B_AUX1) return false;
+    return pl.src_fg >= 0 && (pl.desc.P == 1 || pl.src_fcg >= 0);
+}
+
 std::string tune_problem_key(const mol_plan_ *pl)
 {
     std::ostringstream o;
@@ -878,6 +910,15 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
         pl->nws = 0;
         pl->has_src = build_step_source(b, pl->step_src);
         if (!pl->has_src) pl->step_src.clear();
+        pl->nws = std::max(n0, pl->nws);
+    }
+    if (ok && !pl->masked && d->P <= 2) {
+        // shares the fused programs' chain field; nothing else kept
+        const int n0 = pl->nws;
+        pl->nws = 0;
+        if (pl->chain_a >= 0) pl->nws = std::max(pl->nws, pl->chain_a - B_WS0 + 1);
+        pl->has_solve_src = build_solve_source(b, pl->solve_src, pl->chain_a);
+        if (!pl->has_solve_src) pl->solve_src.clear();
         pl->nws = std::max(n0, pl->nws);
     }
     if (ok) {
@@ -1212,6 +1253,56 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
     if (inc) {
         e = launch_axpby(pl->fp64, pl->npts, 1.0, B, -1.0, A, A, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
+    }
+    return MOL_OK;
+}
+
+mol_status mol_solve_source(mol_plan *pl, void *A, void *B, int64_t nsteps, const void *G,
+                            const void *CG, const double *f, void *stream)
+{
+    if (!pl || !A || !B || !G) return fail(MOL_E_INVALID, "NULL argument");
+    if (!pl->has_solve_src)
+        return fail(MOL_E_UNSUPPORTED, "separable sources are given for box grids with P = 1 and 2");
+    if (pl->desc.flags & MOL_INCREMENT_FORM)
+        return fail(MOL_E_UNSUPPORTED, "separable sources step the three-level form only");
+    if (pl->desc.P == 2 && !CG) return fail(MOL_E_INVALID, "P = 2 needs C[G]");
+    if (A == B) return fail(MOL_E_INVALID, "u_prev and u_curr must differ");
+    if (G == A || G == B || (CG && (CG == A || CG == B)))
+        return fail(MOL_E_INVALID, "G and C[G] must not overlap the solution fields");
+    if (nsteps < 0) return fail(MOL_E_INVALID, "nsteps < 0");
+    if (nsteps == 0) return MOL_OK;
+    if (!f) return fail(MOL_E_INVALID, "NULL f");
+    hipStream_t st = (hipStream_t)stream;
+    const double a2 = (pl->beta / pl->alpha) * (pl->beta / pl->alpha);
+    const double sg = a2 / 12.0;
+    const bool fused = pl->chain_a >= 0;
+    hipError_t e = hipSuccess;
+    if (fused) {
+        e = run_program(pl, pl->solve_pro, A, B, nullptr, nullptr, nullptr, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve_source");
+    }
+    Program prog = pl->solve_src;
+    SweepOp &last = prog.back().op;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        // step k makes u^{n+k+1} from S at t_{n+k-1}, t_{n+k}, t_{n+k+1}
+        if (pl->desc.P == 1) {
+            last.mOF[0][pl->src_fg] = a2 * f[k + 1];
+        } else {
+            last.mOF[0][pl->src_fg] = sg * (f[k + 2] + 10.0 * f[k + 1] + f[k]);
+            last.mOF[0][pl->src_fcg] = -pl->beta * pl->beta * sg * f[k + 1];
+        }
+        e = (k % 2 == 0) ? run_program(pl, prog, A, B, A, nullptr, nullptr, st, G, CG)
+                         : run_program(pl, prog, B, A, B, nullptr, nullptr, st, G, CG);
+        if (e != hipSuccess) return dev_err(e, "mol_solve_source");
+    }
+    if (nsteps % 2) {
+        // the newest field is in A: swap the contents of A and B
+        void *W = pl->ws[pl->nws - 1];
+        const size_t bytes = (size_t)pl->npts * pl->es;
+        e = hipMemcpyAsync(W, A, bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(A, B, bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(B, W, bytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve_source swap");
     }
     return MOL_OK;
 }

@@ -48,6 +48,12 @@ struct mol_plan_ {
     // start with an initial velocity (workspace shared in the same way)
     molt::Program start_g;
     bool has_start_g = false;
+    // steps with a separable source f(t) G(x): the step program (fused when
+    // the plan has one) whose last launch also takes G (B_AUX0) and C[G]
+    // (B_AUX1, P = 2) elementwise, their weights set per step
+    molt::Program solve_src;
+    bool has_solve_src = false;
+    int src_fg = -1, src_fcg = -1;     // field slots of G and C[G] in its last launch
     int dev = 0;
     // graph cache for mol_solve
     hipGraphExec_t gexec = nullptr;

@@ -82,6 +82,7 @@ _lib.mol_plan_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
 _lib.mol_start.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.mol_step.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.mol_step_source.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mol_solve_source.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.mol_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
 _lib.mol_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
 _lib.mol_step_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -122,13 +123,14 @@ _lib.mol_server_stats.argtypes = [_vp, ctypes.POINTER(_SrvInfo)]
 _lib.mol_server_last_error.restype = ctypes.c_char_p
 for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
            "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
-           "mol_step_source",
+           "mol_step_source", "mol_solve_source",
            "mol_solve", "mol_apply", "mol_step_batch", "mol_server_create", "mol_server_create_ex",
            "mol_server_destroy", "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
-           "mol_workspace_bytes", "mol_start", "mol_step", "mol_step_source", "mol_solve", "mol_step_batch",
+           "mol_workspace_bytes", "mol_start", "mol_step", "mol_step_source", "mol_solve", "mol_solve_source",
+           "mol_step_batch",
            "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
            "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error",
            "mol_server_create", "mol_server_create_ex", "mol_server_destroy", "mol_server_submit",
@@ -264,6 +266,19 @@ class Plan:
         opt = lambda x: None if x is None else self._t(x)
         _check(_lib.mol_step_source(self._h, self._t(u_prev), self._t(u_curr), self._t(u_next),
                                     opt(s_prev), self._t(s_curr), opt(s_next), _stream(stream)))
+
+    def solve_source(self, u_prev, u_curr, nsteps, G, CG, f, stream=None):
+        """nsteps steps in place with the separable source f(t) G(x); f holds
+        f(t_{n-1}) .. f(t_{n+nsteps}) (nsteps + 2 values); CG = C[G] (None for
+        P = 1)."""
+        import numpy as np
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        if fa.shape != (int(nsteps) + 2,):
+            raise ValueError("f must hold nsteps + 2 values")
+        _check(_lib.mol_solve_source(self._h, self._t(u_prev), self._t(u_curr), int(nsteps),
+                                     self._t(G), None if CG is None else self._t(CG),
+                                     fa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     _stream(stream)))
 
     def solve(self, u_prev, u_curr, nsteps, stream=None):
         _check(_lib.mol_solve(self._h, self._t(u_prev), self._t(u_curr), int(nsteps),
