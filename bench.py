@@ -212,6 +212,48 @@ def source_workload(n=4096, steps=200, warmup=10):
             "separable_source_solve_ms_per_step": round(out["solve_source"], 5)}
 
 
+def fig3_workload(steps=20, reps=20):
+    """The point-source run of the ADI section's figure: 81^2 nodes (80 x 80
+    cells) on [-1, 1]^2, CFL 2, a discrete delta at the centre times a
+    sinusoid switched on smoothly, FP64, P = 1 and 2, 20 steps (t = 1) through
+    mol_solve_source from rest; wall time per step (a latency-bound size) and
+    the field's largest value at t = 1."""
+    import numpy as np
+    import torch
+    from paper_1308_3214_amd import molt
+    from paper_1308_3214_amd import workloads as W
+    G, f, h = W.point_source_fig3()
+    out = []
+    for P in (1, 2):
+        plan = molt.Plan(G.shape, h, 0, P=P, cfl=2.0, dtype="f64")
+        dt = plan.info["beta"] / plan.info["alpha"]
+        fv = f(dt * np.arange(steps + 2))
+        dG = torch.tensor(G, dtype=torch.float64, device="cuda")
+        dCG = None
+        if P == 2:
+            dCG = torch.empty_like(dG)
+            plan.apply("C", dG, dCG)
+        A, B = torch.zeros_like(dG), torch.zeros_like(dG)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            plan.solve_source(A, B, steps, dG, dCG, fv, stream=stream)
+            stream.synchronize()
+            umax = float(B.abs().max())
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                A.zero_()
+                B.zero_()
+                plan.solve_source(A, B, steps, dG, dCG, fv, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+        plan.close()
+        out.append({"P": P, "steps": steps, "ms_per_step": round(e0.elapsed_time(e1) / (reps * steps), 5),
+                    "max_abs_u_t1": round(umax, 6)})
+    return out
+
+
 # Table 3 of the paper (ADI refinement study, 641^2 on [-1, 1]^2, T = 1.2,
 # dt = 0.025, beta = beta_max(P)): printed max-over-steps L2 error and run time
 # in seconds; the paper states no hardware or precision.
@@ -400,11 +442,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 64 MiB buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["star", "periodic3d", "table3", "source"], default=None,
+    ap.add_argument("--only", choices=["star", "periodic3d", "table3", "source", "fig3"], default=None,
                     help="only run one secondary workload for --steps steps (for profiling)")
     args = ap.parse_args()
     if args.only == "table3":
         print(json.dumps({"table3": [table3_workload(P) for P in (1, 2, 3)]}))
+        return
+    if args.only == "fig3":
+        print(json.dumps({"fig3": fig3_workload()}))
         return
     if args.only:
         fn = {"star": star_workload, "periodic3d": periodic3d_workload,
@@ -496,6 +541,7 @@ def main():
         also["star2048_P3_f32_300steps_averaged_D"] = star_workload(flags=_m.SYMMETRIC_D)
         also["periodic3d_256_P2_f32_200steps"] = periodic3d_workload()
         also["source_4096_P2_f32_200steps"] = source_workload()
+        also["paper_fig3_point_source_81x81_cfl2"] = fig3_workload()
         out["also"] = also
     if not args.no_serve:
         # stream pool (per-request graphs on three streams) and batched rounds

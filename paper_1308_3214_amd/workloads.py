@@ -98,6 +98,22 @@ def sine_mode(n: int, ndim: int):
     return np.ascontiguousarray(f), 2.0 / (n - 1)
 
 
+def point_source_fig3(n: int = 81, periods_per_unit: float = 1.0, ramp: float = 0.3):
+    """The point-source run of the ADI section's figure (80 x 80 cells on
+    [-1, 1]^2, CFL 2): a discrete delta at the centre node (G = 1/h^2 there)
+    and the signal f(t) = sin(2 pi k t) (1 - exp(-(t / ramp)^2)), switched on
+    smoothly from f = 0 at t = 0 (frequency and ramp are not stated; k = 1 and
+    ramp 0.3 resolve a period in 20 steps).  Returns (G, f, h)."""
+    h = 2.0 / (n - 1)
+    G = np.zeros((n, n))
+    G[n // 2, n // 2] = 1.0 / h ** 2
+
+    def f(t):
+        t = np.asarray(t, dtype=np.float64)
+        return np.where(t > 0, np.sin(2 * np.pi * periods_per_unit * t) * (1 - np.exp(-(t / ramp) ** 2)), 0.0)
+    return G, f, h
+
+
 # --------------------------------------------------------------------------
 # 3D plane waves on the periodic unit cube
 # --------------------------------------------------------------------------

@@ -140,3 +140,34 @@ def test_solve_source_errors(torch_cuda, molt):
         p.step_source(z2, z2.clone(), z2.clone(), z2, z2, z2)
     assert ei.value.status == molt.MOL_E_UNSUPPORTED
     p.close()
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_point_source_run_of_the_figure(torch_cuda, molt, oracle_mod, P):
+    # 81^2 nodes on [-1, 1]^2, CFL 2, discrete delta at the centre switched on
+    # smoothly; u^0 = u^1 = 0 (f and its derivatives vanish at t = 0); 20
+    # steps (t = 1) through mol_solve_source against the oracle, FP64
+    torch = torch_cuda
+    G, f, h = W.point_source_fig3()
+    plan = molt.Plan(G.shape, h, 0, P=P, cfl=2.0, dtype="f64")
+    beta, alpha = plan.info["beta"], plan.info["alpha"]
+    dt = beta / alpha
+    nsteps = 20
+    fv = f(dt * np.arange(nsteps + 2))               # f(t_0) .. f(t_{nsteps+1})
+    pb = oracle_mod.Problem(G.shape, h, 0, alpha)
+    a, b = np.zeros_like(G), np.zeros_like(G)
+    for k in range(nsteps):
+        a, b = b, pb.step_source(a, b, fv[k] * G, fv[k + 1] * G, fv[k + 2] * G, P, beta)
+    dG = dev(torch, G, "f64")
+    dCG = None
+    if P == 2:
+        dCG = torch.empty_like(dG)
+        plan.apply("C", dG, dCG)
+    A, B = torch.zeros_like(dG), torch.zeros_like(dG)
+    plan.solve_source(A, B, nsteps, dG, dCG, fv)
+    torch.cuda.synchronize()
+    got = B.double().cpu().numpy()
+    e = rel(got, b)
+    print("figure point source P=%d, 20 steps: max|u| %.3e, rel L2 vs oracle %.3e" % (P, np.abs(b).max(), e))
+    assert np.abs(b).max() > 1e-3 and e < 1e-12
+    plan.close()
