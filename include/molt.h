@@ -160,8 +160,12 @@ mol_status mol_step(mol_plan *plan, const void *u_prev, const void *u_curr, void
  * C[S^n] coefficient is the dt^4 c^4 laplacian(S) / 12 term of the Taylor
  * expansion with the laplacian replaced by -alpha^2 C; the coefficient as
  * printed is not dimensionally consistent and gives a second-order scheme.
- * Dirichlet boundary nodes of u_next are 0 whatever S is there.  A source that
- * depends on u (S^{n+1} through u^{n+1}) needs the caller's iteration.
+ * Dirichlet boundary nodes of u_next are 0 whatever S is there.  Full order
+ * needs S = 0 on Dirichlet boundaries: the end cells of every sweep take the
+ * curvature of homogeneous data (u_xx = 0), while a source makes it -S there
+ * (a source nonzero on the boundary measured order 2.4-2.9 at P = 2 in 1D).
+ * A source that depends on u (S^{n+1} through u^{n+1}) needs the caller's
+ * iteration.
  * s_prev and s_next are not read for P = 1 (may be NULL).  Box plans with
  * P = 1 or 2 only, else MOL_E_UNSUPPORTED.  Aliasing as mol_step; u_next must
  * not overlap a source field.  Asynchronous on stream. */
