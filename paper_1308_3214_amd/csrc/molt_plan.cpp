@@ -709,16 +709,21 @@ bool build_step_source(Builder &b, Program &prog)
 // Start with an initial velocity g (Sec. 3.2): the even terms of the Taylor
 // series of u(dt) give u0 + rhs(u0)/2 as without g; the odd ones give
 // dt sum_m beta^{2m} / (2m+1)! (laplacian / alpha^2)^m g, taken with Table 2's
-// schedule and weights b_{p,m} (p <= P):  t = dt (g + rhs_b(g)), then
-// u1 = u0 + t + rhs(u0) / 2.
+// schedule and weights b_{p,m} (p <= P).  The odd part dt (g + rhs_b(g)) is
+// written to u1 itself, whose last sweep for the even part then reads it
+// elementwise: u1 = u0 + u1 + rhs(u0) / 2.  The two parts share workspace.
 bool build_start_g(Builder &b, Program &prog)
 {
     const double dt = b.pl.desc.dt;
-    const int t = b.new_ws();
+    const int mark = b.pl.nws;
     b.series = 1;
-    const bool ok = build_rhs(b, prog, B_AUX0, {{t, lin(B_AUX0, dt), dt}});
+    const bool ok = build_rhs(b, prog, B_AUX0, {{B_OUT, lin(B_AUX0, dt), dt}});
     b.series = 0;
-    return ok && build_rhs(b, prog, B_IN, {{B_OUT, lin(B_IN) + lin(t), 0.5}});
+    const int used = b.pl.nws;
+    b.pl.nws = mark;
+    const bool ok2 = ok && build_rhs(b, prog, B_IN, {{B_OUT, lin(B_IN) + lin(B_OUT), 0.5}});
+    b.pl.nws = std::max(used, b.pl.nws);
+    return ok2;
 }
 
 // Step for a separable source S = f(t) G(x) (Sec. 4, inclusion of source
