@@ -1398,7 +1398,7 @@ mol_status mol_plan_set_kernel_config(mol_plan *pl, int kernel, int config)
         return fail(MOL_E_INVALID, "configuration not valid for this kernel");
     const std::string key = tune_op_key(ref);
     for (Program *pr : {&pl->step, &pl->start, &pl->inc_step, &pl->solve_pro, &pl->solve_step,
-                        &pl->solve_inc_step}) {
+                        &pl->solve_inc_step, &pl->step_src, &pl->start_g, &pl->solve_src}) {
         for (ProgOp &po : *pr)
             if (tune_op_key(po.op) == key) po.cfg[0] = config;
     }
