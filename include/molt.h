@@ -116,9 +116,10 @@ typedef struct mol_plan_info {
  * (Theorem of Sec. 3.1, eq. Stab_cond); returns -1 for P outside 1..8. */
 double mol_beta_max(int P);
 
-/* Size limits: at most 8192 nodes along x (one workgroup per x line; the same
- * for the line objects of a mask), any length along y and z, and fewer than
- * 2^31 nodes per field; beyond them MOL_E_UNSUPPORTED.
+/* Size limits: at most 16384 nodes along x (one workgroup per x line; 8192 in
+ * FP64 for launches that sweep two combinations, and for the line objects of a
+ * mask), any length along y and z, and fewer than 2^31 nodes per field; beyond
+ * them MOL_E_UNSUPPORTED.
  * Validates the descriptor, derives alpha, the quadrature weights and the
  * stage coefficients in FP64, builds the kernel schedule (and for a mask the
  * line-object tables), and allocates the device workspace on the current

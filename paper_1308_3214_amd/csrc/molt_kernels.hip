@@ -21,12 +21,12 @@ int g_max_lds = -1;
 int max_lds()
 {
     if (g_max_lds < 0) {
-        int dev = 0, v = 65536;
+        int dev = 0, v = 163840;          // gfx950: 160 KB per workgroup
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
             g_max_lds = v;
         else
-            g_max_lds = 65536;
+            g_max_lds = 163840;
     }
     return g_max_lds;
 }
@@ -321,8 +321,8 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
         // and more waves where two capacities tie (the choice the tuner makes
         // on MI355X for FP32 and FP64 at 1024 and 4096 nodes; 16 nodes per
         // lane spill in FP64)
-        static const int order[] = {0, 1, 2, 8, 9, 6, 7};
-        const int cnt = 7;
+        static const int order[] = {0, 1, 2, 8, 9, 6, 7, 10};
+        const int cnt = 8;
         for (int i = 0; i < cnt; ++i) {
             cfg[0] = order[i];
             const XCfg c = kXCfg[cfg[0]];

@@ -1777,7 +1777,8 @@ __global__ void k_axpby(int64_t n, T a, const T *x, T b, const T *y, T *z)
 // ---------------------------------------------------------------------------
 struct XCfg { int S, WPL; };
 struct SCfg { int S, W; };
-constexpr XCfg kXCfg[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}, {16, 8}, {8, 2}, {8, 4}};
+constexpr XCfg kXCfg[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}, {16, 8}, {8, 2}, {8, 4},
+                          {16, 16}};
 constexpr SCfg kSCfg[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {4, 16}, {16, 4}};
 constexpr int NXCFG = sizeof(kXCfg) / sizeof(kXCfg[0]);
 constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);

@@ -77,15 +77,16 @@ def test_descriptor_validation_and_workspace(lib):
 
 
 def test_size_limits(lib):
-    # an x line is one workgroup (at most 8192 nodes); y and z lines are walked
-    # in strips (any length); fields of 2^31 nodes or more are refused (the
-    # kernels index a field with 32-bit offsets)
+    # an x line is one workgroup (at most 16384 nodes: 16 waves of 64 lanes x
+    # 16 nodes); y and z lines are walked in strips (any length); fields of
+    # 2^31 nodes or more are refused (the kernels index a field with 32-bit
+    # offsets)
     from paper_1308_3214_amd import molt
-    assert molt.workspace_bytes(shape=(4, 8192), h=1e-4, P=2, cfl=2.0, dtype="f32") > 0
-    assert molt.workspace_bytes(shape=(4, 8193), h=1e-4, P=2, cfl=2.0, dtype="f32") == 0
+    assert molt.workspace_bytes(shape=(4, 16384), h=1e-4, P=2, cfl=2.0, dtype="f32") > 0
+    assert molt.workspace_bytes(shape=(4, 16385), h=1e-4, P=2, cfl=2.0, dtype="f32") == 0
     assert "line length" in molt.last_error()
-    tall = (1 << 31) // 8192                      # 262144 rows of 8192 nodes = 2^31
-    w = molt.workspace_bytes(shape=(tall - 1, 8192), h=1e-6, P=2, cfl=2.0, dtype="f32")
-    assert w > 0 and w % ((tall - 1) * 8192 * 4) == 0
-    assert molt.workspace_bytes(shape=(tall, 8192), h=1e-6, P=2, cfl=2.0, dtype="f32") == 0
+    tall = (1 << 31) // 16384                     # 131072 rows of 16384 nodes = 2^31
+    w = molt.workspace_bytes(shape=(tall - 1, 16384), h=1e-6, P=2, cfl=2.0, dtype="f32")
+    assert w > 0 and w % ((tall - 1) * 16384 * 4) == 0
+    assert molt.workspace_bytes(shape=(tall, 16384), h=1e-6, P=2, cfl=2.0, dtype="f32") == 0
     assert "2^31" in molt.last_error()

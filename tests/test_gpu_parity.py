@@ -351,3 +351,33 @@ def test_minimum_sizes(torch_cuda, molt, oracle_mod, dtype):
         check("rhs %s bc %s" % (shape, bc), host(out), pb.rhs(v, 2, plan.info["beta"]), dtype,
               TOL[dtype] if np.linalg.norm(pb.rhs(v, 2, plan.info["beta"])) > 0 else 1e-30)
         plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_longest_x_lines(torch_cuda, molt, oracle_mod, dtype):
+    # x lines of 16384 nodes (one workgroup of 16 waves): a step against the
+    # FP64 oracle and 3 graph steps against the 80-bit oracle; Dirichlet P = 2
+    # and periodic P = 3 (FP64 with two swept combinations does not fit the
+    # LDS at this length: P = 3 runs in FP32 only)
+    torch = torch_cuda
+    cases = [((6, 16384), 1.0 / 16383, 0, 2)]
+    if dtype == "f32":
+        cases.append(((5, 16384), 1.0 / 16384, 1, 3))
+    for shape, h, bc, P in cases:
+        plan = molt.Plan(shape, h, bc, P=P, cfl=2.0, dtype=dtype)
+        beta = plan.info["beta"]
+        pb = oracle_mod.Problem(shape, h, bc, plan.info["alpha"])
+        da = _dirichlet_axes(shape, bc)
+        up = W.random_field(shape, seed=61, dirichlet_axes=da)
+        uc = W.random_field(shape, seed=62, dirichlet_axes=da)
+        a, b = dev(torch, up, dtype), dev(torch, uc, dtype)
+        out = torch.empty_like(a)
+        plan.step(a, b, out)
+        torch.cuda.synchronize()
+        check("step %s P=%d bc=%d" % (shape, P, bc), host(out), pb.step(up, uc, P, beta), dtype)
+        pl = oracle_mod.Problem(shape, h, bc, plan.info["alpha"], precision="ld")
+        ra, rb = pl.run(up, uc, 3, P, beta)
+        plan.solve(a, b, 3)
+        torch.cuda.synchronize()
+        check("solve 3 %s P=%d bc=%d" % (shape, P, bc), host(b), rb, dtype, TOL[dtype] * 2)
+        plan.close()
