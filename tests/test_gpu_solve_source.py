@@ -43,24 +43,27 @@ def _dirichlet_axes(bc, nd):
     return tuple(a for a in range(nd) if bb[a] == 0)
 
 
-# (shape, h, bc, cfl, P, dtype, nsteps)
+# (shape, h, bc, cfl, P, dtype, nsteps, split_y)
 CASES = [
-    ((300, 260), 1.0 / 299, 0, 2.0, 2, "f32", 5),       # fused, chained walk
-    ((300, 260), 1.0 / 299, 0, 2.0, 2, "f64", 4),       # fused, split y sweeps
-    ((96, 257), 1.0 / 256, (0, 1), 1.5, 2, "f32", 4),
-    ((129, 200), (1.0 / 199, 1.0 / 128), 0, 2.0, 1, "f64", 5),
-    ((1000,), 1.0 / 999, 0, 2.0, 2, "f64", 5),
-    ((20, 24, 28), 1.0 / 27, (0, 1, 0), 2.0, 2, "f32", 3),
+    ((300, 260), 1.0 / 299, 0, 2.0, 2, "f32", 5, False),       # fused, chained walk
+    ((300, 260), 1.0 / 299, 0, 2.0, 2, "f64", 4, False),       # fused, split y sweeps
+    ((300, 260), 1.0 / 299, 0, 2.0, 2, "f32", 5, True),        # FP32 fused without the walk
+    ((96, 257), 1.0 / 256, (0, 1), 1.5, 2, "f32", 4, False),
+    ((129, 200), (1.0 / 199, 1.0 / 128), 0, 2.0, 1, "f64", 5, False),
+    ((1000,), 1.0 / 999, 0, 2.0, 2, "f64", 5, False),
+    ((20, 24, 28), 1.0 / 27, (0, 1, 0), 2.0, 2, "f32", 3, False),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_solve_source_parity(torch_cuda, molt, oracle_mod, case):
     torch = torch_cuda
-    shape, h, bc, cfl, P, dtype, nsteps = CASES[case]
-    plan = molt.Plan(shape, h, bc, P=P, cfl=cfl, dtype=dtype)
+    shape, h, bc, cfl, P, dtype, nsteps, split = CASES[case]
+    plan = molt.Plan(shape, h, bc, P=P, cfl=cfl, dtype=dtype, flags=molt.SPLIT_Y if split else 0)
     if case == 0:
         assert plan.info["kernels_per_step"] == 2      # the chained fused step
+    if split:
+        assert plan.info["kernels_per_step"] == 3
     beta, alpha = plan.info["beta"], plan.info["alpha"]
     a2 = (beta / alpha) ** 2
     pb = oracle_mod.Problem(shape, h, bc, alpha)
