@@ -1197,23 +1197,28 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
         e = launch_axpby(pl->fp64, pl->npts, 1.0, B, -1.0, A, A, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
     }
-    // one replay unit: increment form = 1 step in place; three-level = 2 steps
+    // one replay unit: UNIT_STEPS steps (three-level: in pairs, so that the
+    // fields return to their buffers), one graph launch per unit
+    constexpr int64_t UNIT_STEPS = 8;
     const bool fused = !pl->solve_step.empty();
     const Program &stepP = fused ? pl->solve_step : pl->step;
     const Program &incP = fused ? pl->solve_inc_step : pl->inc_step;
-    auto unit = [&](hipStream_t s) -> hipError_t {
-        if (inc) return run_program(pl, incP, A, B, nullptr, nullptr, nullptr, s);
-        hipError_t r = run_program(pl, stepP, A, B, A, nullptr, nullptr, s);
-        if (r != hipSuccess) return r;
-        return run_program(pl, stepP, B, A, B, nullptr, nullptr, s);
+    auto steps = [&](int64_t count, hipStream_t s) -> hipError_t {
+        hipError_t r = hipSuccess;
+        for (int64_t i = 0; i < count && r == hipSuccess; ++i) {
+            if (inc) r = run_program(pl, incP, A, B, nullptr, nullptr, nullptr, s);
+            else if (i % 2 == 0) r = run_program(pl, stepP, A, B, A, nullptr, nullptr, s);
+            else r = run_program(pl, stepP, B, A, B, nullptr, nullptr, s);
+        }
+        return r;
     };
+    auto unit = [&](hipStream_t s) -> hipError_t { return steps(UNIT_STEPS, s); };
     if (fused) {
         // D_x of the current field for the first stage of the first step
         e = run_program(pl, pl->solve_pro, A, B, nullptr, nullptr, nullptr, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
     }
-    const int64_t per = inc ? 1 : 2;
-    const int64_t reps = nsteps / per;
+    const int64_t reps = nsteps / UNIT_STEPS;
     if (reps > 0) {
         if (graph && st != nullptr) {
             if (!pl->gexec || pl->gA != A || pl->gB != B || pl->ginc != (int)inc) {
@@ -1244,7 +1249,11 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
             }
         }
     }
-    if (!inc && (nsteps % 2)) {
+    // the steps beyond whole units, launched directly (pairs, then one more)
+    const int64_t rest = nsteps % UNIT_STEPS;
+    e = steps(inc ? rest : rest - rest % 2, st);
+    if (e != hipSuccess) return dev_err(e, "mol_solve");
+    if (!inc && (rest % 2)) {
         // odd count: one more step into A, then swap the contents of A and B
         e = run_program(pl, stepP, A, B, A, nullptr, nullptr, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
