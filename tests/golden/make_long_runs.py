@@ -1,0 +1,140 @@
+"""Write the sampled oracle results of the long, full-size runs.
+
+Calls only ``oracle/`` (80-bit build) and the seeded input generators; run
+from the repository root:
+
+    python tests/golden/make_long_runs.py [name ...]
+
+Each fixture holds u^N at sampled nodes after mol_start's u^1 and N - 1
+steps of the three-level scheme (Sec. 3.2 start, eq. Full_2D steps), with the
+full field's L2 norm and max |u| for relative measures.  Samples: 2048
+uniformly drawn nodes (inside nodes on a mask) and 256 evenly spaced nodes on
+each of the four lines next to the boundary (rows 1 and n - 2, columns 1 and
+n - 2; on a mask the inside nodes of those lines), where truncated carries
+and line-end closures act.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle import lines  # noqa: E402
+from paper_1308_3214_amd import workloads as W  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# name: (description, builder)
+FIXTURES = {}
+
+
+def fixture(name):
+    def reg(fn):
+        FIXTURES[name] = fn
+        return fn
+    return reg
+
+
+def _samples(shape, inside=None, seed=12345):
+    ny, nx = shape
+    g = np.random.default_rng(seed)
+    if inside is None:
+        inside = np.ones(shape, bool)
+    flat = np.flatnonzero(inside.ravel())
+    pick = list(g.choice(flat, size=min(2048, flat.size), replace=False))
+    rows = [(1, None), (ny - 2, None), (None, 1), (None, nx - 2)]
+    for r, c in rows:
+        if r is not None:
+            idx = np.array([r * nx + i for i in range(nx) if inside[r, i]])
+        else:
+            idx = np.array([j * nx + c for j in range(ny) if inside[j, c]])
+        if idx.size:
+            sel = np.unique(np.linspace(0, idx.size - 1, min(256, idx.size)).round().astype(int))
+            pick.extend(idx[sel])
+    return np.unique(np.array(pick, dtype=np.int64))
+
+
+def _write(name, header, u, idx):
+    path = os.path.join(HERE, name + ".txt")
+    flat = u.ravel()
+    with open(path, "w") as f:
+        for line in header:
+            f.write("# " + line + "\n")
+        f.write("l2norm %.17e\n" % np.linalg.norm(flat))
+        f.write("maxabs %.17e\n" % np.abs(flat).max())
+        for i in idx:
+            f.write("%d %.17e\n" % (i, flat[i]))
+    print("wrote", path, len(idx), "samples")
+
+
+def _box_run(n, P, cfl, N):
+    h = 1.0 / (n - 1)
+    beta = float(oracle.beta_max(P))
+    alpha = beta / (cfl * h)
+    u0 = W.gaussian_pulses_2d(n, seed=1)
+    pb = oracle.Problem((n, n), h, oracle.DIRICHLET, alpha, precision="ld")
+    u1 = pb.start(u0, P, beta)
+    _, b = pb.run(u0, u1, N - 1, P, beta)
+    return b, beta, alpha, _samples((n, n))
+
+
+@fixture("config2_1024_p2_cfl2_500")
+def config2():
+    b, beta, alpha, idx = _box_run(1024, 2, 2.0, 500)
+    return ["2D 1024^2 Dirichlet on [0,1]^2, P = 2, CFL 2, 8 Gaussian pulses (sigma 0.02, seed 1)",
+            "u^500 after mol_start and 499 steps; 80-bit oracle",
+            "beta %.17e alpha %.17e" % (beta, alpha)], b, idx
+
+
+@fixture("adi4096_p2_cfl2_10")
+def adi4096():
+    b, beta, alpha, idx = _box_run(4096, 2, 2.0, 10)
+    return ["2D 4096^2 Dirichlet on [0,1]^2, P = 2, CFL 2, 8 Gaussian pulses (sigma 0.02, seed 1)",
+            "u^10 after mol_start and 9 steps; 80-bit oracle",
+            "beta %.17e alpha %.17e" % (beta, alpha)], b, idx
+
+
+def _star_run(n, P, cfl, N):
+    h = 1.0 / (n - 1)
+    beta = float(oracle.beta_max(P))
+    alpha = beta / (cfl * h)
+    dom, mask, cross = W.star_domain(n, seed=1)
+    u0 = W.star_pulses(dom, mask, seed=1)
+    segs = lines.segments(mask, cross)
+    pb = oracle.Problem((n, n), h, oracle.DIRICHLET, alpha, segments=segs, mask=mask,
+                        precision="ld")
+    u1 = pb.start(u0, P, beta)
+    _, b = pb.run(u0, u1, N - 1, P, beta)
+    return b, beta, alpha, _samples((n, n), inside=mask.astype(bool))
+
+
+@fixture("star2048_p3_cfl15_20")
+def star2048():
+    b, beta, alpha, idx = _star_run(2048, 3, 1.5, 20)
+    return ["2D 2048^2 star cavity (seed 1), 16 pulses (seed 1), P = 3, CFL 1.5",
+            "u^20 after mol_start and 19 steps; 80-bit oracle; inside nodes sampled",
+            "beta %.17e alpha %.17e" % (beta, alpha)], b, idx
+
+
+@fixture("star512_p3_cfl15_300")
+def star512():
+    b, beta, alpha, idx = _star_run(512, 3, 1.5, 300)
+    return ["2D 512^2 star cavity (seed 1), 16 pulses (seed 1), P = 3, CFL 1.5",
+            "u^300 after mol_start and 299 steps; 80-bit oracle; inside nodes sampled",
+            "beta %.17e alpha %.17e" % (beta, alpha)], b, idx
+
+
+def main(names):
+    for name in names or list(FIXTURES):
+        t = time.time()
+        header, u, idx = FIXTURES[name]()
+        header.append("written by tests/golden/make_long_runs.py %s (%.0f s)" % (name, time.time() - t))
+        _write(name, header, u, idx)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,125 @@
+"""GPU parity at large CFL numbers, the regime the A-stability of the schemes
+is for (Sec. 3.1, Theorem and Table 1: stable for every dt at beta <=
+beta_max(P)).
+
+At CFL 10, 100 and 1000 (nu = beta / CFL down to 1.2e-3) the decay of the
+exponential recurrences over a carry, d^K, reaches the rounding only after
+K ~ 20 / nu (FP32) to 40 / nu (FP64) nodes: K exceeds every tile and strip of
+the strided kernels and, on short lines, the line itself.  The cases below
+take y lines of 300 and 2048 nodes (Dirichlet and periodic) and periodic y
+lines of 64 nodes, against the FP64 oracle (operators) and its 80-bit build
+(runs): P = 1, 2, 3, FP32 and FP64, tolerances 1e-5 / 1e-12 in relative L2
+and per element.  A further test checks the scheme's conserved energy over
+1000 steps at CFL 100 on the GPU.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import TOL, check, dev, host
+from paper_1308_3214_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def molt(torch_cuda):
+    from paper_1308_3214_amd import molt as m
+    return m
+
+
+# (shape (ny, nx), h (hx, hy), bc (x, y)); dt = CFL h_x / c
+CASES = [
+    ((300, 200), (1.0 / 199, 1.0 / 299), 0),            # Dirichlet, y lines of 300
+    ((300, 200), (1.0 / 200, 1.0 / 300), 1),            # periodic both ways
+    ((2048, 64), (1.0 / 63, 1.0 / 2048), (0, 1)),       # periodic y lines of 2048
+    ((64, 2048), (1.0 / 2047, 1.0 / 64), (0, 1)),       # periodic y lines of 64, x lines of 2048
+]
+
+
+def _dirichlet_axes(bc, nd):
+    bb = list(bc) if np.ndim(bc) else [bc] * nd
+    return tuple(a for a in range(nd) if bb[a] == 0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("cfl", [10.0, 100.0, 1000.0])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_large_cfl_parity(torch_cuda, molt, oracle_mod, case, cfl, dtype):
+    torch = torch_cuda
+    shape, h, bc = CASES[case]
+    da = _dirichlet_axes(bc, 2)
+    v = W.random_field(shape, seed=200 + case, dirichlet_axes=da)
+    w = W.random_field(shape, seed=210 + case, dirichlet_axes=da)
+    vd = dev(torch, v, dtype)
+    out = torch.empty_like(vd)
+    stream = torch.cuda.Stream()
+    for P in (1, 2, 3):
+        plan = molt.Plan(shape, h, bc, P=P, cfl=cfl, dtype=dtype)
+        beta, alpha = plan.info["beta"], plan.info["alpha"]
+        print("case %d %s bc %s CFL %g P %d: nu = %s" % (case, shape, bc, cfl, P, plan.info["nu"][:2]))
+        pb = oracle_mod.Problem(shape, h, bc, alpha)
+        if P == 2:
+            for ax, nm in ((0, "x"), (1, "y")):
+                plan.apply("d_" + nm, vd, out)
+                torch.cuda.synchronize()
+                check("CFL %g D_%s %s" % (cfl, nm, shape), host(out), pb.Dg(v, ax), dtype)
+        plan.apply("rhs", vd, out)
+        torch.cuda.synchronize()
+        check("CFL %g rhs P=%d %s" % (cfl, P, shape), host(out), pb.rhs(v, P, beta), dtype)
+        # 9 steps: one captured 8-step graph on a non-default stream and one
+        # step launched directly, against the 80-bit oracle
+        pl = oracle_mod.Problem(shape, h, bc, alpha, precision="ld")
+        ra, rb = pl.run(w, v, 9, P, beta)
+        a, b = dev(torch, w, dtype), dev(torch, v, dtype)
+        with torch.cuda.stream(stream):
+            plan.solve(a, b, 9)
+        torch.cuda.synchronize()
+        check("CFL %g solve 9 P=%d %s prev" % (cfl, P, shape), host(a), ra, dtype)
+        check("CFL %g solve 9 P=%d %s curr" % (cfl, P, shape), host(b), rb, dtype)
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_energy_cfl100_1000_steps(torch_cuda, molt, bc, dtype):
+    # E = |u^{n+1} - u^n|^2 + <u^{n+1}, K u^n>, K = -rhs (symmetric on a
+    # rectangle with homogeneous Dirichlet or periodic lines), is conserved by
+    # the three-level scheme; FP64 keeps it to rounding, FP32 within
+    # 2^-23 per step accumulated over the 1000 steps (1.2e-4)
+    torch = torch_cuda
+    shape = (160, 192)
+    h = (1.0 / 191, 1.0 / 159) if bc == 0 else (1.0 / 192, 1.0 / 160)
+    nsteps = 1000
+    u0 = W.random_field(shape, seed=220 + bc, dirichlet_axes=(0, 1) if bc == 0 else ())
+    for P in (1, 2, 3):
+        plan = molt.Plan(shape, h, bc, P=P, cfl=100.0, dtype=dtype)
+        a = dev(torch, u0, dtype)
+        b = torch.empty_like(a)
+        r = torch.empty_like(a)
+        plan.start(a, b)
+
+        def energy(x, y):
+            plan.apply("rhs", x, r)
+            return float(((y - x).double() ** 2).sum() - (y.double() * r.double()).sum())
+
+        E0 = energy(a, b)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            plan.solve(a, b, nsteps)
+        torch.cuda.synchronize()
+        E1 = energy(a, b)
+        drift = abs(E1 - E0) / abs(E0)
+        mx = float(b.abs().max())
+        print("CFL 100 bc %d P %d %s: energy %.15e -> %.15e (rel drift %.2e), max |u| %.3f"
+              % (bc, P, dtype, E0, E1, drift, mx))
+        assert np.isfinite(E1)
+        assert drift < (1e-10 if dtype == "f64" else nsteps * 2.0 ** -23)
+        plan.close()

@@ -13,12 +13,10 @@ import pytest
 
 import closed_forms as cf
 from oracle import scheme
+from gpu_common import check, dev, rel
 from paper_1308_3214_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"f64": 1e-12, "f32": 1e-5}
-
 
 @pytest.fixture(scope="module")
 def torch_cuda():
@@ -32,16 +30,6 @@ def torch_cuda():
 def molt(torch_cuda):
     from paper_1308_3214_amd import molt as m
     return m
-
-
-def dev(torch, a, dtype):
-    t = torch.from_numpy(np.ascontiguousarray(a))
-    return t.to(device="cuda", dtype=torch.float64 if dtype == "f64" else torch.float32)
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def _dirichlet_axes(bc, nd):
@@ -81,17 +69,14 @@ def test_step_source_parity(torch_cuda, molt, oracle_mod, case, P, dtype):
     plan.step_source(t[0], t[1], out, t[2] if P == 2 else None, t[3], t[4] if P == 2 else None)
     torch.cuda.synchronize()
     got = out.double().cpu().numpy()
-    e = rel(got, ref)
+    check("source step %s P=%d" % (shape, P), got, ref, dtype)
     # the source part alone, so that a lost term of S is not hidden by rhs(u)
-    es = rel(got - pb.step(up, uc, P, beta), ref - pb.step(up, uc, P, beta))
-    print("source step %s P=%d %s: rel L2 %.3e (source part %.3e)" % (shape, P, dtype, e, es))
-    assert np.isfinite(got).all()
-    assert e <= TOL[dtype]
-    assert es <= TOL[dtype]
+    check("source step %s P=%d, source part" % (shape, P), got - pb.step(up, uc, P, beta),
+          ref - pb.step(up, uc, P, beta), dtype)
     # u_next may alias u_prev, as for mol_step
     plan.step_source(t[0], t[1], t[0], t[2] if P == 2 else None, t[3], t[4] if P == 2 else None)
     torch.cuda.synchronize()
-    assert rel(t[0].double().cpu().numpy(), ref) <= TOL[dtype]
+    check("source step in place %s P=%d" % (shape, P), t[0].double().cpu().numpy(), ref, dtype)
     plan.close()
 
 

@@ -2,18 +2,16 @@
 3.2) against the oracle's start_g, and a started run of the Table 3 mode
 against its 40-digit closed form.  g is scaled by 1 / dt so that the odd part
 of u^1 is as large as the even part (tolerances as for every single step:
-1e-12 FP64, 1e-5 FP32, relative L2)."""
+1e-12 FP64, 1e-5 FP32, relative L2 and per element)."""
 import numpy as np
 import pytest
 
 import closed_forms as cf
 from oracle import lines, scheme
+from gpu_common import check, dev
 from paper_1308_3214_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"f64": 1e-12, "f32": 1e-5}
-
 
 @pytest.fixture(scope="module")
 def torch_cuda():
@@ -27,16 +25,6 @@ def torch_cuda():
 def molt(torch_cuda):
     from paper_1308_3214_amd import molt as m
     return m
-
-
-def dev(torch, a, dtype):
-    t = torch.from_numpy(np.ascontiguousarray(a))
-    return t.to(device="cuda", dtype=torch.float64 if dtype == "f64" else torch.float32)
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def _dirichlet_axes(bc, nd):
@@ -80,12 +68,9 @@ def test_start_with_velocity_parity(torch_cuda, molt, oracle_mod, case, P, dtype
     plan.start(du0, out, g=dg)
     torch.cuda.synchronize()
     got = out.double().cpu().numpy()
-    e = rel(got, ref)
+    check("start with g %s P=%d" % (shape, P), got, ref, dtype)
     odd_ref = ref - pb.start(u0, P, beta)
-    eo = rel(got - pb.start(u0, P, beta), odd_ref)
-    print("start with g %s P=%d %s: rel L2 %.3e (odd part %.3e)" % (shape, P, dtype, e, eo))
-    assert np.isfinite(got).all()
-    assert e <= TOL[dtype] and eo <= TOL[dtype]
+    check("start with g %s P=%d, odd part" % (shape, P), got - pb.start(u0, P, beta), odd_ref, dtype)
     plan.close()
 
 
