@@ -62,10 +62,13 @@ def traffic_for(kernel_tag: str):
     return found
 
 
-def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=None, **kw):
-    """Time `steps` steps of mol_solve (graph replay) after `warmup` steps, with
-    HIP events on the library's stream; optional per-kernel breakdown; `keep`
-    (a list) receives the final field on the host."""
+def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=None, reps=3, **kw):
+    """Time `steps` steps of mol_solve after `warmup` untimed steps: the
+    graphs a `steps`-step call replays are captured beforehand
+    (mol_solve_prepare, nothing run), then `reps` calls of `steps` steps are
+    timed one by one with HIP events on the library's stream, each bracketed
+    by device synchronisation; returns the median call.  Optional per-kernel
+    breakdown; `keep` (a list) receives the final field on the host."""
     import torch
     from paper_1308_3214_amd import molt
 
@@ -74,19 +77,22 @@ def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=
     a = torch.tensor(u0, dtype=td, device="cuda")
     b = torch.empty_like(a)
     stream = torch.cuda.Stream()
+    times = []
     with torch.cuda.stream(stream):
         plan.start(a, b)
-        plan.solve(a, b, warmup)             # also captures the graph
-        stream.synchronize()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        plan.solve(a, b, steps)
-        e1.record(stream)
-        stream.synchronize()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+        plan.solve(a, b, warmup)
+        plan.solve_prepare(a, b, steps)
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.solve(a, b, steps)
+            e1.record(stream)
+            stream.synchronize()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+    ms = sorted(times)[len(times) // 2]
     assert torch.isfinite(b).all().item(), "non-finite field"
     if keep is not None:
         keep.append(b.double().cpu().numpy())
@@ -97,9 +103,56 @@ def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=
         with torch.cuda.stream(stream):
             kern = plan.profile_step(a, b, scratch, reps=max(3, min(20, steps // 5)))
         torch.cuda.synchronize()
-    info = plan.info
+    info = dict(plan.info)
+    info["rep_ms"] = [round(t, 4) for t in times]
     plan.close()
     return ms, kern, info
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def fixture_error(name, field):
+    """Error of a field against a sampled oracle result under tests/golden/
+    (written by tests/golden/make_long_runs.py, which calls only the oracle):
+    relative L2 over the samples and the largest sampled error relative to
+    max |u|."""
+    import numpy as np
+    idx, ref, mx = [], [], None
+    with open(os.path.join(GOLDEN, name + ".txt")) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            a, b = line.split()
+            if a == "maxabs":
+                mx = float(b)
+            elif a != "l2norm":
+                idx.append(int(a))
+                ref.append(float(b))
+    idx, ref = np.array(idx), np.array(ref)
+    g = np.asarray(field, dtype=np.float64).ravel()[idx]
+    return {"vs": "80-bit oracle, %d sampled nodes (%s)" % (idx.size, name),
+            "rel_L2": float("%.3e" % (np.linalg.norm(g - ref) / np.linalg.norm(ref))),
+            "max_elem": float("%.3e" % (np.abs(g - ref).max() / mx))}
+
+
+def solve_from_start(shape, h, bc, P, cfl, dtype, u0, nsteps, **kw):
+    """u^nsteps from mol_start and nsteps - 1 steps of mol_solve (graph
+    replay on a non-default stream), on the host."""
+    import torch
+    from paper_1308_3214_amd import molt
+    plan = molt.Plan(shape, h, bc, P=P, cfl=cfl, dtype=dtype, **kw)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    a = torch.tensor(u0, dtype=td, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.start(a, b)
+        plan.solve(a, b, nsteps - 1)
+    torch.cuda.synchronize()
+    out = b.double().cpu().numpy()
+    plan.close()
+    return out
 
 
 def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None, flags=0):
@@ -111,9 +164,13 @@ def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None, flags=0):
 
 def also_line(ms, steps, info, points):
     step_ms = ms / steps
-    return {"Mpoint-updates/s": round(points / (step_ms * 1e-3) / 1e6, 2),
-            "ms_per_step": round(step_ms, 5),
-            "model_hbm_frac": round(info["bytes_per_step"] / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out = {"Mpoint-updates/s": round(points / (step_ms * 1e-3) / 1e6, 2),
+           "ms_per_step": round(step_ms, 5),
+           "model_hbm_frac": round(info["bytes_per_step"] / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if "rep_ms" in info:
+        out["steps_per_rep"] = steps
+        out["rep_ms"] = info["rep_ms"]
+    return out
 
 
 def line1d_workload(steps=200, warmup=10):
@@ -137,16 +194,50 @@ def star_workload(steps=300, warmup=10, flags=0):
                            profile=False, mask=mask, cross=cross, flags=flags)
     out = also_line(ms, steps, info, info["unknowns"])
     out["points"] = "inside nodes (%d)" % info["unknowns"]
+    if not flags:
+        u20 = solve_from_start((n, n), 1.0 / (n - 1), 0, 3, 1.5, "f32", u0, 20, mask=mask, cross=cross)
+        out["error_u20"] = fixture_error("star2048_p3_cfl15_20", u20)
     return out
 
 
+def closed_form_plane_waves(n, ks, ph, P, beta, alpha, nsteps):
+    """Exact discrete solution of the 3D periodic scheme for plane-wave data
+    (each wave an eigenvector: a scalar three-level recurrence with the
+    symbols of C and D from the 40-digit symbol of L^{-1})."""
+    import mpmath as mp
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import closed_forms as cf
+    h = 1.0 / n
+    x = np.arange(n) / n
+    expect = np.zeros((n, n, n))
+    for (kx, ky, kz), p in zip(ks, ph):
+        Kg = [cf.khat(2 * mp.pi * int(k) * h, alpha * h) for k in (kx, ky, kz)]
+        Dg = [1 - K for K in Kg]
+        Ch = Kg[1] * Kg[2] * Dg[0] + Kg[2] * Kg[0] * Dg[1] + Kg[0] * Kg[1] * Dg[2]
+        Dh = 1 - Kg[0] * Kg[1] * Kg[2]
+        r = cf.rhs_symbol(P, beta, Ch, Dh)
+        amp = float(cf.mode_sequence(r, 1, 1 + r / 2, nsteps)[nsteps])
+        expect += 0.25 * amp * np.cos(2 * np.pi * (kx * x[None, None, :] + ky * x[None, :, None]
+                                                   + kz * x[:, None, None]) + p)
+    return expect
+
+
 def periodic3d_workload(steps=200, warmup=10):
-    """3D periodic 256^3, P = 2, CFL 2, FP32, four plane waves."""
+    """3D periodic 256^3, P = 2, CFL 2, FP32, four plane waves; error of u^200
+    against the exact discrete solution."""
+    import numpy as np
     from paper_1308_3214_amd import workloads as W
     n = 256
-    u0, _, _ = W.plane_waves_3d(n, seed=1)
+    u0, ks, ph = W.plane_waves_3d(n, seed=1)
     ms, _, info = run_plan((n, n, n), 1.0 / n, 1, 2, 2.0, "f32", u0, steps, warmup, profile=False)
-    return also_line(ms, steps, info, n ** 3)
+    out = also_line(ms, steps, info, n ** 3)
+    u200 = solve_from_start((n, n, n), 1.0 / n, 1, 2, 2.0, "f32", u0, 200)
+    ex = closed_form_plane_waves(n, ks, ph, 2, info["beta"], info["alpha"], 200)
+    out["error_u200"] = {"vs": "exact discrete solution (closed form, plane waves are eigenvectors)",
+                         "rel_L2": float("%.3e" % (np.linalg.norm(u200 - ex) / np.linalg.norm(ex))),
+                         "max_elem": float("%.3e" % (np.abs(u200 - ex).max() / np.abs(ex).max()))}
+    return out
 
 
 def source_workload(n=4096, steps=200, warmup=10):
@@ -373,6 +464,68 @@ def serve(count=256, rate_hz=50.0, seed=1, budget=2 << 30, nstreams=3, burst=Fal
     return out
 
 
+def plain_f64_vs_served(count=256, seed=1, steps=100, every=4):
+    """The ordering target: the serving workload's requests solved one after
+    another with plain FP64 plans (plan, start, graph-replayed solve, result in
+    device memory, plan freed), against the same requests served in FP32
+    (batched rounds, whole burst admitted).  Aggregate rates over the same
+    point-updates; the served FP32 results compared with the FP64 ones on
+    every `every`-th request (relative L2 per request)."""
+    import numpy as np
+    import torch
+    from paper_1308_3214_amd import molt
+    from paper_1308_3214_amd import workloads as W
+    reqs = W.request_stream(count, 50.0, seed, steps=steps, burst=True)
+    inits = [W.request_initial(r) for r in reqs]
+    pts = float(sum(r.n * r.n * r.steps for r in reqs))
+    ref = {}
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    gpu_ms = 0.0
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        plan = molt.Plan((r.n, r.n), 1.0 / (r.n - 1), 0, P=r.P, cfl=r.cfl, dtype="f64")
+        a = torch.tensor(inits[i], dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            plan.start(a, b)
+            plan.solve(a, b, r.steps - 1)
+            e1.record(stream)
+        stream.synchronize()
+        gpu_ms += e0.elapsed_time(e1)
+        if i % every == 0:
+            ref[i] = b.cpu().numpy()
+        plan.close()
+    wall = time.perf_counter() - t0
+    # the same requests served in FP32 (burst, batched rounds), results kept
+    srv = molt.Server(32 << 30, 3, batched=True)
+    rid_of = {}
+    for i, r in enumerate(reqs):
+        rid = srv.submit(inits[i], (r.n, r.n), 1.0 / (r.n - 1), r.steps, P=r.P, cfl=r.cfl, dtype="f32")
+        rid_of[rid] = i
+    errs = []
+    left = set(rid_of)
+    while left:
+        for rid in srv.poll():
+            i = rid_of[rid]
+            got = srv.result(rid)
+            left.discard(rid)
+            if i in ref:
+                errs.append(float(np.linalg.norm(got - ref[i]) / np.linalg.norm(ref[i])))
+        time.sleep(1e-4)
+    srv.close()
+    return {"requests": count, "plain_f64_wall_s": round(wall, 3),
+            "plain_f64_Mpoint-updates/s_wall": round(pts / wall / 1e6, 1),
+            "plain_f64_gpu_s": round(gpu_ms * 1e-3, 3),
+            "plain_f64_Mpoint-updates/s_gpu": round(pts / (gpu_ms * 1e-3) / 1e6, 1),
+            "served_f32_vs_plain_f64_rel_L2_max": float("%.3e" % max(errs)),
+            "served_f32_vs_plain_f64_rel_L2_median": float("%.3e" % float(np.median(errs))),
+            "compared_requests": len(errs)}
+
+
 def stream_copy(n_bytes=64 << 20, nsets=6, reps=24):
     """Measured device copy bandwidth, GB/s counting read + write: `nsets`
     buffer pairs rotated so that every copy starts from data outside the
@@ -397,21 +550,30 @@ def stream_copy(n_bytes=64 << 20, nsets=6, reps=24):
     return out
 
 
-def cpu_baseline(n, P, cfl, nsteps=1, seed=1):
-    import numpy as np
+def cpu_baseline(n, P, cfl, nsteps=1, seed=1, reps=1, keep=None):
+    """The FP64 oracle on the same workload: its start u^1, then `reps` timed
+    windows of `nsteps` steps each (the median window gives the rate); `keep`
+    (a list) receives the oracle's last field, u^(1 + reps * nsteps)."""
     import oracle
     from paper_1308_3214_amd import workloads as W
     h = 1.0 / (n - 1)
     b = oracle.beta_max(P)
     pb = oracle.Problem((n, n), h, oracle.DIRICHLET, b / (cfl * h))
     u0 = W.gaussian_pulses_2d(n, seed=seed)
-    u1 = u0.copy()
-    t = time.perf_counter()
-    pb.run(u0, u1, nsteps, P, b)
-    dt = time.perf_counter() - t
+    a, c = u0, pb.start(u0, P, b)
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        a, c = pb.run(a, c, nsteps, P, b)
+        times.append(time.perf_counter() - t)
+    dt = sorted(times)[len(times) // 2]
+    if keep is not None:
+        keep.append(c)
     return {"value": n * n * nsteps / dt / 1e6, "unit": "Mpoint-updates/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d step(s) of the %dx%d P=%d FP64 workload, %.1f s" % (nsteps, n, n, P, dt)}
+            "sample": "median of %d timed windows of %d step(s) of the %dx%d P=%d FP64 workload "
+                      "(after the oracle's start): %s s" % (reps, nsteps, n, n, P,
+                                                             ", ".join("%.2f" % x for x in times))}
 
 
 def cpu_single_thread(n=1024, P=2, cfl=2.0, nsteps=2):
@@ -475,6 +637,7 @@ def main():
     ms_step = ms / args.steps
     points = n * n
     value = points / (ms_step * 1e-3) / 1e6
+    es = 8 if args.dtype == "f64" else 4
     # dominant kernel
     dom = max(range(len(kern)), key=lambda i: kern[i]["ms"])
     k = kern[dom]
@@ -482,6 +645,10 @@ def main():
     tag = "%s_sweep_k%d" % (k["dir"], dom)
     traffic = traffic_for(tag)
     step_gbs = info["bytes_per_step"] / (ms_step * 1e-3) / 1e9
+    ksum = sum(x["ms"] for x in kern)
+    # the fixed model: 12 field passes per step for 2D P = 2 (every directional
+    # sweep reads its input and writes its output once)
+    model12 = 12 * es * points if (P == 2) else None
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -500,6 +667,10 @@ def main():
                    "grid": [n, n], "P": P, "cfl": args.cfl, "beta": info["beta"],
                    "nu": info["nu"][0], "kernels_per_step": info["kernels_per_step"],
                    "parallelism": "1 GPU"},
+        "timing": {"reps": len(info["rep_ms"]), "steps_per_rep": args.steps, "rep_ms": info["rep_ms"],
+                   "median_rep": True, "graphs_prepared": True,
+                   "kernel_sum_ms_per_step": round(ksum, 5),
+                   "ms_per_step_over_kernel_sum": round(ms_step / ksum, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": tag,
@@ -507,20 +678,32 @@ def main():
         "step_bytes": info["bytes_per_step"],
         "stream_copy_GBs": stream_copy(),
         "step_hbm_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+        "step_hbm_frac_model12": (round(model12 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                  if model12 else None),
         "kernels": [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
                      "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kern],
     }
+    if n == 4096 and P == 2 and args.cfl == 2.0:
+        from paper_1308_3214_amd import workloads as W
+        u10 = solve_from_start((n, n), 1.0 / (n - 1), 0, P, args.cfl, args.dtype,
+                               W.gaussian_pulses_2d(n, seed=1), 10)
+        out["error_u10"] = fixture_error("adi4096_p2_cfl2_10", u10)
     if not args.no_also:
         also = {}
         import numpy as np
+        from paper_1308_3214_amd import workloads as W
         fields = {}
         for dt in ("f64", "f32"):
             keep = []
-            # both precisions run start + 10 + 500 steps: the error statement
-            # compares the same u^n
+            # both precisions run start + 10 + 3 x 500 steps: the FP32-vs-FP64
+            # statement compares the same u^n
             ms2, _, inf2 = run_gpu(1024, 2, 2.0, dt, 500, 10, keep=keep)
             fields[dt] = keep[0]
-            also["1024x1024_P2_%s_500steps" % dt] = also_line(ms2, 500, inf2, 1024 * 1024)
+            line = also_line(ms2, 500, inf2, 1024 * 1024)
+            u500 = solve_from_start((1024, 1024), 1.0 / 1023, 0, 2, 2.0, dt,
+                                    W.gaussian_pulses_2d(1024, seed=1), 500)
+            line["error_u500"] = fixture_error("config2_1024_p2_cfl2_500", u500)
+            also["1024x1024_P2_%s_500steps" % dt] = line
         also["1024x1024_P2_f32_vs_f64_rel_L2"] = float(
             "%.3e" % (np.linalg.norm(fields["f32"] - fields["f64"]) / np.linalg.norm(fields["f64"])))
         # the same workload with the two y sweeps of a step in separate launches
@@ -533,8 +716,24 @@ def main():
                           "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kern2]
         also["%dx%d_P%d_%s_split_y" % (n, n, P, args.dtype)] = sp
         k64 = max(20, args.steps // 4)
-        ms2, _, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
-        also["%dx%d_P%d_f64" % (n, n, P)] = also_line(ms2, k64, inf2, points)
+        ms2, kern64, inf2 = run_gpu(n, P, args.cfl, "f64", k64, 5)
+        l64 = also_line(ms2, k64, inf2, points)
+        l64["model12_hbm_frac"] = round(12 * 8 * points / (ms2 / k64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        l64["kernels"] = [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
+                           "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kern64]
+        if n == 4096 and P == 2 and args.cfl == 2.0:
+            u10 = solve_from_start((n, n), 1.0 / (n - 1), 0, P, args.cfl, "f64",
+                                   W.gaussian_pulses_2d(n, seed=1), 10)
+            l64["error_u10"] = fixture_error("adi4096_p2_cfl2_10", u10)
+        also["%dx%d_P%d_f64" % (n, n, P)] = l64
+        # the A-stable regime: CFL 10, 100 and 1000 on the same grid
+        for cfl in (10.0, 100.0, 1000.0):
+            msc, kc, infc = run_gpu(n, P, cfl, args.dtype, args.steps, args.warmup)
+            lc = also_line(msc, args.steps, infc, points)
+            lc["nu"] = round(infc["nu"][0], 6)
+            lc["kernels"] = [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
+                              "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kc]
+            also["%dx%d_P%d_%s_cfl%g" % (n, n, P, args.dtype, cfl)] = lc
         also["line1d_1024_P1_f64_200steps"] = line1d_workload()
         also["paper_table3_641_dt0.025"] = [table3_workload(P) for P in (1, 2, 3)]
         also["star2048_P3_f32_300steps"] = star_workload()
@@ -552,10 +751,22 @@ def main():
                                       "burst": serve(burst=True, batched=True)},
                           "budget_32GiB": {"burst_pool": serve(burst=True, budget=32 << 30),
                                            "burst_batched": serve(burst=True, batched=True,
-                                                                  budget=32 << 30)}}
+                                                                  budget=32 << 30)},
+                          "plain_f64_sequential": plain_f64_vs_served()}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, P, args.cfl, 1)
+        import numpy as np
+        from paper_1308_3214_amd import workloads as W
+        keep = []
+        out["cpu_baseline"] = cpu_baseline(n, P, args.cfl, 1, reps=3, keep=keep)
         out["cpu_baseline"]["single_thread"] = cpu_single_thread(1024, P, args.cfl, 2)
+        # the headline's error against the oracle on the same seed and
+        # workload: u^4 of the GPU (start and 3 steps) against the oracle's
+        g4 = solve_from_start((n, n), 1.0 / (n - 1), 0, P, args.cfl, args.dtype,
+                              W.gaussian_pulses_2d(n, seed=1), 4)
+        r4 = keep[0]
+        out["rel_L2_vs_oracle"] = float("%.3e" % (np.linalg.norm(g4 - r4) / np.linalg.norm(r4)))
+        out["max_elem_vs_oracle"] = float("%.3e" % (np.abs(g4 - r4).max() / np.abs(r4).max()))
+        out["vs_oracle_window"] = "u^4 (start + 3 steps), FP64 oracle, same seed and workload"
     print(json.dumps(out))
 
 

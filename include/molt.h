@@ -177,11 +177,26 @@ mol_status mol_step_source(mol_plan *plan, const void *u_prev, const void *u_cur
                            const void *s_prev, const void *s_curr, const void *s_next,
                            void *stream);
 
-/* nsteps >= 0 steps in place: on entry (u_prev_io, u_curr_io) = (u^{n-1}, u^n),
- * on return (u^{n+nsteps-1}, u^{n+nsteps}).  Unless MOL_NO_GRAPH is set, the
- * step sequence is captured once in a hipGraph and replayed.  Asynchronous. */
+/* nsteps >= 0 steps of the three-level scheme (eq. Full_2D; in 1D eq.
+ * update_P) in place: on entry (u_prev_io, u_curr_io) = (u^{n-1}, u^n), on
+ * return (u^{n+nsteps-1}, u^{n+nsteps}).  The two buffers must differ and
+ * must not overlap.  On a non-NULL stream, unless MOL_NO_GRAPH is set, the
+ * steps run as replays of two hipGraphs captured for this pair of buffers on
+ * first use: a unit of 8 steps and the even remainder (nsteps mod 8, rounded
+ * down to even; an odd last step is launched directly and the two buffers'
+ * contents swapped with device copies).  On the NULL stream every launch is
+ * direct.  Calls with another pair of buffers recapture.  2D box plans with
+ * P >= 2 first launch one x sweep of u_curr (its D_x, kept in the workspace
+ * for the first step).  Asynchronous on stream. */
 mol_status mol_solve(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
                      void *stream);
+
+/* Captures and instantiates the hipGraphs that mol_solve(plan, u_prev_io,
+ * u_curr_io, nsteps, stream) replays, without running a step (for callers
+ * that keep graph instantiation out of a timed or latency-bound region).
+ * No-op on the NULL stream or with MOL_NO_GRAPH. */
+mol_status mol_solve_prepare(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
+                             void *stream);
 
 /* nsteps steps in place like mol_solve with a separable source
  * S(x, t) = f(t) G(x), a point source switched on in time for instance (Sec. 4,
@@ -264,8 +279,11 @@ mol_status mol_server_destroy(mol_server *server);
 /* Queues a request: the solution u^nsteps (nsteps >= 1) from u^0 = u0 with
  * zero initial velocity (Sec. 2, start of the three-level scheme).  u0 is a
  * host (u0_on_device = 0) or device pointer to one field of the descriptor's
- * shape and dtype; it must stay valid and unchanged until the request is
- * reported finished.  The descriptor (and its mask / cross arrays) is copied.
+ * shape and dtype (the server cannot check its size: a shorter buffer is read
+ * beyond its end); it must stay valid and unchanged until the request is
+ * reported finished.  A device u0 is read on a server stream with no ordering
+ * against the caller's streams: its contents must be complete when submit is
+ * called (synchronise the stream that wrote it first).  The descriptor (and its mask / cross arrays) is copied.
  * MOL_E_INVALID for a descriptor mol_plan_create would reject, MOL_E_NOMEM if
  * the footprint exceeds the budget.  *id receives the request id (> 0). */
 mol_status mol_server_submit(mol_server *server, const mol_desc *desc, const void *u0,
@@ -274,9 +292,10 @@ mol_status mol_server_submit(mol_server *server, const mol_desc *desc, const voi
  * requests that finished since the last poll to done_ids (*ndone of them).
  * Never blocks. */
 mol_status mol_server_poll(mol_server *server, int64_t *done_ids, int max, int *ndone);
-/* Copies the result of a finished request to dst (host or device pointer,
- * one field) and releases the request.  MOL_E_DEVICE if the request failed
- * (mol_server_last_error() tells why). */
+/* Copies the result of a finished request to dst (host or device pointer as
+ * dst_on_device says, room for one field of the request's shape and dtype)
+ * and releases the request; returns after the copy has completed.
+ * MOL_E_DEVICE if the request failed (mol_server_last_error() tells why). */
 mol_status mol_server_result(mol_server *server, int64_t id, void *dst, int dst_on_device);
 mol_status mol_server_stats(mol_server *server, mol_server_info *info);
 const char *mol_server_last_error(void);

@@ -999,11 +999,26 @@ double program_bytes(const mol_plan_ *pl, const Program &prog)
     return b * (double)pl->npts * (double)pl->es;
 }
 
-void free_plan(mol_plan_ *pl, hipStream_t st = nullptr)
+// drop the graphs captured by mol_solve
+void drop_graphs(mol_plan_ *pl)
+{
+    if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->gtail) (void)hipGraphExecDestroy(pl->gtail);
+    if (pl->gtailg) (void)hipGraphDestroy(pl->gtailg);
+    pl->gexec = nullptr;
+    pl->graph = nullptr;
+    pl->gtail = nullptr;
+    pl->gtailg = nullptr;
+    pl->gtail_n = 0;
+    pl->gA = pl->gB = nullptr;
+    pl->ginc = -1;
+}
+
+void free_plan(mol_plan_ *pl, hipStream_t st)
 {
     if (!pl) return;
-    if (pl->gexec) hipGraphExecDestroy(pl->gexec);
-    if (pl->graph) hipGraphDestroy(pl->graph);
+    drop_graphs(pl);
     for (void *p : pl->ws) {
         if (!p) continue;
         if (pl->async_ws) (void)hipFreeAsync(p, st);
@@ -1012,6 +1027,8 @@ void free_plan(mol_plan_ *pl, hipStream_t st = nullptr)
     masked_free(pl);
     delete pl;
 }
+
+mol_status set_error(mol_status s, const std::string &msg) { return fail(s, msg); }
 
 mol_status dev_err(hipError_t e, const char *what)
 {
@@ -1181,6 +1198,97 @@ mol_status mol_apply(mol_plan *pl, int op, const void *in, void *out, void *stre
     return e == hipSuccess ? MOL_OK : dev_err(e, "mol_apply");
 }
 
+}  // extern "C"
+
+namespace {
+
+// one replay unit of mol_solve: UNIT_STEPS steps (three-level: in pairs, so
+// that the fields return to their buffers), one graph launch per unit
+constexpr int64_t UNIT_STEPS = 8;
+
+// count steps of the solve program on (A, B), launched directly; the
+// three-level form alternates the roles of the two buffers
+hipError_t solve_steps(mol_plan_ *pl, void *A, void *B, int64_t count, bool inc, hipStream_t s)
+{
+    const bool fused = !pl->solve_step.empty();
+    const Program &stepP = fused ? pl->solve_step : pl->step;
+    const Program &incP = fused ? pl->solve_inc_step : pl->inc_step;
+    hipError_t r = hipSuccess;
+    for (int64_t i = 0; i < count && r == hipSuccess; ++i) {
+        if (inc) r = run_program(pl, incP, A, B, nullptr, nullptr, nullptr, s);
+        else if (i % 2 == 0) r = run_program(pl, stepP, A, B, A, nullptr, nullptr, s);
+        else r = run_program(pl, stepP, B, A, B, nullptr, nullptr, s);
+    }
+    return r;
+}
+
+// a graph of count steps on (A, B), captured on st and instantiated
+mol_status capture_steps(mol_plan_ *pl, void *A, void *B, int64_t count, bool inc, hipStream_t st,
+                         hipGraph_t *gout, hipGraphExec_t *eout)
+{
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return dev_err(e, "hipStreamBeginCapture");
+    const hipError_t eu = solve_steps(pl, A, B, count, inc, st);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(st, &gr);
+    if (eu != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return dev_err(eu, "capture");
+    }
+    if (e != hipSuccess) return dev_err(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return dev_err(e, "hipGraphInstantiate");
+    }
+    *gout = gr;
+    *eout = ge;
+    return MOL_OK;
+}
+
+// Makes sure the graphs mol_solve(A, B, nsteps) replays exist: the unit
+// (nsteps >= UNIT_STEPS) and the tail of the even part of the remainder.
+// Graphs of other buffers are dropped first.
+mol_status ensure_graphs(mol_plan_ *pl, void *A, void *B, int64_t nsteps, bool inc, hipStream_t st)
+{
+    if (pl->gA != A || pl->gB != B || pl->ginc != (int)inc) drop_graphs(pl);
+    pl->gA = A;
+    pl->gB = B;
+    pl->ginc = (int)inc;
+    if (nsteps >= UNIT_STEPS && !pl->gexec) {
+        mol_status s = capture_steps(pl, A, B, UNIT_STEPS, inc, st, &pl->graph, &pl->gexec);
+        if (s != MOL_OK) return s;
+    }
+    const int64_t rest = nsteps % UNIT_STEPS;
+    const int64_t tail = inc ? rest : rest - rest % 2;
+    if (tail > 0 && pl->gtail_n != tail) {
+        if (pl->gtail) (void)hipGraphExecDestroy(pl->gtail);
+        if (pl->gtailg) (void)hipGraphDestroy(pl->gtailg);
+        pl->gtail = nullptr;
+        pl->gtailg = nullptr;
+        pl->gtail_n = 0;
+        mol_status s = capture_steps(pl, A, B, tail, inc, st, &pl->gtailg, &pl->gtail);
+        if (s != MOL_OK) return s;
+        pl->gtail_n = tail;
+    }
+    return MOL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mol_status mol_solve_prepare(mol_plan *pl, void *A, void *B, int64_t nsteps, void *stream)
+{
+    if (!pl || !A || !B) return fail(MOL_E_INVALID, "NULL argument");
+    if (A == B) return fail(MOL_E_INVALID, "u_prev and u_curr must differ");
+    if (nsteps < 0) return fail(MOL_E_INVALID, "nsteps < 0");
+    if ((pl->desc.flags & MOL_NO_GRAPH) || stream == nullptr) return MOL_OK;
+    return ensure_graphs(pl, A, B, nsteps, (pl->desc.flags & MOL_INCREMENT_FORM) != 0,
+                         (hipStream_t)stream);
+}
+
 mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *stream)
 {
     if (!pl || !A || !B) return fail(MOL_E_INVALID, "NULL argument");
@@ -1189,7 +1297,8 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
     if (nsteps == 0) return MOL_OK;
     hipStream_t st = (hipStream_t)stream;
     const bool inc = (pl->desc.flags & MOL_INCREMENT_FORM) != 0;
-    const bool graph = !(pl->desc.flags & MOL_NO_GRAPH);
+    // graph capture needs a stream other than the legacy default stream
+    const bool graph = !(pl->desc.flags & MOL_NO_GRAPH) && st != nullptr;
     const size_t bytes = (size_t)pl->npts * pl->es;
     hipError_t e;
     if (inc) {
@@ -1197,62 +1306,32 @@ mol_status mol_solve(mol_plan *pl, void *A, void *B, int64_t nsteps, void *strea
         e = launch_axpby(pl->fp64, pl->npts, 1.0, B, -1.0, A, A, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
     }
-    // one replay unit: UNIT_STEPS steps (three-level: in pairs, so that the
-    // fields return to their buffers), one graph launch per unit
-    constexpr int64_t UNIT_STEPS = 8;
     const bool fused = !pl->solve_step.empty();
     const Program &stepP = fused ? pl->solve_step : pl->step;
-    const Program &incP = fused ? pl->solve_inc_step : pl->inc_step;
-    auto steps = [&](int64_t count, hipStream_t s) -> hipError_t {
-        hipError_t r = hipSuccess;
-        for (int64_t i = 0; i < count && r == hipSuccess; ++i) {
-            if (inc) r = run_program(pl, incP, A, B, nullptr, nullptr, nullptr, s);
-            else if (i % 2 == 0) r = run_program(pl, stepP, A, B, A, nullptr, nullptr, s);
-            else r = run_program(pl, stepP, B, A, B, nullptr, nullptr, s);
-        }
-        return r;
-    };
-    auto unit = [&](hipStream_t s) -> hipError_t { return steps(UNIT_STEPS, s); };
+    if (graph) {
+        // captured before the prologue's launch below: capture records the
+        // launches without running them
+        mol_status s = ensure_graphs(pl, A, B, nsteps, inc, st);
+        if (s != MOL_OK) return s;
+    }
     if (fused) {
         // D_x of the current field for the first stage of the first step
         e = run_program(pl, pl->solve_pro, A, B, nullptr, nullptr, nullptr, st);
         if (e != hipSuccess) return dev_err(e, "mol_solve");
     }
     const int64_t reps = nsteps / UNIT_STEPS;
-    if (reps > 0) {
-        if (graph && st != nullptr) {
-            if (!pl->gexec || pl->gA != A || pl->gB != B || pl->ginc != (int)inc) {
-                if (pl->gexec) { hipGraphExecDestroy(pl->gexec); pl->gexec = nullptr; }
-                if (pl->graph) { hipGraphDestroy(pl->graph); pl->graph = nullptr; }
-                e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) return dev_err(e, "hipStreamBeginCapture");
-                hipError_t eu = unit(st);
-                hipGraph_t gr = nullptr;
-                e = hipStreamEndCapture(st, &gr);
-                if (eu != hipSuccess) { if (gr) hipGraphDestroy(gr); return dev_err(eu, "capture"); }
-                if (e != hipSuccess) return dev_err(e, "hipStreamEndCapture");
-                e = hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0);
-                if (e != hipSuccess) { hipGraphDestroy(gr); return dev_err(e, "hipGraphInstantiate"); }
-                pl->graph = gr;
-                pl->gA = A;
-                pl->gB = B;
-                pl->ginc = (int)inc;
-            }
-            for (int64_t r = 0; r < reps; ++r) {
-                e = hipGraphLaunch(pl->gexec, st);
-                if (e != hipSuccess) return dev_err(e, "hipGraphLaunch");
-            }
-        } else {
-            for (int64_t r = 0; r < reps; ++r) {
-                e = unit(st);
-                if (e != hipSuccess) return dev_err(e, "mol_solve");
-            }
-        }
+    for (int64_t r = 0; r < reps; ++r) {
+        e = graph ? hipGraphLaunch(pl->gexec, st) : solve_steps(pl, A, B, UNIT_STEPS, inc, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve");
     }
-    // the steps beyond whole units, launched directly (pairs, then one more)
+    // the steps beyond whole units: the even part (or all of them in the
+    // increment form) as one more graph, then one odd step
     const int64_t rest = nsteps % UNIT_STEPS;
-    e = steps(inc ? rest : rest - rest % 2, st);
-    if (e != hipSuccess) return dev_err(e, "mol_solve");
+    const int64_t tail = inc ? rest : rest - rest % 2;
+    if (tail > 0) {
+        e = graph ? hipGraphLaunch(pl->gtail, st) : solve_steps(pl, A, B, tail, inc, st);
+        if (e != hipSuccess) return dev_err(e, "mol_solve");
+    }
     if (!inc && (rest % 2)) {
         // odd count: one more step into A, then swap the contents of A and B
         e = run_program(pl, stepP, A, B, A, nullptr, nullptr, st);
@@ -1414,9 +1493,8 @@ mol_status mol_plan_set_kernel_config(mol_plan *pl, int kernel, int config)
     for (Program &pr : pl->apply)
         for (ProgOp &po : pr)
             if (tune_op_key(po.op) == key) po.cfg[0] = config;
-    // the captured graph holds the old launches
-    if (pl->gexec) { (void)hipGraphExecDestroy(pl->gexec); pl->gexec = nullptr; }
-    if (pl->graph) { (void)hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+    // the captured graphs hold the old launches
+    drop_graphs(pl);
     return MOL_OK;
 }
 

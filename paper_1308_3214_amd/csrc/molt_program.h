@@ -55,9 +55,13 @@ struct mol_plan_ {
     bool has_solve_src = false;
     int src_fg = -1, src_fcg = -1;     // field slots of G and C[G] in its last launch
     int dev = 0;
-    // graph cache for mol_solve
+    // graph cache for mol_solve: the unit of UNIT_STEPS steps and one tail of
+    // an even number of steps (gtail_n), both for the buffers (gA, gB)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
+    hipGraphExec_t gtail = nullptr;
+    hipGraph_t gtailg = nullptr;
+    int64_t gtail_n = 0;
     const void *gA = nullptr, *gB = nullptr;
     int ginc = -1;
     // masked plans (embedded boundary)
@@ -167,6 +171,16 @@ void resolve_op(const mol_plan_ *pl, const ProgOp &po, const void *uprev, const 
 hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, const void *ucurr,
                        void *unext, const void *in, void *out, hipStream_t st,
                        const void *aux0 = nullptr, const void *aux1 = nullptr);
+
+// The plan of a descriptor without its workspace (dry: no device tables
+// either), and its release (frees pl->ws entries; hipFreeAsync on st for
+// plans of the request server).
+mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry);
+void free_plan(mol_plan_ *pl, hipStream_t st = nullptr);
+// A failing status with the message mol_last_error() returns; dev_err adds
+// the HIP error string.
+mol_status set_error(mol_status s, const std::string &msg);
+mol_status dev_err(hipError_t e, const char *what);
 
 // plans whose workspace is allocated and freed in stream order on st (no
 // device-wide synchronisation; used by the request server)

@@ -84,6 +84,7 @@ _lib.mol_step.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.mol_step_source.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mol_solve_source.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.mol_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
+_lib.mol_solve_prepare.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
 _lib.mol_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
 _lib.mol_step_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                 ctypes.POINTER(_vp), ctypes.c_int, _vp]
@@ -124,12 +125,14 @@ _lib.mol_server_last_error.restype = ctypes.c_char_p
 for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
            "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
            "mol_step_source", "mol_solve_source",
-           "mol_solve", "mol_apply", "mol_step_batch", "mol_server_create", "mol_server_create_ex",
+           "mol_solve", "mol_solve_prepare", "mol_apply", "mol_step_batch", "mol_server_create",
+           "mol_server_create_ex",
            "mol_server_destroy", "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
-           "mol_workspace_bytes", "mol_start", "mol_step", "mol_step_source", "mol_solve", "mol_solve_source",
+           "mol_workspace_bytes", "mol_start", "mol_step", "mol_step_source", "mol_solve",
+           "mol_solve_prepare", "mol_solve_source",
            "mol_step_batch",
            "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
            "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error",
@@ -284,6 +287,11 @@ class Plan:
         _check(_lib.mol_solve(self._h, self._t(u_prev), self._t(u_curr), int(nsteps),
                               _stream(stream)))
 
+    def solve_prepare(self, u_prev, u_curr, nsteps, stream=None):
+        """Capture the graphs solve(u_prev, u_curr, nsteps) replays, running nothing."""
+        _check(_lib.mol_solve_prepare(self._h, self._t(u_prev), self._t(u_curr), int(nsteps),
+                                      _stream(stream)))
+
     def profile_step(self, u_prev, u_curr, u_next, reps=10, stream=None):
         """Per-kernel mean duration (ms) and algorithmic bytes of one step,
         from hipEvents around each launch."""
@@ -341,19 +349,46 @@ class Server:
         if st != MOL_OK:
             raise MolError(st, _lib.mol_server_last_error().decode())
 
+    @staticmethod
+    def _field_check(x, shape, want_np, what, need_cuda=None):
+        """x must be one contiguous field of the request's shape and dtype."""
+        import torch
+        want_t = torch.float64 if want_np == np.float64 else torch.float32
+        if isinstance(x, np.ndarray):
+            if need_cuda:
+                raise ValueError("%s must be a CUDA tensor" % what)
+            if x.shape != shape:
+                raise ValueError("%s has shape %s, expected %s" % (what, x.shape, shape))
+            return
+        if not isinstance(x, torch.Tensor):
+            raise TypeError("%s must be a numpy array or a torch tensor" % what)
+        if x.dtype != want_t or tuple(x.shape) != shape or not x.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s" % (what, want_t, shape))
+        if need_cuda is not None and x.is_cuda != need_cuda:
+            raise ValueError("%s must be a %s tensor" % (what, "CUDA" if need_cuda else "host"))
+        if x.is_cuda and x.device.index != torch.cuda.current_device():
+            raise ValueError("%s is on another device than the server" % what)
+
     def submit(self, u0, shape, h, nsteps, **kw):
+        """Queue a request.  A device u0 is read later on a server stream:
+        the producing stream is synchronised here, so the data is complete."""
+        shape = tuple(int(x) for x in shape)
         d, keep = make_desc(shape, h, **kw)
+        dt = np.float64 if d.dtype == F64 else np.float32
+        self._field_check(u0, shape, dt, "u0")
         if isinstance(u0, np.ndarray):
-            arr = np.ascontiguousarray(u0, dtype=np.float64 if d.dtype == F64 else np.float32)
+            arr = np.ascontiguousarray(u0, dtype=dt)
             ptr, ondev = arr.ctypes.data, 0
         else:                      # torch tensor: device, or (pinned) host memory
             arr = u0
             ptr, ondev = u0.data_ptr(), 1 if u0.is_cuda else 0
+            if u0.is_cuda:
+                import torch
+                torch.cuda.current_stream().synchronize()
         rid = ctypes.c_int64()
         self._chk(_lib.mol_server_submit(self._h, ctypes.byref(d), ctypes.c_void_p(ptr), ondev,
                                          int(nsteps), ctypes.byref(rid)))
-        self._keep[rid.value] = (arr, keep, tuple(int(x) for x in shape),
-                                 np.float64 if d.dtype == F64 else np.float32)
+        self._keep[rid.value] = (arr, keep, shape, dt)
         return rid.value
 
     def poll(self, max_ids=1024):
@@ -371,6 +406,7 @@ class Server:
             self._keep.pop(rid, None)
             self._chk(st)
             return host
+        self._field_check(out, shape, dt, "out", need_cuda=True)
         st = _lib.mol_server_result(self._h, int(rid), ctypes.c_void_p(out.data_ptr()), 1)
         self._keep.pop(rid, None)
         self._chk(st)
