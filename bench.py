@@ -62,10 +62,10 @@ def traffic_for(kernel_tag: str):
     return found
 
 
-def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=None, reps=3, **kw):
+def run_plan(shape, h, bc, P, cfl, dtype, u0, steps, warmup, profile=True, keep=None, reps=5, **kw):
     """Time `steps` steps of mol_solve after `warmup` untimed steps: the
     graphs a `steps`-step call replays are captured beforehand
-    (mol_solve_prepare, nothing run), then `reps` calls of `steps` steps are
+    (mol_solve_prepare, nothing run), then `reps` (5) calls of `steps` steps are
     timed one by one with HIP events on the library's stream, each bracketed
     by device synchronisation; returns the median call.  Optional per-kernel
     breakdown; `keep` (a list) receives the final field on the host."""
@@ -119,7 +119,10 @@ def fixture_error(name, field):
     max |u|."""
     import numpy as np
     idx, ref, mx = [], [], None
-    with open(os.path.join(GOLDEN, name + ".txt")) as f:
+    path = os.path.join(GOLDEN, name + ".txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
         for line in f:
             if line.startswith("#"):
                 continue
@@ -170,6 +173,19 @@ def also_line(ms, steps, info, points):
     if "rep_ms" in info:
         out["steps_per_rep"] = steps
         out["rep_ms"] = info["rep_ms"]
+    return out
+
+
+def cfl_lines(n, P, dtype, steps, warmup):
+    """The A-stable regime: CFL 10, 100 and 1000 on the headline grid."""
+    out = {}
+    for cfl in (10.0, 100.0, 1000.0):
+        msc, kc, infc = run_gpu(n, P, cfl, dtype, steps, warmup)
+        lc = also_line(msc, steps, infc, n * n)
+        lc["nu"] = round(infc["nu"][0], 6)
+        lc["kernels"] = [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
+                          "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kc]
+        out["%dx%d_P%d_%s_cfl%g" % (n, n, P, dtype, cfl)] = lc
     return out
 
 
@@ -604,7 +620,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 64 MiB buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["star", "periodic3d", "table3", "source", "fig3"], default=None,
+    ap.add_argument("--only", choices=["star", "periodic3d", "table3", "source", "fig3", "cfl"], default=None,
                     help="only run one secondary workload for --steps steps (for profiling)")
     args = ap.parse_args()
     if args.only == "table3":
@@ -612,6 +628,9 @@ def main():
         return
     if args.only == "fig3":
         print(json.dumps({"fig3": fig3_workload()}))
+        return
+    if args.only == "cfl":
+        print(json.dumps({"cfl": cfl_lines(args.n, args.P, args.dtype, args.steps, args.warmup)}))
         return
     if args.only:
         fn = {"star": star_workload, "periodic3d": periodic3d_workload,
@@ -726,14 +745,7 @@ def main():
                                    W.gaussian_pulses_2d(n, seed=1), 10)
             l64["error_u10"] = fixture_error("adi4096_p2_cfl2_10", u10)
         also["%dx%d_P%d_f64" % (n, n, P)] = l64
-        # the A-stable regime: CFL 10, 100 and 1000 on the same grid
-        for cfl in (10.0, 100.0, 1000.0):
-            msc, kc, infc = run_gpu(n, P, cfl, args.dtype, args.steps, args.warmup)
-            lc = also_line(msc, args.steps, infc, points)
-            lc["nu"] = round(infc["nu"][0], 6)
-            lc["kernels"] = [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
-                              "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kc]
-            also["%dx%d_P%d_%s_cfl%g" % (n, n, P, args.dtype, cfl)] = lc
+        also.update(cfl_lines(n, P, args.dtype, args.steps, args.warmup))
         also["line1d_1024_P1_f64_200steps"] = line1d_workload()
         also["paper_table3_641_dt0.025"] = [table3_workload(P) for P in (1, 2, 3)]
         also["star2048_P3_f32_300steps"] = star_workload()

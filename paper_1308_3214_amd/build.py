@@ -14,6 +14,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = (["molt_sweep_%s%s_n%d.hip" % (k, t, n) for k in ("x", "s") for t in ("32", "64")
             for n in (4, 16)]
            + ["molt_sweep_p%s_p%d.hip" % (t, n) for t in ("32", "64") for n in (1, 2, 4)]
+           + ["molt_sweep_e%s_n%d.hip" % (t, n) for t in ("32", "64") for n in (4, 16)]
            + ["molt_sweep_yy32.hip", "molt_kernels.hip", "molt_plan.cpp", "molt_masked.cpp", "molt_seg.hip",
               "molt_server.cpp"])
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -22,8 +23,18 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str) -> str:
+def _newest_header() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".inc"))]
+    hs.append(os.path.join(HERE, "..", "include", "molt.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
+            return obj
     cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -32,11 +43,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8, out: str = OUT) -> str:
+def build(jobs: int = 8, out: str = OUT, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their object
+    or than a header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs, "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,4 +61,5 @@ def build(jobs: int = 8, out: str = OUT) -> str:
 
 
 if __name__ == "__main__":
-    print(build(out=sys.argv[1] if len(sys.argv) > 1 else OUT))
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    print(build(out=args[0] if args else OUT, incremental="--incremental" in sys.argv))

@@ -64,9 +64,17 @@ struct Geom {
 // Launch one sweep.  ptrs: resolved device pointers for op.f / op.o (followed
 // by the chained output when op.chain is set).
 // Returns hipSuccess or the launch error.
+// agg: the plan's aggregate table for exact two-pass strided sweeps (may be
+// NULL for other configurations).
 hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
                         const void *const *fptr, void *const *optr, const int *cfg,
-                        hipStream_t st);
+                        hipStream_t st, void *agg = nullptr);
+// Exact two-pass strided configurations: the smallest tile they use, whether
+// cfg is one, and the bytes of the aggregate table a plan holds for sweeps
+// along dir (0 for x).
+constexpr int EXACT_MIN_TILE = 128;
+bool config_exact(const SweepOp &op, const int *cfg);
+size_t exact_agg_bytes(const Geom &g, int dir, bool fp64);
 
 // Per-direction launch configuration chosen by the plan: cfg[0] = variant id.
 // Strided sweeps: ids below NSCFG are the tile kernel, the

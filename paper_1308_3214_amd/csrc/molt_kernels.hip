@@ -87,10 +87,12 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
 // Argument set, instantiation key and workgroup count of one launch.
 template <typename T>
 void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *const *fptr,
-            void *const *optr, const int *cfg, KArgs<T> &k, SweepKey &key, int64_t &blocks)
+            void *const *optr, const int *cfg, KArgs<T> &k, SweepKey &key, int64_t &blocks,
+            void *agg = nullptr)
 {
     k = KArgs<T>{};
     fill_common<T>(k, op, dc, fptr, optr);
+    k.agg = static_cast<T *>(agg);
     const int dir = op.dir;
     key = SweepKey{};
     key.fp64 = sizeof(T) == 8 ? 1 : 0;
@@ -110,6 +112,7 @@ void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *con
             if (i < op.no && (reinterpret_cast<uintptr_t>(optr[i]) % (vw * sizeof(T)))) k.aligned = 0;
         k.dS = (T)exp(-dc.nu * c.S);
         k.dBlk = (T)exp(-dc.nu * c.S * 64.0);
+        for (int i = 0; i < 6; ++i) k.dpw[i] = (T)exp(-dc.nu * c.S * (double)(1 << i));
         k.pn1 = g.n[1];
         k.pn2 = g.n[2];
         k.pd1 = g.ndim > 1 ? g.dirichlet[1] : 0;
@@ -156,6 +159,21 @@ void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *con
         key.cls = 3;
         key.nsno = op.no;
         key.nfb = 3;
+        blocks = k.nblocks;
+        return;
+    }
+    if (cfg[0] >= NSCFG + NPCFG) {
+        // exact two-pass tiles
+        const SCfg c = kECfg[cfg[0] - NSCFG - NPCFG];
+        const int64_t WS = (int64_t)c.S * c.W;
+        k.ntiles = (int)((dc.n + WS - 1) / WS);
+        k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
+        k.dS = (T)exp(-dc.nu * c.S);
+        k.dBlk = k.dS;
+        k.dT = (T)exp(-dc.nu * (double)WS);
+        key.cls = 4;
+        key.cfg = cfg[0] - NSCFG - NPCFG;
+        key.nfb = op.nf <= 4 ? 4 : 16;
         blocks = k.nblocks;
         return;
     }
@@ -221,6 +239,13 @@ hipError_t dispatch_t(const KArgs<T> &k, const SweepKey &key, int64_t blocks, co
     case 3:
         if constexpr (sizeof(T) == 4) return dispatch_yy_f32(k, key.nsno, key.cfg, bt, st);
         else return hipErrorInvalidValue;
+    case 4:
+        // two launches of their own: no batched table
+        if (bt) return hipErrorInvalidValue;
+        if constexpr (sizeof(T) == 4)
+            return small ? dispatch_e_f32_n4(k, key.nsno, key.cfg, st) : dispatch_e_f32_n16(k, key.nsno, key.cfg, st);
+        else
+            return small ? dispatch_e_f64_n4(k, key.nsno, key.cfg, st) : dispatch_e_f64_n16(k, key.nsno, key.cfg, st);
     default:
         return hipErrorInvalidValue;
     }
@@ -228,12 +253,13 @@ hipError_t dispatch_t(const KArgs<T> &k, const SweepKey &key, int64_t blocks, co
 
 template <typename T>
 hipError_t launch_t(const SweepOp &op, const Geom &g, const DirCoef &dc,
-                    const void *const *fptr, void *const *optr, const int *cfg, hipStream_t st)
+                    const void *const *fptr, void *const *optr, const int *cfg, hipStream_t st,
+                    void *agg)
 {
     KArgs<T> k;
     SweepKey key;
     int64_t blocks = 0;
-    prep_t<T>(op, g, dc, fptr, optr, cfg, k, key, blocks);
+    prep_t<T>(op, g, dc, fptr, optr, cfg, k, key, blocks, agg);
     return dispatch_t<T>(k, key, blocks, nullptr, st);
 }
 
@@ -274,7 +300,17 @@ bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64
         if (lds > (size_t)max_lds()) return false;
         return true;
     }
-    if (cfg[0] < 0 || cfg[0] >= NSCFG + NPCFG) return false;
+    if (cfg[0] < 0 || cfg[0] >= NSCFG + NPCFG + NECFG) return false;
+    if (cfg[0] >= NSCFG + NPCFG) {
+        // exact two-pass tiles: a line of at least two tiles (a shorter one is
+        // exact in the tile kernel), at most ntiles_max(dc.n) tiles (the size
+        // of the aggregate table a plan holds)
+        const SCfg c = kECfg[cfg[0] - NSCFG - NPCFG];
+        const int64_t WS = (int64_t)c.S * c.W;
+        if (dc.n <= WS) return false;
+        if (WS < EXACT_MIN_TILE) return false;
+        return true;
+    }
     if (cfg[0] >= NSCFG) {
         // pipelined strips: at most 4 fields, sub-tiles at least as tall as
         // the halo and lines of at least two sub-tiles per strip
@@ -342,21 +378,51 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
         if (groups * (tiles / 2) >= 256 && config_valid(g, dc, op, fp64, cfg)) return 0;
     }
     const int regs = (2 * ns + no) * (fp64 ? 2 : 1);
-    cfg[0] = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
+    const int tcfg = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
+    // carries longer than half a tile (small nu): the tile kernel's halo sums
+    // would read more than the tile itself; the exact two-pass sweep of the
+    // same tile shape reads the tile twice, whatever the carry length
+    const SCfg tc = kSCfg[tcfg];
+    if (2 * (int64_t)dc.halo > (int64_t)tc.S * tc.W) {
+        cfg[0] = NSCFG + NPCFG + (tcfg == 0 ? 0 : 1);
+        static_assert(kECfg[0].S == kSCfg[0].S && kECfg[0].W == kSCfg[0].W &&
+                      kECfg[1].S == kSCfg[2].S && kECfg[1].W == kSCfg[2].W,
+                      "exact tile shapes follow the tile configurations 0 and 2");
+        if (config_valid(g, dc, op, fp64, cfg)) return 0;
+    }
+    cfg[0] = tcfg;
     return config_valid(g, dc, op, fp64, cfg) ? 0 : -1;
 }
 
 int uniform_x_capacity(int id) { return (id >= 0 && id < NXCFG) ? kXCfg[id].S * kXCfg[id].WPL : 0; }
 
-int config_count(const SweepOp &op) { return op.yy ? NYCFG : op.dir == 0 ? NXCFG : NSCFG + NPCFG; }
+int config_count(const SweepOp &op)
+{
+    return op.yy ? NYCFG : op.dir == 0 ? NXCFG : NSCFG + NPCFG + NECFG;
+}
+
+bool config_exact(const SweepOp &op, const int *cfg)
+{
+    return !op.yy && op.dir != 0 && cfg[0] >= NSCFG + NPCFG;
+}
+
+size_t exact_agg_bytes(const Geom &g, int dir, bool fp64)
+{
+    if (dir < 1 || dir >= g.ndim) return 0;
+    const int64_t ncg = (g.n[0] + 63) / 64;
+    const int64_t nouter = dir == 1 ? g.n[2] : g.n[1];
+    const int64_t ntiles = (g.n[dir] + EXACT_MIN_TILE - 1) / EXACT_MIN_TILE;
+    return (size_t)(nouter * ncg * ntiles) * MAXS * 3 * 64 * (fp64 ? 8 : 4);
+}
 
 hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp64,
                         const void *const *fptr, void *const *optr, const int *cfg,
-                        hipStream_t st)
+                        hipStream_t st, void *agg)
 {
     if (!config_valid(g, dc, op, fp64, cfg)) return hipErrorInvalidValue;
-    return fp64 ? launch_t<double>(op, g, dc, fptr, optr, cfg, st)
-                : launch_t<float>(op, g, dc, fptr, optr, cfg, st);
+    if (config_exact(op, cfg) && !agg) return hipErrorInvalidValue;
+    return fp64 ? launch_t<double>(op, g, dc, fptr, optr, cfg, st, agg)
+                : launch_t<float>(op, g, dc, fptr, optr, cfg, st, agg);
 }
 
 size_t sweep_args_bytes(bool fp64) { return fp64 ? sizeof(KArgs<double>) : sizeof(KArgs<float>); }
@@ -365,7 +431,7 @@ bool sweep_prepare(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp6
                    const void *const *fptr, void *const *optr, const int *cfg, void *args,
                    SweepKey &key, int64_t &blocks)
 {
-    if (!config_valid(g, dc, op, fp64, cfg)) return false;
+    if (!config_valid(g, dc, op, fp64, cfg) || config_exact(op, cfg)) return false;
     if (fp64) {
         KArgs<double> k;
         prep_t<double>(op, g, dc, fptr, optr, cfg, k, key, blocks);

@@ -877,6 +877,8 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
         pl->dc[a] = make_dircoef(nu, g.n[a], d->bc[a] == MOL_BC_PERIODIC, pl->fp64);
     }
     pl->masked = (d->mask != nullptr);
+    if (!pl->masked)
+        pl->agg_bytes = std::max(exact_agg_bytes(g, 1, pl->fp64), exact_agg_bytes(g, 2, pl->fp64));
     if (pl->masked) {
         std::string err;
         pl->h_mask.assign(d->mask, d->mask + pl->npts);
@@ -978,7 +980,7 @@ hipError_t run_program(mol_plan_ *pl, const Program &prog, const void *uprev, co
         if (pl->masked)
             e = launch_seg_op(po.op, pl, fp, op, st);
         else
-            e = launch_sweep(po.op, pl->geom, pl->dc[po.op.dir], pl->fp64, fp, op, po.cfg, st);
+            e = launch_sweep(po.op, pl->geom, pl->dc[po.op.dir], pl->fp64, fp, op, po.cfg, st, pl->agg);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1024,6 +1026,11 @@ void free_plan(mol_plan_ *pl, hipStream_t st)
         if (pl->async_ws) (void)hipFreeAsync(p, st);
         else (void)hipFree(p);
     }
+    if (pl->agg) {
+        if (pl->async_ws) (void)hipFreeAsync(pl->agg, st);
+        else (void)hipFree(pl->agg);
+        pl->agg = nullptr;
+    }
     masked_free(pl);
     delete pl;
 }
@@ -1060,6 +1067,11 @@ mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **o
         }
         (void)hipMemsetAsync(pl->ws[i], 0, (size_t)pl->npts * pl->es, st);
     }
+    if (pl->agg_bytes && hipMallocAsync(&pl->agg, pl->agg_bytes, st) != hipSuccess) {
+        pl->agg = nullptr;
+        free_plan(pl, st);
+        return fail(MOL_E_NOMEM, "stream-ordered allocation of the aggregate table failed");
+    }
     *out = pl;
     return MOL_OK;
 }
@@ -1087,7 +1099,7 @@ size_t mol_workspace_bytes(const mol_desc *desc)
     if (!pl) return 0;
     size_t r = 0;
     if (build_plan(desc, pl, true) == MOL_OK)
-        r = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes;
+        r = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes + pl->agg_bytes;
     masked_free(pl);
     delete pl;
     return r;
@@ -1113,6 +1125,11 @@ mol_status mol_plan_create(const mol_desc *desc, mol_plan **out)
         }
         // workspace never holds stale non-finite values
         hipMemset(pl->ws[i], 0, (size_t)pl->npts * pl->es);
+    }
+    if (pl->agg_bytes && hipMalloc(&pl->agg, pl->agg_bytes) != hipSuccess) {
+        pl->agg = nullptr;
+        free_plan(pl);
+        return fail(MOL_E_NOMEM, "hipMalloc of the aggregate table failed");
     }
     hipDeviceSynchronize();
     *out = pl;
@@ -1143,7 +1160,7 @@ mol_status mol_plan_get_info(const mol_plan *pl, mol_plan_info *info)
     const Program &sp = pl->solve_step.empty() ? pl->step : pl->solve_step;
     info->kernels_per_step = (int)sp.size();
     info->bytes_per_step = program_bytes(pl, sp);
-    info->workspace_bytes = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes;
+    info->workspace_bytes = (size_t)pl->nws * (size_t)pl->npts * pl->es + pl->table_bytes + pl->agg_bytes;
     if (pl->has_src) {
         info->kernels_per_source_step = (int)pl->step_src.size();
         info->bytes_per_source_step = program_bytes(pl, pl->step_src);

@@ -35,6 +35,10 @@ struct mol_plan_ {
     size_t es = 8;
     int nws = 0;                       // workspace fields
     std::vector<void *> ws;            // device workspace fields
+    // aggregate table of the exact two-pass strided sweeps (box plans in 2D
+    // and 3D; sized for the smallest tile along y and z)
+    void *agg = nullptr;
+    size_t agg_bytes = 0;
     molt::Program step, start, inc_step;
     // fused solve (2D rectangles, P >= 2): the last x sweep of a step also
     // writes D_x u^{n+1} into ws chain_a for the next step's first stage

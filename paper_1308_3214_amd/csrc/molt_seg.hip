@@ -24,6 +24,7 @@ struct SegArgs {
     int64_t seg0;        // first record of this launch
     int64_t pstride;     // element stride along the line
     T d, g, w2, gw, dS, dBlk;
+    T dpw[6];            // d^{S 2^i}, i < 6: the lane scan's multipliers
     double nu;
 };
 
@@ -154,14 +155,14 @@ k_seg_sweep(const SegArgs<T> a)
     T cL[NS], cR[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        T xl = aL[k], xr = aR[k], mm = a.dS;
+        T xl = aL[k], xr = aR[k];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
+        for (int i = 0, off = 1; off < 64; ++i, off <<= 1) {
+            const T mm = a.dpw[i];       // d^(S off), rounded once from FP64
             const T yl = shfl_up(xl, off);
             const T yr = shfl_down(xr, off);
             if (lane >= off) xl += mm * yl;
             if (lane + off < 64) xr += mm * yr;
-            mm *= mm;
         }
         const T exl = shfl_up(xl, 1);
         const T exr = shfl_down(xr, 1);
@@ -371,6 +372,7 @@ hipError_t seg_sweep_t(const SweepOp &op, const SegTable &tab, const DirCoef &dc
         k.seg0 = tab.cls_begin[c];
         k.dS = (T)std::exp(-dc.nu * kSegCfg[c].S);
         k.dBlk = (T)std::exp(-dc.nu * kSegCfg[c].S * 64.0);
+        for (int i = 0; i < 6; ++i) k.dpw[i] = (T)std::exp(-dc.nu * kSegCfg[c].S * (double)(1 << i));
         hipError_t e;
         switch (nsno) {
         case 11: e = dispatch_seg<T, 1, 1>(k, c, count, st); break;

@@ -49,7 +49,7 @@ namespace molt {
 template <typename... A, typename F>
 inline void launch_k(F fn, dim3 grid, dim3 block, size_t shmem, hipStream_t st, A... args)
 {
-    if (g_prof.start) {
+    if (g_prof.start || g_prof.stop) {
         hipExtLaunchKernelGGL(fn, grid, block, (std::uint32_t)shmem, st, g_prof.start, g_prof.stop, 0u,
                               args...);
         g_prof = ProfEvents{};
@@ -84,6 +84,7 @@ struct KArgs {
     T gw;             // g + w2
     T dS;             // d^S
     T dBlk;           // x: d^{64 S} (one wave of lanes)
+    T dpw[6];         // x: d^{S 2^i}, i < 6 (the lane scan's multipliers)
     double nu;
     double K00, K01, K10, K11;
     // projection: line index = (i1 in [0,pn1), i2 in [0,pn2)); Dirichlet flags
@@ -98,6 +99,10 @@ struct KArgs {
     // yk0 = 1 / mOD[0][0] (field terms of a single output), ykh = mV[1] -
     // mOD[1][0] mV[0] / mOD[0][0] (weight of v1 left in output 1)
     T ykv, yk0, ykh;
+    // exact two-pass strided sweeps: per-tile aggregates (device table of
+    // nouter x column groups x ntiles x MAXS x 3 x 64 values) and d^(W S)
+    T *agg;
+    T dT;
 };
 
 // ---------------------------------------------------------------------------
@@ -472,14 +477,16 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
     T cL[NSW], cR[NSW];
 #pragma unroll
     for (int k = 0; k < NSW; ++k) {
-        T xl = aL[k], xr = aR[k], m = a.dS;
+        T xl = aL[k], xr = aR[k];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
+        for (int i = 0, off = 1; off < 64; ++i, off <<= 1) {
+            // multiplier d^(S off), rounded once from FP64 (repeated squaring
+            // in FP32 would compound its rounding 32-fold)
+            const T m = a.dpw[i];
             const T yl = shfl_up(xl, off);
             const T yr = shfl_down(xr, off);
             if (lane >= off) xl += m * yl;
             if (lane + off < 64) xr += m * yr;
-            m *= m;
         }
         const T exl = shfl_up(xl, 1);
         const T exr = shfl_down(xr, 1);
@@ -1038,6 +1045,221 @@ k_sweep_s_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first,
 {
     const int e = batch_entry(first, nent, blockIdx.x);
     sweep_s_body<T, S, W, NS, NO, PER, NFMAX>(tab[e], (int64_t)blockIdx.x - first[e]);
+}
+
+// ---------------------------------------------------------------------------
+// exact strided sweep in two passes (y or z lines of any length and any nu)
+// ---------------------------------------------------------------------------
+// The recurrences are linear, so the carry entering a tile is a sum over the
+// tiles before it of their own aggregates, each damped by d per node.  Pass 1
+// (MODE 1) sweeps every tile with zero carries in and writes, per column, its
+// forward aggregate TL (E^L at its last row), its backward aggregate TR (E^R
+// at its first row) and, for the tile holding node M, E^L at M (EM).  Pass 2
+// (MODE 2) sweeps every tile again: its wave 0 folds the aggregates into the
+// exact carries entering the tile, cTop = sum_{t'<t} d^{WS (t-1-t')} TL_t' and
+// cBot = sum_{t'>t} d^{WS (t'-t-1)} TR_t', and into the line-end values
+// E^R_0 = sum_t d^{WS t} TR_t and E^L_M = EM + d^{M - s_last + 1} cTop_last, from
+// which the boundary correction (Dirichlet or periodic) is formed as on a
+// line held by one tile.  Nothing is truncated: the cost is one more read of
+// the swept fields instead of halos that grow like 1/nu.
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX, int MODE>
+__device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bid)
+{
+    constexpr int WS = W * S;
+    __shared__ T red[2][NS][W][64];      // wave aggregates
+    __shared__ T carry[4][NS][64];       // cTop, cBot, E^R_0, E^L_M of the tile's columns
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t L = xcd_remap(bid, a.nblocks);
+    const int ntiles = a.ntiles;
+    const int tile = (int)(L % ntiles);
+    const int64_t rest = L / ntiles;
+    const int64_t ncg = (a.nlines + 63) / 64;
+    const int64_t cg = rest % ncg;
+    const int64_t outer = rest / ncg;
+    const int col = (int)(cg * 64) + lane;
+    const bool active = col < a.nlines;
+    const int n = (int)a.n, M = n - 1;
+    const int ls = (int)a.ls;
+    const int64_t blk = cg * 64 + outer * a.os;
+    const int loff = active ? lane : 0;
+    constexpr bool dir_end = !PER;
+    const T d = a.d, g = a.g, w2 = a.w2;
+    const int oa = tile * WS;
+    const int p0 = oa + wave * S;
+    // aggregate table of this column group: [tile][k][3][64]
+    T *tab = a.agg + (size_t)(outer * ncg + cg) * (size_t)ntiles * (MAXS * 3 * 64);
+
+    // ---- loads of nodes p0-1 .. p0+S and the prologue ----
+    constexpr int NOE = (MODE == 2) ? NO : 1;
+    T ev[NOE][S];
+    T v[NS][S + 2];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) v[k][j] = T(0);
+#pragma unroll
+    for (int o = 0; o < NOE; ++o)
+#pragma unroll
+        for (int j = 0; j < S; ++j) ev[o][j] = T(0);
+    const unsigned lo = (unsigned)loff;
+    auto rowptr = [&](const T *fb, int p) -> const T * {
+        if (PER) {
+            if (p < 0) p += n;
+            if (p >= n) p -= n;
+        }
+        return (p >= 0 && p <= M) ? fb + (int64_t)p * ls : zero_row<T>();
+    };
+    auto load_fields = [&](int f0, auto cc) {
+        constexpr int C = decltype(cc)::value;
+        T x[C][S + 2];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const T *fb = a.f[f0 + c] + blk;
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j) x[c][j] = rowptr(fb, p0 - 1 + j)[lo];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int f = f0 + c;
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) v[k][j] += a.mS[k][f] * x[c][j];
+                if (MODE == 2 && j >= 1 && j <= S) {
+#pragma unroll
+                    for (int o = 0; o < NOE; ++o) ev[o][j - 1] += a.mOF[o][f] * x[c][j];
+                }
+            }
+        }
+    };
+    field_chunks<2, NFMAX>(a.nf, load_fields);
+    if (dir_end) {
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) {
+            const int p = p0 - 1 + j;
+            if (p == 0 || p == M) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) v[k][j] = T(0);
+            }
+        }
+    }
+
+    // ---- local recurrences of this wave's S nodes (zero carries in) ----
+    const int jm = M - p0;
+    const bool slow = PER && (p0 + S - 1 > M);          // periodic wave crossing the end
+    T sum[NS][S];
+    T aL[NS], aR[NS], eLM[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (PER && slow) {
+            seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
+        } else {
+            seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
+            eLM[k] = aL[k];
+            if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
+                T vM1 = T(0);
+#pragma unroll
+                for (int j = 0; j < S + 2; ++j)
+                    if (j == jm) vM1 = v[k][j];            // node M-1
+                seg_fix_dirichlet<T, S>(p0, M, v[k][2], vM1, d, w2, sum[k], aL[k], aR[k], eLM[k]);
+            }
+        }
+        red[0][k][wave][lane] = aL[k];
+        red[1][k][wave][lane] = aR[k];
+    }
+    __syncthreads();
+
+    if (MODE == 1) {
+        // the tile's aggregates; E^L at node M from the wave holding it
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T *tk = tab + ((size_t)tile * MAXS + k) * (3 * 64);
+            if (wave == 0) {
+                T c = T(0), cr = T(0);
+                for (int w = 0; w < W; ++w) c = a.dS * c + red[0][k][w][lane];
+                for (int w = W - 1; w >= 0; --w) cr = a.dS * cr + red[1][k][w][lane];
+                tk[lane] = c;
+                tk[64 + lane] = cr;
+            }
+            if (jm >= 0 && jm < S) {
+                T c = T(0);
+                for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
+                tk[128 + lane] = eLM[k] + expneg<T>(a.nu * (double)(jm + 1)) * c;
+            }
+        }
+        return;
+    }
+
+    // ---- exact carries and line-end values from the aggregates (wave 0) ----
+    if (wave == 0) {
+        const int last = ntiles - 1;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T e = T(0), cb = T(0);
+            for (int t = last; t >= 0; --t) {
+                if (t == tile) cb = e;
+                e = a.dT * e + tab[((size_t)t * MAXS + k) * (3 * 64) + 64 + lane];
+            }
+            T c = T(0), ct = T(0);
+            for (int t = 0; t < last; ++t) {
+                if (t == tile) ct = c;
+                c = a.dT * c + tab[((size_t)t * MAXS + k) * (3 * 64) + lane];
+            }
+            if (tile == last) ct = c;
+            const T em = tab[((size_t)last * MAXS + k) * (3 * 64) + 128 + lane];
+            carry[0][k][lane] = ct;
+            carry[1][k][lane] = cb;
+            carry[2][k][lane] = e;
+            carry[3][k][lane] = em + expneg<T>(a.nu * (double)(M - last * WS + 1)) * c;
+        }
+    }
+    __syncthreads();
+    T cL[NS], cR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T c = carry[0][k][lane];
+        for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
+        cL[k] = c;
+        T cr = carry[1][k][lane];
+        for (int w = W - 1; w > wave; --w) cr = a.dS * cr + red[1][k][w][lane];
+        cR[k] = cr;
+    }
+
+    // ---- closure and epilogue ----
+    bool bline = false;
+    if (a.proj)
+        bline = (a.pd1 && (col == 0 || col == a.pn1 - 1)) ||
+                (a.pd2 && (outer == 0 || outer == a.pn2 - 1));
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const double er0 = (double)carry[2][k][lane], elm = (double)carry[3][k][lane];
+        const double A = a.K00 * er0 + a.K01 * elm;
+        const double B = a.K10 * er0 + a.K11 * elm;
+        if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, false);
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, dir_end);
+    }
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        if (p > M) break;
+        const bool z = a.proj && (bline || (dir_end && (p == 0 || p == M)));
+#pragma unroll
+        for (int o = 0; o < NOE; ++o) {
+            T r = ev[o][j];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * sum[k][j];
+            (a.o[o] + blk + (int64_t)p * ls)[lo] = z ? T(0) : r;
+        }
+    }
+}
+template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX, int MODE>
+__global__ void __launch_bounds__(64 * W)
+k_sweep_e(const KArgs<T> a)
+{
+    sweep_e_body<T, S, W, NS, NO, PER, NFMAX, MODE>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1787,6 +2009,9 @@ constexpr int NSCFG = sizeof(kSCfg) / sizeof(kSCfg[0]);
 struct PCfg { int S, W, target; };
 constexpr PCfg kPCfg[] = {{8, 16, 256}, {16, 8, 512}, {8, 8, 512}, {8, 16, 512}, {16, 8, 256}, {4, 16, 256}};
 constexpr int NPCFG = sizeof(kPCfg) / sizeof(kPCfg[0]);
+// exact two-pass strided configurations (tile shapes, S x W rows per tile)
+constexpr SCfg kECfg[] = {{16, 16}, {8, 16}};
+constexpr int NECFG = sizeof(kECfg) / sizeof(kECfg[0]);
 // chained strided configurations (same fields as PCfg)
 constexpr PCfg kYCfg[] = {{8, 8, 256}, {4, 16, 256}, {8, 8, 512}, {4, 16, 512}, {4, 8, 256}};
 constexpr int NYCFG = sizeof(kYCfg) / sizeof(kYCfg[0]);
@@ -1821,6 +2046,11 @@ hipError_t dispatch_p_f32_p4(const KArgs<float> &k, int nsno, int id, const Batc
 hipError_t dispatch_p_f64_p1(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
 hipError_t dispatch_p_f64_p2(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
 hipError_t dispatch_p_f64_p4(const KArgs<double> &k, int nsno, int id, const BatchTab *bt, hipStream_t st);
+// exact two-pass strided kernels: both passes of one sweep (k.agg set)
+hipError_t dispatch_e_f32_n4(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_e_f64_n4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_e_f32_n16(const KArgs<float> &k, int nsno, int id, hipStream_t st);
+hipError_t dispatch_e_f64_n16(const KArgs<double> &k, int nsno, int id, hipStream_t st);
 // chained strided kernels (FP32, op.nf <= 3, one or two outputs)
 hipError_t dispatch_yy_f32(const KArgs<float> &k, int no, int id, const BatchTab *bt, hipStream_t st);
 

@@ -1,0 +1,5 @@
+// Exact two-pass strided-sweep kernels, float, field loop bound 4.
+#define MOLT_T float
+#define MOLT_TAG f32
+#define MOLT_NFMAX 4
+#include "molt_sweep_e.inc"

@@ -1,0 +1,5 @@
+// Exact two-pass strided-sweep kernels, double, field loop bound 16.
+#define MOLT_T double
+#define MOLT_TAG f64
+#define MOLT_NFMAX 16
+#include "molt_sweep_e.inc"

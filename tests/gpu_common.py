@@ -29,6 +29,10 @@ def check(name, got, ref, dtype, tol=None):
     ref = np.asarray(ref, dtype=np.float64)
     e, m = rel(got, ref), elem(got, ref)
     print("%-52s %s rel L2 = %.3e  max elem = %.3e" % (name, dtype, e, m))
+    if m > t and got.size:
+        i = int(np.abs(got - ref).argmax())
+        print("    largest error at index %s: got %.17g ref %.17g (max |ref| %.6g)"
+              % (np.unravel_index(i, got.shape), got.ravel()[i], ref.ravel()[i], np.abs(ref).max()))
     assert np.isfinite(got).all(), name
     assert e <= t, (name, "rel L2", e)
     assert m <= t, (name, "max elem", m)

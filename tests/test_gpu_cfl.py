@@ -9,8 +9,18 @@ the strided kernels and, on short lines, the line itself.  The cases below
 take y lines of 300 and 2048 nodes (Dirichlet and periodic) and periodic y
 lines of 64 nodes, against the FP64 oracle (operators) and its 80-bit build
 (runs): P = 1, 2, 3, FP32 and FP64, tolerances 1e-5 / 1e-12 in relative L2
-and per element.  A further test checks the scheme's conserved energy over
-1000 steps at CFL 100 on the GPU.
+and per element.
+
+Data.  The directional operators D_x, D_y are checked on random data (values
+that vary on the grid scale, D of order 1).  The rhs and the time steps are
+checked on smooth data (Gaussian pulses of width 0.05): for data that varies
+on the grid scale, the ADI operator C = L_y^-1 D_x + L_x^-1 D_y is small
+where L^-1 damps (its symbol (1 - Dx) Dy + (1 - Dy) Dx tends to 0 as nu -> 0
+for every non-smooth mode), so C v is a difference of order-1 terms whose
+rounding is |D_x v| / |C v| times that of one directional sweep (measured
+|C v| / |D_x v| = 1.6e-3 at CFL 1000 for random data on the 300 x 200 grid).
+A further test checks the scheme's conserved energy over 1000 steps at CFL
+100 on the GPU, from random data.
 """
 import numpy as np
 import pytest
@@ -49,6 +59,11 @@ def _dirichlet_axes(bc, nd):
     return tuple(a for a in range(nd) if bb[a] == 0)
 
 
+def _smooth(shape, seed):
+    ny, nx = shape
+    return W.gaussian_pulses_2d(nx, seed=seed, npulses=3, sigma=0.05, ny=ny)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("cfl", [10.0, 100.0, 1000.0])
 @pytest.mark.parametrize("case", range(len(CASES)))
@@ -56,9 +71,10 @@ def test_large_cfl_parity(torch_cuda, molt, oracle_mod, case, cfl, dtype):
     torch = torch_cuda
     shape, h, bc = CASES[case]
     da = _dirichlet_axes(bc, 2)
-    v = W.random_field(shape, seed=200 + case, dirichlet_axes=da)
-    w = W.random_field(shape, seed=210 + case, dirichlet_axes=da)
-    vd = dev(torch, v, dtype)
+    r = W.random_field(shape, seed=200 + case, dirichlet_axes=da)
+    v = _smooth(shape, 200 + case)
+    w = _smooth(shape, 210 + case)
+    rd, vd = dev(torch, r, dtype), dev(torch, v, dtype)
     out = torch.empty_like(vd)
     stream = torch.cuda.Stream()
     for P in (1, 2, 3):
@@ -68,9 +84,16 @@ def test_large_cfl_parity(torch_cuda, molt, oracle_mod, case, cfl, dtype):
         pb = oracle_mod.Problem(shape, h, bc, alpha)
         if P == 2:
             for ax, nm in ((0, "x"), (1, "y")):
-                plan.apply("d_" + nm, vd, out)
+                plan.apply("d_" + nm, rd, out)
                 torch.cuda.synchronize()
-                check("CFL %g D_%s %s" % (cfl, nm, shape), host(out), pb.Dg(v, ax), dtype)
+                # a periodic line shorter than the decay length (nu n < 1)
+                # couples every node to every other: the closure's factor
+                # 1 / (1 - e^{-nu n}) multiplies the rounding of the sweep
+                n_ax = shape[1 - ax]
+                per = (list(bc) if np.ndim(bc) else [bc] * 2)[ax] == 1
+                amp = 1.0 / -np.expm1(-plan.info["nu"][ax] * n_ax) if per else 1.0
+                check("CFL %g D_%s random %s (closure factor %.2f)" % (cfl, nm, shape, amp),
+                      host(out), pb.Dg(r, ax), dtype, TOL[dtype] * max(1.0, amp))
         plan.apply("rhs", vd, out)
         torch.cuda.synchronize()
         check("CFL %g rhs P=%d %s" % (cfl, P, shape), host(out), pb.rhs(v, P, beta), dtype)
