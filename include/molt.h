@@ -223,6 +223,22 @@ mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
                           const void *const *u_curr, void *const *u_next, int count,
                           void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one step
+ * like mol_step(plan, u_prev, u_curr, u_next, stream) for the plan desc
+ * describes, with no plan and no device allocation.  The step's workspace
+ * fields and carry table live in one device array of the library, of
+ * mol_step_static_max_bytes() bytes (64 MiB; each GPU holds its own copy
+ * until the process ends); a step that needs more returns MOL_E_INVALID and
+ * says how much, a mask returns MOL_E_UNSUPPORTED.  Calls on one GPU share the
+ * array: calls that overlap in time on one GPU (several streams or host
+ * threads) race and must be serialised by the caller.  The schedule and launch
+ * configurations are those of mol_plan_create's plan of desc, so the result
+ * is bitwise that of mol_step.  Host work per call: building that schedule. */
+size_t mol_step_static_max_bytes(void);
+mol_status mol_step_static(const mol_desc *desc, const void *u_prev, const void *u_curr,
+                           void *u_next, void *stream);
+
 /* ---- Request server (serving many independent solves on one GPU) ----
  *
  * Continuous batching of independent requests of differing n, P, CFL and

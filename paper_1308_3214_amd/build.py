@@ -16,7 +16,7 @@ SOURCES = (["molt_sweep_%s%s_n%d.hip" % (k, t, n) for k in ("x", "s") for t in (
            + ["molt_sweep_p%s_p%d.hip" % (t, n) for t in ("32", "64") for n in (1, 2, 4)]
            + ["molt_sweep_e%s_n%d.hip" % (t, n) for t in ("32", "64") for n in (4, 16)]
            + ["molt_sweep_yy32.hip", "molt_kernels.hip", "molt_plan.cpp", "molt_masked.cpp", "molt_seg.hip",
-              "molt_server.cpp"])
+              "molt_server.cpp", "molt_static.hip"])
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed-FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -85,6 +85,8 @@ _lib.mol_step_source.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mol_solve_source.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.mol_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
 _lib.mol_solve_prepare.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
+_lib.mol_step_static.argtypes = [ctypes.POINTER(_Desc), _vp, _vp, _vp, _vp]
+_lib.mol_step_static_max_bytes.restype = ctypes.c_size_t
 _lib.mol_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
 _lib.mol_step_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                 ctypes.POINTER(_vp), ctypes.c_int, _vp]
@@ -125,14 +127,15 @@ _lib.mol_server_last_error.restype = ctypes.c_char_p
 for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
            "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
            "mol_step_source", "mol_solve_source",
-           "mol_solve", "mol_solve_prepare", "mol_apply", "mol_step_batch", "mol_server_create",
+           "mol_solve", "mol_solve_prepare", "mol_step_static", "mol_apply", "mol_step_batch",
+           "mol_server_create",
            "mol_server_create_ex",
            "mol_server_destroy", "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
            "mol_workspace_bytes", "mol_start", "mol_step", "mol_step_source", "mol_solve",
-           "mol_solve_prepare", "mol_solve_source",
+           "mol_solve_prepare", "mol_step_static", "mol_step_static_max_bytes", "mol_solve_source",
            "mol_step_batch",
            "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
            "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error",
@@ -428,6 +431,21 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def step_static(u_prev, u_curr, u_next, shape, h, stream=None, **kw):
+    """One step that allocates no device memory (mol_step_static): the plan of
+    make_desc(shape, h, **kw), workspace in the library's static array."""
+    import torch
+    d, keep = make_desc(shape, h, **kw)
+    want = torch.float64 if d.dtype == F64 else torch.float32
+    for t in (u_prev, u_curr, u_next):
+        if not isinstance(t, torch.Tensor) or t.dtype != want or not t.is_cuda \
+                or tuple(t.shape) != tuple(int(x) for x in shape) or not t.is_contiguous():
+            raise ValueError("expected contiguous %s CUDA tensors of shape %s" % (want, tuple(shape)))
+    _check(_lib.mol_step_static(ctypes.byref(d), ctypes.c_void_p(u_prev.data_ptr()),
+                                ctypes.c_void_p(u_curr.data_ptr()), ctypes.c_void_p(u_next.data_ptr()),
+                                _stream(stream)))
 
 
 def step_batch(plans, u_prev, u_curr, u_next, stream=None):
