@@ -51,7 +51,11 @@ typedef enum {
     MOL_E_DEVICE = 5       /* a HIP call or kernel launch failed */
 } mol_status;
 
-typedef enum { MOL_BC_DIRICHLET = 0, MOL_BC_PERIODIC = 1 } mol_bc;
+/* Boundary type of an axis.  MOL_BC_NEUMANN (1D plans only): the end nodes
+ * are unknowns, the slope u_x is prescribed there (zero with mol_step, data
+ * with mol_step_bdata); Sec. 3.2, boundary data of the recursive
+ * convolutions. */
+typedef enum { MOL_BC_DIRICHLET = 0, MOL_BC_PERIODIC = 1, MOL_BC_NEUMANN = 2 } mol_bc;
 typedef enum { MOL_F64 = 0, MOL_F32 = 1 } mol_dtype;
 
 enum {
@@ -176,6 +180,28 @@ mol_status mol_step(mol_plan *plan, const void *u_prev, const void *u_curr, void
 mol_status mol_step_source(mol_plan *plan, const void *u_prev, const void *u_curr, void *u_next,
                            const void *s_prev, const void *s_curr, const void *s_next,
                            void *stream);
+
+/* One step of the 1D scheme (eq. update_P) with time-dependent boundary data
+ * (Sec. 3.2, boundary conditions for the recursive convolutions).  Each
+ * application of D within D^p needs at each end the shape of its input in the
+ * end cell and what L^{-1} of its input must satisfy there; both are space
+ * derivatives of u at the end, which the wave equation gives from the data by
+ * inverse Lax-Wendroff, (d_xx)^j u = (d_tt / c^2)^j u, truncated at j <= P.
+ *   Dirichlet plans (u(a, t) = u_L(t), u(b, t) = u_R(t)): the curvature of the
+ *   input in the end cell and the value of L^{-1} at the end (even
+ *   derivatives).  The end nodes of u_curr must hold u_L(t_n) and u_R(t_n);
+ *   those of u_next receive u_L(t_{n+1}) and u_R(t_{n+1}).
+ *   Neumann plans (u_x(a, t) = g_L(t), u_x(b, t) = g_R(t)): the slope of the
+ *   input at the end (the end cell's quadratic passes through the end node
+ *   and its neighbour with that slope) and the slope of L^{-1} at the end (odd
+ *   derivatives); every node is updated.
+ * bdata: HOST array of 2 (P + 2) doubles: d_t^{2j} of the data at a (u_L or
+ * g_L) at t_n for j = 0..P, then u_L(t_{n+1}) (ignored for Neumann); the same
+ * for b.  With zero data this is mol_step.  1D Dirichlet or Neumann plans,
+ * else MOL_E_UNSUPPORTED.  Aliasing as mol_step.  Asynchronous on stream
+ * (bdata is read before the call returns). */
+mol_status mol_step_bdata(mol_plan *plan, const void *u_prev, const void *u_curr, void *u_next,
+                          const double *bdata, void *stream);
 
 /* nsteps >= 0 steps of the three-level scheme (eq. Full_2D; in 1D eq.
  * update_P) in place: on entry (u_prev_io, u_curr_io) = (u^{n-1}, u^n), on

@@ -1,6 +1,8 @@
 """Build libmolt.so (HIP for gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import fcntl
+import hashlib
 import os
 import subprocess
 import sys
@@ -23,40 +25,63 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wno-unused-command-line-argument"]
 
 
-def _newest_header() -> float:
-    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".inc"))]
-    hs.append(os.path.join(HERE, "..", "include", "molt.h"))
-    return max(os.path.getmtime(h) for h in hs)
+def _inputs_digest(src: str) -> str:
+    """Digest of what an object is compiled from: the source, every header
+    of the library, the public header and the flags."""
+    h = hashlib.sha256()
+    h.update(" ".join(FLAGS).encode())
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".h", ".inc")))
+    for path in [os.path.join(CSRC, src)] + [os.path.join(CSRC, f) for f in names] + \
+            [os.path.join(HERE, "..", "include", "molt.h")]:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    if incremental and os.path.exists(obj):
-        t = os.path.getmtime(obj)
-        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
-            return obj
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    stamp = obj + ".stamp"
+    digest = _inputs_digest(src)
+    if incremental and os.path.exists(obj) and os.path.exists(stamp):
+        with open(stamp) as f:
+            if f.read().strip() == digest:
+                return obj
+    if os.path.exists(stamp):
+        os.remove(stamp)
+    tmp = obj + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed for " + src)
+    os.replace(tmp, obj)
+    # the digest was taken before the compile: a source changed meanwhile
+    # leaves a stale stamp, and the next incremental build compiles again
+    with open(stamp, "w") as f:
+        f.write(digest + "\n")
     return obj
 
 
 def build(jobs: int = 8, out: str = OUT, incremental: bool = False) -> str:
-    """Compile every source (incremental: only those older than their object
-    or than a header) and link the library."""
+    """Compile every source (incremental: only those whose source, headers or
+    flags differ from what their object was compiled from) and link the
+    library.  One build at a time: a second one waits for the first, so that
+    no object is compiled from one state of the headers and linked with
+    objects of another."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs, "-ldl"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("link failed")
-    os.replace(tmp, out)
+    with open(os.path.join(BUILD, ".lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs, "-ldl"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("link failed")
+        os.replace(tmp, out)
     return out
 
 

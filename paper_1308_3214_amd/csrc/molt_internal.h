@@ -27,6 +27,7 @@ constexpr int MAXO = 3;   // outputs per launch
 // and [A, B] = K [E^R_0, E^L_M] (Dirichlet or periodic closure).
 struct DirCoef {
     double nu, d, g, w2;
+    double w0, w1;      // weights of the I recurrences: J^L_p = w0 v_p + w1 v_{p-1} + w2 (curvature)
     double K[2][2];
     int periodic;
     int64_t n;          // nodes on the line
@@ -44,6 +45,14 @@ struct SweepOp {
     double mS[MAXS][MAXF] = {};
     double mOF[MAXO][MAXF] = {};
     double mOD[MAXO][MAXS] = {};
+    int kform[MAXS] = {};  // 1: combination k is swept for L^{-1} (the I recurrences), else D
+    // x sweeps of 1D lines with boundary data, one combination.  Dirichlet
+    // (bmode = 1): L^{-1} targets and data curvatures (times h^2) at the two
+    // ends, and the values the projected outputs take at the end nodes.
+    // Neumann (bmode = 2): bt = (S_a, -S_b) / alpha for the slopes S that
+    // L^{-1} takes at the ends, bk = 2 h times the slopes of the input
+    int bmode = 0;
+    double bt[2] = {}, bk[2] = {}, bend[2] = {};
     int proj = 0;        // write 0 on every Dirichlet boundary node of the outputs
     int chain = 0;       // x sweeps: also write D_x(out_0) to buffer ochain
     int ochain = -1;

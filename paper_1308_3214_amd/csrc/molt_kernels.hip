@@ -61,11 +61,22 @@ void fill_common(KArgs<T> &k, const SweepOp &op, const DirCoef &dc, const void *
     for (int i = 0; i < MAXO; ++i) k.o[i] = i < op.no ? static_cast<T *>(optr[i]) : nullptr;
     for (int s = 0; s < MAXS; ++s)
         for (int f = 0; f < MAXF; ++f) k.mS[s][f] = (T)op.mS[s][f];
+    // a combination swept for L^{-1} comes back as -(I^L + I^R + closure):
+    // its output weights carry the sign
     for (int o = 0; o < MAXO; ++o) {
         for (int f = 0; f < MAXF; ++f) k.mOF[o][f] = (T)op.mOF[o][f];
-        for (int s = 0; s < MAXS; ++s) k.mOD[o][s] = (T)op.mOD[o][s];
+        for (int s = 0; s < MAXS; ++s) k.mOD[o][s] = (T)(op.kform[s] ? -op.mOD[o][s] : op.mOD[o][s]);
         k.mV[o] = (T)op.mV[o];
     }
+    for (int s = 0; s < MAXS; ++s) k.kform[s] = op.kform[s];
+    k.bmode = op.bmode;
+    for (int i = 0; i < 2; ++i) {
+        k.bt[i] = (T)op.bt[i];
+        k.bk[i] = (T)op.bk[i];
+        k.bend[i] = (T)op.bend[i];
+    }
+    k.w0 = (T)dc.w0;
+    k.w1 = (T)dc.w1;
     for (int f = 0; f < MAXF; ++f) k.mE1[f] = (T)op.mE1[f];
     k.nf = op.nf;
     k.proj = op.proj;
@@ -171,6 +182,7 @@ void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *con
         k.dS = (T)exp(-dc.nu * c.S);
         k.dBlk = k.dS;
         k.dT = (T)exp(-dc.nu * (double)WS);
+        k.tile_rows = (int)WS;
         key.cls = 4;
         key.cfg = cfg[0] - NSCFG - NPCFG;
         key.nfb = op.nf <= 4 ? 4 : 16;
@@ -269,7 +281,9 @@ bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64
 {
     const int dir = op.dir, nf = op.nf, ns = op.ns, no = op.no;
     const size_t es = fp64 ? 8 : 4;
+    const bool kf = op.kform[0] || op.kform[1];
     if (op.yy) {
+        if (kf) return false;
         // chained strided sweeps (FP32): at most 3 fields, one swept
         // combination, field terms only in the last output, a walk whose
         // data rows next to a strip fit one sub-tile, lines of at least two
@@ -290,7 +304,8 @@ bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64
         if ((dc.n + 3 * WS + 8) * ls * (int64_t)es + 64 * (int64_t)es >= ((int64_t)1 << 31)) return false;
         return true;
     }
-    if (!((ns == 1 && (no == 1 || no == 2)) || (ns == 2 && (no == 2 || no == 3)))) return false;
+    // (ns, no) in {(1, 1), (1, 2), (2, 1), (2, 2), (2, 3)}; (2, 1) not for the strip kernel
+    if (!((ns == 1 && (no == 1 || no == 2)) || (ns == 2 && (no >= 1 && no <= 3)))) return false;
     if (dir == 0) {
         if (cfg[0] < 0 || cfg[0] >= NXCFG) return false;
         const XCfg c = kXCfg[cfg[0]];
@@ -311,9 +326,16 @@ bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64
         if (WS < EXACT_MIN_TILE) return false;
         return true;
     }
+    if (cfg[0] < NSCFG && kf) {
+        // tiles joined by halo sums carry the D recurrences only: a line
+        // swept for L^{-1} fits one tile (else the exact two-pass sweep)
+        const SCfg c = kSCfg[cfg[0]];
+        if (dc.n > (int64_t)c.S * c.W) return false;
+    }
     if (cfg[0] >= NSCFG) {
-        // pipelined strips: at most 4 fields, sub-tiles at least as tall as
-        // the halo and lines of at least two sub-tiles per strip
+        // pipelined strips (D sweeps only): at most 4 fields, sub-tiles at
+        // least as tall as the halo and lines of at least two sub-tiles per strip
+        if (kf || (ns == 2 && no == 1)) return false;
         const PCfg c = kPCfg[cfg[0] - NSCFG];
         const int64_t WS = (int64_t)c.S * c.W;
         if (nf < 1 || nf > 4) return false;
@@ -379,6 +401,17 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
     }
     const int regs = (2 * ns + no) * (fp64 ? 2 : 1);
     const int tcfg = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
+    if (op.kform[0] || op.kform[1]) {
+        // L^{-1} sweeps: one tile, else the exact two-pass sweep
+        cfg[0] = tcfg;
+        if (config_valid(g, dc, op, fp64, cfg)) return 0;
+        cfg[0] = 0;
+        if (config_valid(g, dc, op, fp64, cfg)) return 0;
+        cfg[0] = NSCFG + NPCFG + (tcfg == 0 ? 0 : 1);
+        if (config_valid(g, dc, op, fp64, cfg)) return 0;
+        cfg[0] = NSCFG + NPCFG;
+        return config_valid(g, dc, op, fp64, cfg) ? 0 : -1;
+    }
     // carries longer than half a tile (small nu): the tile kernel's halo sums
     // would read more than the tile itself; the exact two-pass sweep of the
     // same tile shape reads the tile twice, whatever the carry length
@@ -431,7 +464,10 @@ bool sweep_prepare(const SweepOp &op, const Geom &g, const DirCoef &dc, bool fp6
                    const void *const *fptr, void *const *optr, const int *cfg, void *args,
                    SweepKey &key, int64_t &blocks)
 {
-    if (!config_valid(g, dc, op, fp64, cfg) || config_exact(op, cfg)) return false;
+    // batched tables hold D sweeps of one launch each
+    if (!config_valid(g, dc, op, fp64, cfg) || config_exact(op, cfg) || op.kform[0] || op.kform[1] ||
+        op.bmode)
+        return false;
     if (fp64) {
         KArgs<double> k;
         prep_t<double>(op, g, dc, fptr, optr, cfg, k, key, blocks);

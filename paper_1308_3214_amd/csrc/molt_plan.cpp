@@ -144,13 +144,37 @@ int halo_for(double nu, bool fp64)
     return K > 1e9 ? 1000000000 : (int)K;
 }
 
-DirCoef make_dircoef(double nu, int64_t n, bool periodic, bool fp64)
+// weights of the I recurrences, w0 = 1/2 - g and w1 = g - d/2 (g = (1 - d) /
+// (2 nu)): series below nu = 1, where the differences cancel
+//   w0 = (1/2) sum_{k>=1} (-1)^(k+1) nu^k / (k+1)!
+//   w1 = (1/2) sum_{k>=1} (-1)^(k+1) k nu^k / (k+1)!
+void w01_of(double nu, double &w0, double &w1)
+{
+    if (nu < 1.0) {
+        double s0 = 0.0, s1 = 0.0, t = 1.0;   // t = nu^k / (k+1)!
+        for (int k = 1; k < 40; ++k) {
+            t *= nu / (double)(k + 1);
+            const double sg = (k % 2) ? 1.0 : -1.0;
+            s0 += sg * t;
+            s1 += sg * (double)k * t;
+        }
+        w0 = 0.5 * s0;
+        w1 = 0.5 * s1;
+        return;
+    }
+    const double g = -std::expm1(-nu) / (2.0 * nu);
+    w0 = 0.5 - g;
+    w1 = g - 0.5 * std::exp(-nu);
+}
+
+DirCoef make_dircoef(double nu, int64_t n, bool periodic, bool fp64, bool neumann = false)
 {
     DirCoef c{};
     c.nu = nu;
     c.d = std::exp(-nu);
     c.g = -std::expm1(-nu) / (2.0 * nu);
     c.w2 = w2_of(nu);
+    w01_of(nu, c.w0, c.w1);
     c.periodic = periodic ? 1 : 0;
     c.n = n;
     c.halo = halo_for(nu, fp64);
@@ -158,6 +182,15 @@ DirCoef make_dircoef(double nu, int64_t n, bool periodic, bool fp64)
         const double f = c.d / (-std::expm1(-nu * (double)n));
         c.K[0][0] = 0.0; c.K[0][1] = f;
         c.K[1][0] = f;   c.K[1][1] = 0.0;
+    } else if (neumann) {
+        // slopes imposed: (-1, mu; -mu, 1) (A, B) = (-r0, r1) on the end
+        // residuals the sweep forms (r0 = I^R(a) - S_a / alpha,
+        // r1 = I^L(b) + S_b / alpha)
+        const double L = nu * (double)(n - 1);
+        const double mu = std::exp(-L);
+        const double inv = 1.0 / (-std::expm1(-2.0 * L));
+        c.K[0][0] = inv;       c.K[0][1] = mu * inv;
+        c.K[1][0] = mu * inv;  c.K[1][1] = inv;
     } else {
         const double L = nu * (double)(n - 1);       // alpha * (b - a)
         const double mu = std::exp(-L);
@@ -201,7 +234,8 @@ void uniform_config(const mol_plan_ &pl, const SweepOp &op, int *cfg)
 }
 
 bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
-                   const std::vector<OutSpec> &outs, int proj, int chain_buf)
+                   const std::vector<OutSpec> &outs, int proj, int chain_buf,
+                   const std::vector<int> &kf)
 {
 
         const int ns = (int)combos.size(), no = (int)outs.size();
@@ -220,6 +254,22 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
         op.proj = proj;
         op.chain = chain_buf >= 0 ? 1 : 0;
         op.ochain = chain_buf;
+        for (int k = 0; k < ns && k < (int)kf.size(); ++k) op.kform[k] = kf[k] ? 1 : 0;
+        if (op.chain && (op.kform[0] || op.kform[1])) {
+            err = "internal: chained sweeps sweep for D";
+            return false;
+        }
+        if (pl.neumann) {
+            // the sweep closes each line by the slopes at its ends (zero
+            // data here; mol_step_bdata sets them per step); every node is
+            // an unknown, nothing is projected
+            if (ns != 1 || op.kform[0] || op.chain) {
+                err = "Neumann lines take one D sweep per launch";
+                return false;
+            }
+            op.bmode = 2;
+            op.proj = 0;
+        }
         std::vector<int> fields;
         auto fid = [&](int b) -> int {
             for (size_t i = 0; i < fields.size(); ++i)
@@ -263,13 +313,14 @@ bool Builder::emit(Program &prog, int dir, const std::vector<Lin> &combos,
                     else o0.push_back(t);
                 }
                 bool ok = true;
-                if (!o0.empty()) ok = ok && emit(prog, dir, {combos[0]}, o0, proj);
-                if (!o1.empty()) ok = ok && emit(prog, dir, {combos[1]}, o1, proj);
+                if (!o0.empty()) ok = ok && emit(prog, dir, {combos[0]}, o0, proj, -1, {op.kform[0]});
+                if (!o1.empty()) ok = ok && emit(prog, dir, {combos[1]}, o1, proj, -1, {op.kform[1]});
                 return ok;
             }
             if (no > 1) {
                 bool ok = true;
-                for (const OutSpec &o : outs) ok = ok && emit(prog, dir, combos, {o}, proj);
+                for (const OutSpec &o : outs)
+                    ok = ok && emit(prog, dir, combos, {o}, proj, -1, {op.kform[0], op.kform[1]});
                 return ok;
             }
             err = "no kernel configuration fits this line length";
@@ -401,6 +452,94 @@ bool build_rhs_1d(Builder &b, Program &prog, int u, const std::vector<FinalOut> 
         acc = acc + lin(w[p], b.Ap(p));
     }
     return b.emit(prog, 0, {lin(w[P - 1])}, finals(fo, acc, b.Ap(P)), 1);
+}
+
+// 2D rectangles at small nu: the stage schedule of Table 2 with
+//   C v = D_x(K_y v) + K_x(D_y v),   D v = D_x(K_y v) + D_y v   (K = L^{-1}),
+// the same operators as eqs. C_def_ADI, D_def_ADI on a rectangle (the
+// directional operators commute), written so that no term cancels: for data
+// that varies on the grid scale L^{-1} is small where nu is small, and the
+// D-form C v = D_x(v - 2 D_y v) + D_y v would be a difference of order-one
+// terms.  One y launch per input sweeps it for D_y and for K_y; one x launch
+// per new term sweeps K_y v for D_x and D_y v for K_x.
+bool build_rhs_box_k(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo)
+{
+    const int P = b.pl.desc.P;
+    std::vector<int> v{u};
+    int accbuf = -1;
+    for (int p = 1; p <= P; ++p) {
+        const int nin = (int)v.size();
+        std::vector<int> y(nin), k(nin);
+        for (int j = 0; j < nin; ++j) {
+            y[j] = b.new_ws();
+            k[j] = b.new_ws();
+            OutSpec oy{}, ok{};
+            oy.buf = y[j];
+            oy.dc[0] = 1.0;
+            ok.buf = k[j];
+            ok.dc[1] = 1.0;
+            if (!b.emit(prog, 1, {lin(v[j]), lin(v[j])}, {oy, ok}, 0, -1, {0, 1})) return false;
+        }
+        // terms: D_x(g) + K_x(gk) + h
+        struct KT { Lin g, gk, h; };
+        std::vector<KT> t;
+        for (int j = 0; j < nin; ++j) t.push_back({lin(k[j]), lin(y[j]), Lin{}});
+        if (p >= 2) t.push_back({lin(k[nin - 1]), Lin{}, lin(y[nin - 1])});
+        const int nt = (int)t.size();
+        Lin acc_in;
+        if (p == 2) acc_in = lin(v[0], b.coef(1, 1));
+        else if (p >= 3) acc_in = lin(accbuf);
+        if (p == P) {
+            Lin gs, gks, hs = acc_in;
+            for (int j = 0; j < nt; ++j) {
+                const double c = b.coef(p, p - j);
+                gs = gs + c * t[j].g;
+                gks = gks + c * t[j].gk;
+                hs = hs + c * t[j].h;
+            }
+            std::vector<OutSpec> outs;
+            for (const FinalOut &f : fo) {
+                OutSpec o{};
+                o.buf = f.buf;
+                o.elem = f.elem + f.r * hs;
+                o.dc[0] = f.r;
+                o.dc[1] = gks.empty() ? 0.0 : f.r;
+                outs.push_back(o);
+            }
+            if (gks.empty()) return b.emit(prog, 0, {gs}, outs, 1);
+            return b.emit(prog, 0, {gs, gks}, outs, 1, -1, {0, 1});
+        }
+        std::vector<int> nv(nt);
+        const bool need_acc = (P >= 3);
+        const int newacc = need_acc ? b.new_ws() : -1;
+        Lin acc_done = acc_in;
+        for (int j = 0; j < nt; ++j) {
+            nv[j] = b.new_ws();
+            const double c = b.coef(p, p - j);
+            const bool two = !t[j].gk.empty();
+            OutSpec o{};
+            o.buf = nv[j];
+            o.elem = t[j].h;
+            o.dc[0] = 1.0;
+            o.dc[1] = two ? 1.0 : 0.0;
+            std::vector<OutSpec> outs{o};
+            if (j + 1 == nt && need_acc) {
+                OutSpec a{};
+                a.buf = newacc;
+                a.elem = acc_done + c * t[j].h;
+                a.dc[0] = c;
+                a.dc[1] = two ? c : 0.0;
+                outs.push_back(a);
+            }
+            const bool okj = two ? b.emit(prog, 0, {t[j].g, t[j].gk}, outs, 0, -1, {0, 1})
+                                 : b.emit(prog, 0, {t[j].g}, outs, 0);
+            if (!okj) return false;
+            acc_done = acc_done + lin(nv[j], c);
+        }
+        v = nv;
+        accbuf = newacc;
+    }
+    return true;
 }
 
 // 2D / 3D rectangles and boxes: stage schedule of Table 2; each application of
@@ -603,6 +742,7 @@ bool build_rhs(Builder &b, Program &prog, int u, const std::vector<FinalOut> &fo
         return build_rhs_masked(b, prog, u, fo);
     }
     if (b.pl.geom.ndim == 1) return build_rhs_1d(b, prog, u, fo);
+    if (b.pl.kmode) return build_rhs_box_k(b, prog, u, fo);
     return build_rhs_box(b, prog, u, fo);
 }
 
@@ -619,12 +759,18 @@ bool build_apply(Builder &b, Program &prog, int op)
             b.err = "operator direction not present";
             return false;
         }
+        if (pl.masked) return build_apply_masked(b, prog, op);
+        // L^{-1} by its own recurrences, D by the difference-driven ones;
+        // on Neumann lines L^{-1} v = v - D v
         OutSpec o{};
         o.buf = B_OUT;
-        o.dc[0] = (op <= MOL_OP_LINV_Z) ? -1.0 : 1.0;
-        if (op <= MOL_OP_LINV_Z) o.elem = lin(B_IN);   // L^{-1} = 1 - D
-        if (pl.masked) return build_apply_masked(b, prog, op);
-        return b.emit(prog, dir, {lin(B_IN)}, {o}, 1);
+        o.dc[0] = 1.0;
+        if (pl.neumann && op <= MOL_OP_LINV_Z) {
+            o.elem = lin(B_IN);
+            o.dc[0] = -1.0;
+            return b.emit(prog, dir, {lin(B_IN)}, {o}, 1);
+        }
+        return b.emit(prog, dir, {lin(B_IN)}, {o}, 1, -1, {op <= MOL_OP_LINV_Z ? 1 : 0});
     }
     if (pl.masked) return build_apply_masked(b, prog, op);
     if (op == MOL_OP_RHS) return build_rhs(b, prog, B_IN, {{B_OUT, Lin{}, 1.0}});
@@ -640,6 +786,25 @@ bool emit_CD(Builder &b, Program &prog, bool isC, int in, int out)
         o.buf = out;
         o.dc[0] = 1.0;
         return b.emit(prog, 0, {lin(in)}, {o}, 1);
+    }
+    if (nd == 2 && b.pl.kmode) {
+        // C = D_x(K_y in) + K_x(D_y in), D = D_x(K_y in) + D_y in
+        const int y = b.new_ws(), k = b.new_ws();
+        OutSpec oy{}, ok{};
+        oy.buf = y;
+        oy.dc[0] = 1.0;
+        ok.buf = k;
+        ok.dc[1] = 1.0;
+        if (!b.emit(prog, 1, {lin(in), lin(in)}, {oy, ok}, 0, -1, {0, 1})) return false;
+        OutSpec f{};
+        f.buf = out;
+        f.dc[0] = 1.0;
+        if (isC) {
+            f.dc[1] = 1.0;
+            return b.emit(prog, 0, {lin(k), lin(y)}, {f}, 1, -1, {0, 1});
+        }
+        f.elem = lin(y);
+        return b.emit(prog, 0, {lin(k)}, {f}, 1);
     }
     if (nd == 2) {
         const int y = b.new_ws();
@@ -695,7 +860,7 @@ bool build_step_source(Builder &b, Program &prog)
     } else {
         const double sg = a2 / 12.0;
         elem = elem + lin(B_AUX0, sg) + lin(B_IN, 10.0 * sg) + lin(B_AUX1, sg);
-        if (pl.geom.ndim == 2)
+        if (pl.geom.ndim == 2 && !pl.kmode)
             // C[S^n] folded into the step's own sweeps
             return build_rhs_box(b, prog, B_UCURR, {{B_UNEXT, elem, 1.0}}, -1, B_IN,
                                  -pl.beta * pl.beta * sg);
@@ -767,6 +932,7 @@ std::string tune_op_key(const SweepOp &op)
     std::ostringstream o;
     o << "dir" << op.dir << " nf" << op.nf << " ns" << op.ns << " no" << op.no << " ch" << op.chain;
     if (op.yy) o << " yy";
+    if (op.kform[0] || op.kform[1]) o << " kf" << op.kform[0] << op.kform[1];
     return o.str();
 }
 
@@ -818,8 +984,10 @@ mol_status validate(const mol_desc *d)
         if (a < d->ndim) {
             if (d->n[a] < 3) return fail(MOL_E_INVALID, "every axis needs at least 3 nodes");
             if (!(d->h[a] > 0.0)) return fail(MOL_E_INVALID, "h must be > 0");
-            if (d->bc[a] != MOL_BC_DIRICHLET && d->bc[a] != MOL_BC_PERIODIC)
+            if (d->bc[a] != MOL_BC_DIRICHLET && d->bc[a] != MOL_BC_PERIODIC && d->bc[a] != MOL_BC_NEUMANN)
                 return fail(MOL_E_INVALID, "unknown boundary type");
+            if (d->bc[a] == MOL_BC_NEUMANN && d->ndim != 1)
+                return fail(MOL_E_UNSUPPORTED, "Neumann ends are supported on 1D lines");
         } else if (d->n[a] != 1 && d->n[a] != 0) {
             return fail(MOL_E_INVALID, "unused axes must have n = 1");
         }
@@ -874,9 +1042,13 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
     pl->alpha = pl->beta / (d->c * d->dt);
     for (int a = 0; a < d->ndim; ++a) {
         const double nu = pl->alpha * d->h[a];
-        pl->dc[a] = make_dircoef(nu, g.n[a], d->bc[a] == MOL_BC_PERIODIC, pl->fp64);
+        pl->dc[a] = make_dircoef(nu, g.n[a], d->bc[a] == MOL_BC_PERIODIC, pl->fp64,
+                                 d->bc[a] == MOL_BC_NEUMANN);
     }
     pl->masked = (d->mask != nullptr);
+    pl->neumann = d->ndim == 1 && d->bc[0] == MOL_BC_NEUMANN;
+    pl->kmode = !pl->masked && g.ndim == 2 &&
+                std::min(pl->dc[0].nu, pl->dc[1].nu) < KMODE_NU;
     if (!pl->masked)
         pl->agg_bytes = std::max(exact_agg_bytes(g, 1, pl->fp64), exact_agg_bytes(g, 2, pl->fp64));
     if (pl->masked) {
@@ -896,7 +1068,7 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
     ok = ok && build_rhs(b, pl->inc_step, B_UCURR,
                          {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0}, {B_UPREV, lin(B_UPREV), 1.0}});
     // fused solve programs (2D rectangles, P >= 2)
-    if (ok && !pl->masked && g.ndim == 2 && d->P >= 2) {
+    if (ok && !pl->masked && !pl->kmode && g.ndim == 2 && d->P >= 2) {
         pl->chain_a = b.new_ws();
         OutSpec o{};
         o.buf = pl->chain_a;
@@ -1202,6 +1374,91 @@ mol_status mol_step_source(mol_plan *pl, const void *u_prev, const void *u_curr,
     hipError_t e = run_program(pl, pl->step_src, u_prev, u_curr, u_next, s_curr, nullptr,
                                (hipStream_t)stream, s_prev, s_next);
     return e == hipSuccess ? MOL_OK : dev_err(e, "mol_step_source");
+}
+
+}  // extern "C"
+
+namespace {
+
+double binom_or0(int m, int k) { return (m >= 0 && k >= 0 && m >= k) ? binom(m, k) : 0.0; }
+
+// Data of application p (1..P) of D at one end of a line with boundary data,
+// from U_j = (X^j q)(end), X = d_xx / alpha^2, j = 0..P, where q is u
+// (Dirichlet: values) or u_x (Neumann: slopes): the end value of D^{p-1} q
+// (val), the curvature of D^{p-1} u there (kap, Dirichlet only) and the end
+// value of L^{-1} D^{p-1} q (tgt); D = -X (1 - X)^{-1} and L^{-1} = (1 - X)^{-1}
+// as power series in X, truncated at X^P.
+void ilw_pass(int p, int P, const double *U, double alpha, double &val, double &kap, double &tgt)
+{
+    const double s = (p % 2) ? 1.0 : -1.0;        // (-1)^(p-1)
+    double v = 0.0, k = 0.0, t = 0.0;
+    for (int j = 0; j <= P; ++j) {
+        t += binom_or0(j, p - 1) * U[j];
+        v += (p == 1) ? (j == 0 ? U[j] : 0.0) : binom_or0(j - 1, p - 2) * U[j];
+        k += (p == 1) ? (j == 1 ? U[j] : 0.0) : binom_or0(j - 2, p - 2) * U[j];
+    }
+    val = s * v;
+    kap = s * alpha * alpha * k;
+    tgt = s * t;
+}
+
+}  // namespace
+
+extern "C" {
+
+mol_status mol_step_bdata(mol_plan *pl, const void *u_prev, const void *u_curr, void *u_next,
+                          const double *bdata, void *stream)
+{
+    if (!pl || !u_prev || !u_curr || !u_next || !bdata) return fail(MOL_E_INVALID, "NULL argument");
+    if (u_next == u_curr) return fail(MOL_E_INVALID, "u_next must not overlap u_curr");
+    const bool dir = pl->geom.ndim == 1 && pl->geom.dirichlet[0] != 0;
+    if (pl->masked || !(dir || pl->neumann))
+        return fail(MOL_E_UNSUPPORTED, "boundary data are given for 1D Dirichlet or Neumann plans");
+    const int P = pl->desc.P;
+    Program prog = pl->step;
+    if ((int)prog.size() != P) return fail(MOL_E_UNSUPPORTED, "internal: 1D step program shape");
+    // U_j = (X^j u)(end) = (dt / beta)^{2j} d_t^{2j} (data): even space
+    // derivatives of u (Dirichlet) or of u_x (Neumann) from the data (Sec. 3.2)
+    const double r = 1.0 / ((pl->alpha * pl->desc.c) * (pl->alpha * pl->desc.c));
+    double Ua[16], Ub[16];
+    double rj = 1.0;
+    for (int j = 0; j <= P; ++j) {
+        Ua[j] = bdata[j] * rj;
+        Ub[j] = bdata[P + 2 + j] * rj;
+        rj *= r;
+    }
+    const double h = pl->desc.h[0];
+    for (int p = 1; p <= P; ++p) {
+        SweepOp &op = prog[p - 1].op;
+        if (op.dir != 0 || op.ns != 1) return fail(MOL_E_UNSUPPORTED, "internal: 1D step program shape");
+        double va, vb, ka, kb, ta, tb;
+        ilw_pass(p, P, Ua, pl->alpha, va, ka, ta);
+        ilw_pass(p, P, Ub, pl->alpha, vb, kb, tb);
+        if (dir) {
+            // curvature of D^{p-1} u in the end cells (times h^2) and the
+            // values L^{-1} D^{p-1} u takes at the ends
+            op.bmode = 1;
+            op.bk[0] = ka * h * h;
+            op.bk[1] = kb * h * h;
+            op.bt[0] = ta;
+            op.bt[1] = tb;
+        } else {
+            // slopes of D^{p-1} u at the ends (the end cells' quadratics) and
+            // the slopes L^{-1} D^{p-1} u takes there, as the sweep's closure
+            // reads them
+            op.bmode = 2;
+            op.bk[0] = 2.0 * h * va;
+            op.bk[1] = 2.0 * h * vb;
+            op.bt[0] = ta / pl->alpha;
+            op.bt[1] = -tb / pl->alpha;
+        }
+    }
+    if (dir) {
+        prog.back().op.bend[0] = bdata[P + 1];
+        prog.back().op.bend[1] = bdata[2 * P + 3];
+    }
+    hipError_t e = run_program(pl, prog, u_prev, u_curr, u_next, nullptr, nullptr, (hipStream_t)stream);
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_step_bdata");
 }
 
 mol_status mol_apply(mol_plan *pl, int op, const void *in, void *out, void *stream)

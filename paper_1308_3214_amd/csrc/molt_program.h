@@ -70,6 +70,9 @@ struct mol_plan_ {
     int ginc = -1;
     // masked plans (embedded boundary)
     bool masked = false;
+    // 1D line with Neumann ends: every x sweep runs in boundary-data mode
+    // (zero data unless mol_step_bdata gives some), no projection
+    bool neumann = false;
     molt::SegTable seg[2];
     // y line objects on the transposed grid (x <-> y), swept through
     // transposed copies of a launch's fields (coalesced rows)
@@ -85,9 +88,18 @@ struct mol_plan_ {
     std::vector<std::pair<std::string, int>> tuned;
     // workspace from the stream-ordered allocator (plans of the request server)
     bool async_ws = false;
+    // 2D box plans at small nu: the ADI operator C composed as
+    // D_x(L_y^-1 v) + L_x^-1(D_y v), with L^-1 swept by its own recurrences
+    bool kmode = false;
 };
 
 namespace molt {
+
+// 2D box plans whose smaller nu lies below this compose C from L^{-1} and D
+// sweeps (D_x(L_y^-1 v) + L_x^-1(D_y v)) instead of D sweeps alone: the D-form
+// C of data that varies on the grid scale cancels about 1 / (2 min K^) ~ 3 / nu
+// (60 at this nu) of its leading digits
+constexpr double KMODE_NU = 0.05;
 
 // linear expression over buffers
 typedef std::vector<std::pair<int, double>> Lin;
@@ -134,8 +146,10 @@ struct Builder {
     int new_ws() { return B_WS0 + pl.nws++; }
 
     // one directional launch: combos = swept combinations, outs = outputs
+    // kf[k] = 1: combination k is swept for L^{-1} (else D)
     bool emit(Program &prog, int dir, const std::vector<Lin> &combos,
-              const std::vector<OutSpec> &outs, int proj, int chain_buf = -1);
+              const std::vector<OutSpec> &outs, int proj, int chain_buf = -1,
+              const std::vector<int> &kf = {});
 
     // chained strided launch: v1 = e1 + D s1, y = D v1 along direction dir;
     // output expressions may name the two results through the ids V1 and Y

@@ -62,6 +62,9 @@ struct Req {
     };
     std::vector<Cached> ops[2];
     std::vector<unsigned char> args[2];
+    // launches that cannot share a batched table (line objects of a mask,
+    // L^{-1} sweeps, the two-pass exact sweeps) run one by one in their position
+    bool direct = false;
     hipEvent_t done = nullptr;
     std::string err;
 };
@@ -198,10 +201,11 @@ mol_status admit_batched(mol_server_ *s, Req *r)
         return sfail(MOL_E_DEVICE, "completion event failed");
     // argument sets of the step for both buffer roles (masked plans run their
     // launches directly)
+    r->direct = pl->masked;
     if (!pl->masked) {
         const molt::Program &prog = pl->solve_step.empty() ? pl->step : pl->solve_step;
         const size_t asz = molt::sweep_args_bytes(pl->fp64);
-        for (int par = 0; par < 2; ++par) {
+        for (int par = 0; par < 2 && !r->direct; ++par) {
             void *A = par ? r->d_curr : r->d_prev, *B = par ? r->d_prev : r->d_curr;
             r->args[par].resize(prog.size() * asz);
             for (int k = 0; k < (int)prog.size(); ++k) {
@@ -211,8 +215,10 @@ mol_status admit_batched(mol_server_ *s, Req *r)
                 molt::resolve_op(pl, prog[k], A, B, A, nullptr, nullptr, fp, op);
                 Req::Cached c{k, molt::SweepKey{}, 0, k * asz, asz};
                 if (!molt::sweep_prepare(prog[k].op, pl->geom, pl->dc[prog[k].op.dir], pl->fp64, fp, op,
-                                         prog[k].cfg, r->args[par].data() + c.off, c.key, c.blocks))
-                    return sfail(MOL_E_DEVICE, "no launch configuration for a step launch");
+                                         prog[k].cfg, r->args[par].data() + c.off, c.key, c.blocks)) {
+                    r->direct = true;
+                    break;
+                }
                 r->ops[par].push_back(c);
             }
         }
@@ -256,7 +262,7 @@ bool issue_round(mol_server_ *s)
         mol_plan_ *pl = r->plan;
         const molt::Program &prog = pl->solve_step.empty() ? pl->step : pl->solve_step;
         maxk = std::max(maxk, (int)prog.size());
-        if (pl->masked) {
+        if (r->direct) {
             for (int k = 0; k < (int)prog.size(); ++k) direct.push_back({k, r, &prog[k]});
             continue;
         }

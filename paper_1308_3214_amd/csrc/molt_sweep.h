@@ -82,6 +82,8 @@ struct KArgs {
     int periodic;     // along the sweep
     T d, g, w2;
     T gw;             // g + w2
+    T w0, w1;         // weights of the I recurrences (combinations swept for L^{-1})
+    int kform[MAXS];  // 1: combination k is swept for L^{-1} (I recurrences), else D
     T dS;             // d^S
     T dBlk;           // x: d^{64 S} (one wave of lanes)
     T dpw[6];         // x: d^{S 2^i}, i < 6 (the lane scan's multipliers)
@@ -103,6 +105,14 @@ struct KArgs {
     // nouter x column groups x ntiles x MAXS x 3 x 64 values) and d^(W S)
     T *agg;
     T dT;
+    int tile_rows;    // exact sweeps: rows per tile (W S)
+    // x sweeps of a line with boundary data.  bmode = 1 (Dirichlet): the
+    // L^{-1} targets at the two ends, the data's curvature there times h^2,
+    // and the values the outputs take at the end nodes when projected.
+    // bmode = 2 (Neumann): bt = (S_a, -S_b) / alpha from the slopes S of
+    // L^{-1} at the ends, bk = 2 h times the slopes of the input there
+    int bmode;
+    T bt[2], bk[2], bend[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -344,6 +354,63 @@ __device__ __forceinline__ void seg_recur_fast(const T (&v)[S + 2], T d, T gw, T
     aR = e;
 }
 
+// The recurrences of I^L and I^R themselves (a combination swept for
+// L^{-1} = 1 - D, whose values are small where D is close to 1: formed from D
+// they would lose the digits D and the data share).  Forcing by the local
+// integrals J^L_j = w0 v_j + w1 v_{j-1} + w2 (v_{j+1} - 2 v_j + v_{j-1}) and
+// J^R_j = w0 v_j + w1 v_{j+1} + w2 (...), w0 = 1/2 - g, w1 = g - d/2.  The
+// Dirichlet end fix-ups of the D form apply unchanged (same curvature term),
+// and the closure is the same linear map of the end values; the kernel
+// returns -(sums + carries + closure), which the host's output weights negate.
+template <typename T, int S>
+__device__ __forceinline__ void seg_recur_fast_I(const T (&v)[S + 2], T d, T w0, T w1, T w2, T (&sum)[S],
+                                                 T &aL, T &aR)
+{
+    T e = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const T cv = (v[j + 2] - v[j + 1]) - (v[j + 1] - v[j]);
+        e = d * e + (w0 * v[j + 1] + w1 * v[j] + w2 * cv);
+        sum[j] = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        const T cv = (v[j + 2] - v[j + 1]) - (v[j + 1] - v[j]);
+        e = d * e + (w0 * v[j + 1] + w1 * v[j + 2] + w2 * cv);
+        sum[j] += e;
+    }
+    aR = e;
+}
+// The same for a periodic segment that crosses the line end (nodes beyond M
+// force nothing; values already wrapped).
+template <typename T, int S>
+__device__ __forceinline__ void seg_recur_I(const T (&v)[S + 2], int p0, int M, T d, T w0, T w1, T w2,
+                                            T (&sum)[S], T &aL, T &aR, T &eLM)
+{
+    T e = T(0);
+    eLM = T(0);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int p = p0 + j;
+        const T cv = (v[j + 2] - v[j + 1]) - (v[j + 1] - v[j]);
+        e = d * e + ((p > M) ? T(0) : (w0 * v[j + 1] + w1 * v[j] + w2 * cv));
+        sum[j] = e;
+        if (p == M) eLM = e;
+    }
+    aL = e;
+    e = T(0);
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j) {
+        const int p = p0 + j;
+        const T cv = (v[j + 2] - v[j + 1]) - (v[j + 1] - v[j]);
+        e = d * e + ((p > M) ? T(0) : (w0 * v[j + 1] + w1 * v[j + 2] + w2 * cv));
+        sum[j] += e;
+    }
+    aR = e;
+}
+
 // Dirichlet end nodes inside a segment handled by seg_recur_fast: at node 0 the
 // forcing must be F^L = 0, F^R = g v_1 and at node M F^L = g v_{M-1}, F^R = 0
 // (no curvature at a boundary node); the branch-free forcing is off by
@@ -386,6 +453,48 @@ __device__ __forceinline__ void seg_fix_dirichlet(int p0, int M, T v1, T vM1, T 
         for (int j = 0; j < S; ++j)
             if (j == jm) em = sum[j];     // E^R_M = 0 locally: sum = E^L_M
         eLM = em;
+    }
+}
+
+// End nodes of a line with boundary data (end values v_0 = v(a), v_M = v(b) in
+// the field; ka, kb the curvatures of the end cells' quadratics times h^2:
+// the data's for Dirichlet ends, those the end slopes give for Neumann ends).
+// The recurrences start at the end nodes, E^L_0 = -v_0/2 and E^R_M = -v_M/2,
+// and the end cells take the quadratic through the end node and its inner
+// neighbour with that curvature (the forcing of a node next to a ghost value
+// 2 v_0 - v_1 + ka).  The branch-free forcing (values beyond the line read as 0) is
+// corrected at nodes 0, M and M+1 by the differences below, propagated by
+// powers of d; returns E^L_M (local) in eLM.
+template <typename T, int S>
+__device__ __forceinline__ void seg_fix_bdata(int p0, int M, T v0, T v1, T vM1, T vM, T ka, T kb, T d,
+                                              T g, T w2, T (&sum)[S], T &aL, T &aR, T &eLM)
+{
+    const T gw2 = g + T(2) * w2;
+    const int q[3] = {0, M, M + 1};
+    const T cLq[3] = {-T(0.5) * v0 - w2 * v1 + gw2 * v0, w2 * (kb + T(2) * vM - vM1), -(g + w2) * vM};
+    const T cRq[3] = {w2 * (ka - v1 + T(2) * v0), -T(0.5) * vM + gw2 * vM - w2 * vM1, -w2 * vM};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int jq = q[i] - p0;
+        if (jq < 0 || jq >= S) continue;
+        T pf = cLq[i], pb = cRq[i], lf = T(0), lb = T(0);
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            if (j >= jq) { sum[j] += pf; lf = pf; pf *= d; }
+#pragma unroll
+        for (int j = S - 1; j >= 0; --j)
+            if (j <= jq) { sum[j] += pb; lb = pb; pb *= d; }
+        aL += lf;
+        aR += lb;
+    }
+    // E^R_M is -v_M/2 locally (the forcing beyond M is removed)
+    const int jm = M - p0;
+    if (jm >= 0 && jm < S) {
+        T em = T(0);
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            if (j == jm) em = sum[j];
+        eLM = em + T(0.5) * vM;
     }
 }
 
@@ -436,10 +545,13 @@ __device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A
 // ---------------------------------------------------------------------------
 // D_x of NSW combinations staged in LDS (sm + k*NPAD, padded slots); the D
 // values replace the inputs in place.  Ends with a __syncthreads.
-template <typename T, int S, int WPL, int NSW, bool PER>
+// XM: 0 = D sweeps, 1 = some combination swept for L^{-1}, 2 = a line with
+// boundary data (Dirichlet or Neumann, one combination)
+template <typename T, int S, int WPL, int NSW, bool PER, int XM = 0>
 __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)[MAXS][WPL],
                                              T (*ends)[MAXS], int t, int n)
 {
+    constexpr bool KF = (XM == 1), BD = (XM == 2);
     constexpr int NT = 64 * WPL;
     constexpr int NPAD = NT * (S + 1);
     const int lane = t & 63, wave = t >> 6;
@@ -461,15 +573,30 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
         v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
         if (PER && jm >= 0 && jm < S) v[jm + 2] = sk[0];          // wrap at node M
         if (PER && slow) {
-            seg_recur<T, S>(v, p0, M, false, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+            if (KF && a.kform[k]) seg_recur_I<T, S>(v, p0, M, a.d, a.w0, a.w1, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+            else seg_recur<T, S>(v, p0, M, false, a.d, a.g, a.w2, sum[k], aL[k], aR[k], eLM[k]);
         } else {
-            seg_recur_fast<T, S>(v, a.d, a.gw, a.w2, sum[k], aL[k], aR[k]);
+            if (KF && a.kform[k]) seg_recur_fast_I<T, S>(v, a.d, a.w0, a.w1, a.w2, sum[k], aL[k], aR[k]);
+            else seg_recur_fast<T, S>(v, a.d, a.gw, a.w2, sum[k], aL[k], aR[k]);
             eLM[k] = aL[k];                            // periodic: node M ends its lane
             if (dir_end) {
                 const T v1 = (p0 == 0 && n > 1) ? sk[1] : T(0);
                 const int q = M - 1;
                 const T vM1 = (jm >= 0 && jm < S && q >= 0) ? sk[(q / S) * (S + 1) + (q % S)] : T(0);
-                seg_fix_dirichlet<T, S>(p0, M, v1, vM1, a.d, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+                if (BD) {
+                    // end-cell curvatures times h^2: the data's (bmode 1), or
+                    // those of the quadratics through the end node and its
+                    // neighbour with the given slopes, bk = 2 h slope (bmode 2)
+                    const T v0 = sk[0];
+                    const T vM = sk[(M / S) * (S + 1) + (M % S)];
+                    const bool nm = a.bmode == 2;
+                    const T ka = nm ? T(2) * (v1 - v0) - a.bk[0] : a.bk[0];
+                    const T kb = nm ? T(2) * (vM1 - vM) + a.bk[1] : a.bk[1];
+                    seg_fix_bdata<T, S>(p0, M, v0, v1, vM1, vM, ka, kb, a.d, a.g, a.w2, sum[k], aL[k], aR[k],
+                                        eLM[k]);
+                } else {
+                    seg_fix_dirichlet<T, S>(p0, M, v1, vM1, a.d, a.w2, sum[k], aL[k], aR[k], eLM[k]);
+                }
             }
         }
     }
@@ -519,21 +646,29 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NSW; ++k) {
-        const double er0 = (double)ends[0][k], elm = (double)ends[1][k];
+        T *sk = sm + k * NPAD;
+        double er0 = (double)ends[0][k], elm = (double)ends[1][k];
+        if (BD) {
+            // L^{-1} v takes the targets at the ends: the closure acts on
+            // E^R_0 - (t_a - v_0/2) and E^L_M - (t_b - v_M/2)
+            er0 -= (double)a.bt[0] - 0.5 * (double)sk[0];
+            elm -= (double)a.bt[1] - 0.5 * (double)sk[(M / S) * (S + 1) + (M % S)];
+            __syncthreads();     // every thread has read the end values before any D replaces them
+        }
         const double A = a.K00 * er0 + a.K01 * elm;
         const double B = a.K10 * er0 + a.K11 * elm;
         if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, false);
-        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end);
-        T *sk = sm + k * NPAD;
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end && !BD);
 #pragma unroll
         for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
     }
     __syncthreads();
 }
 
-template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX, int XM = 0>
 __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bid)
 {
+    constexpr bool BD = (XM == 2);
     constexpr int NT = 64 * WPL;
     constexpr int NPAD = NT * (S + 1);
     constexpr int NV = S / VW;
@@ -621,7 +756,8 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
         for (int c = 0; c < VW; ++c) {
             const int e = (i * NT + t) * VW + c;
             const int slot = (e / S) * (S + 1) + (e % S);
-            const bool zero = (e >= n) || (dir_end && (e == 0 || e == M));
+            // (a line with Dirichlet data keeps its end values)
+            const bool zero = (e >= n) || (dir_end && !BD && (e == 0 || e == M));
 #pragma unroll
             for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][i * VW + c];
         }
@@ -629,7 +765,7 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
     __syncthreads();
 
     // ---- phases 2-3: recurrences, scans, closure (D in LDS) ----
-    x_line_sweep<T, S, WPL, NS, PER>(a, sm, wtot, ends, t, n);
+    x_line_sweep<T, S, WPL, NS, PER, XM>(a, sm, wtot, ends, t, n);
 
     // ---- phase 4: epilogue in the coalesced layout ----
 #pragma unroll
@@ -644,12 +780,14 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
 #pragma unroll
             for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
             const bool z = a.proj && (bline || (dir_end && (e == 0 || e == M)));
+            // projected end nodes of a line with Dirichlet data take the data
+            const T zv = BD ? (e == 0 ? a.bend[0] : a.bend[1]) : T(0);
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
                 T r = ev[o][i * VW + c];
 #pragma unroll
                 for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
-                out[o][c] = z ? T(0) : r;
+                out[o][c] = z ? zv : r;
             }
         }
 #pragma unroll
@@ -704,11 +842,13 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
         }
     }
 }
-template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
+// XM = 1: some combination is swept for L^{-1} (the I recurrences); XM = 2: a
+// line with Dirichlet data; XM = 0: D recurrences and homogeneous ends only
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX, int XM = 0>
 __global__ void __launch_bounds__(64 * WPL)
 k_sweep_x(const KArgs<T> a)
 {
-    sweep_x_body<T, S, WPL, NS, NO, VW, PER, NFMAX>(a, blockIdx.x);
+    sweep_x_body<T, S, WPL, NS, NO, VW, PER, NFMAX, XM>(a, blockIdx.x);
 }
 template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX>
 __global__ void __launch_bounds__(64 * WPL)
@@ -935,9 +1075,11 @@ __device__ __forceinline__ void sweep_s_body(const KArgs<T> &a, const int64_t bi
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         if (PER && slow) {
-            seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
+            if (a.kform[k]) seg_recur_I<T, S>(v[k], p0, M, d, a.w0, a.w1, w2, sum[k], aL[k], aR[k], eLM[k]);
+            else seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
         } else {
-            seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
+            if (a.kform[k]) seg_recur_fast_I<T, S>(v[k], d, a.w0, a.w1, w2, sum[k], aL[k], aR[k]);
+            else seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
             eLM[k] = aL[k];
             if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
                 T vM1 = T(0);
@@ -1054,13 +1196,13 @@ k_sweep_s_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first,
 // tiles before it of their own aggregates, each damped by d per node.  Pass 1
 // (MODE 1) sweeps every tile with zero carries in and writes, per column, its
 // forward aggregate TL (E^L at its last row), its backward aggregate TR (E^R
-// at its first row) and, for the tile holding node M, E^L at M (EM).  Pass 2
-// (MODE 2) sweeps every tile again: its wave 0 folds the aggregates into the
-// exact carries entering the tile, cTop = sum_{t'<t} d^{WS (t-1-t')} TL_t' and
-// cBot = sum_{t'>t} d^{WS (t'-t-1)} TR_t', and into the line-end values
-// E^R_0 = sum_t d^{WS t} TR_t and E^L_M = EM + d^{M - s_last + 1} cTop_last, from
-// which the boundary correction (Dirichlet or periodic) is formed as on a
-// line held by one tile.  Nothing is truncated: the cost is one more read of
+// at its first row) and, for the tile holding node M, E^L at M (EM).  A small
+// scan (k_exact_scan, one lane per column) folds the aggregates in place into
+// the exact carries entering every tile, cTop = sum_{t'<t} d^{WS (t-1-t')} TL_t'
+// and cBot = sum_{t'>t} d^{WS (t'-t-1)} TR_t', and into the line-end values
+// E^R_0 = sum_t d^{WS t} TR_t and E^L_M = EM + d^{M - s_last + 1} cTop_last.
+// Pass 2 (MODE 2) sweeps every tile again with those carries and forms the
+// boundary correction (Dirichlet or periodic) as on a line held by one tile.  Nothing is truncated: the cost is one more read of
 // the swept fields instead of halos that grow like 1/nu.
 template <typename T, int S, int W, int NS, int NO, bool PER, int NFMAX, int MODE>
 __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bid)
@@ -1154,9 +1296,11 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         if (PER && slow) {
-            seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
+            if (a.kform[k]) seg_recur_I<T, S>(v[k], p0, M, d, a.w0, a.w1, w2, sum[k], aL[k], aR[k], eLM[k]);
+            else seg_recur<T, S>(v[k], p0, M, false, d, g, w2, sum[k], aL[k], aR[k], eLM[k]);
         } else {
-            seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
+            if (a.kform[k]) seg_recur_fast_I<T, S>(v[k], d, a.w0, a.w1, w2, sum[k], aL[k], aR[k]);
+            else seg_recur_fast<T, S>(v[k], d, a.gw, w2, sum[k], aL[k], aR[k]);
             eLM[k] = aL[k];
             if (dir_end && (p0 == 0 || (jm >= 0 && jm < S))) {
                 T vM1 = T(0);
@@ -1192,27 +1336,15 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
         return;
     }
 
-    // ---- exact carries and line-end values from the aggregates (wave 0) ----
+    // ---- exact carries and line-end values (written by k_exact_scan) ----
     if (wave == 0) {
         const int last = ntiles - 1;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            T e = T(0), cb = T(0);
-            for (int t = last; t >= 0; --t) {
-                if (t == tile) cb = e;
-                e = a.dT * e + tab[((size_t)t * MAXS + k) * (3 * 64) + 64 + lane];
-            }
-            T c = T(0), ct = T(0);
-            for (int t = 0; t < last; ++t) {
-                if (t == tile) ct = c;
-                c = a.dT * c + tab[((size_t)t * MAXS + k) * (3 * 64) + lane];
-            }
-            if (tile == last) ct = c;
-            const T em = tab[((size_t)last * MAXS + k) * (3 * 64) + 128 + lane];
-            carry[0][k][lane] = ct;
-            carry[1][k][lane] = cb;
-            carry[2][k][lane] = e;
-            carry[3][k][lane] = em + expneg<T>(a.nu * (double)(M - last * WS + 1)) * c;
+            carry[0][k][lane] = tab[((size_t)tile * MAXS + k) * (3 * 64) + lane];
+            carry[1][k][lane] = tab[((size_t)tile * MAXS + k) * (3 * 64) + 64 + lane];
+            carry[2][k][lane] = tab[(size_t)k * (3 * 64) + 128 + lane];
+            carry[3][k][lane] = tab[((size_t)last * MAXS + k) * (3 * 64) + 128 + lane];
         }
     }
     __syncthreads();
@@ -1260,6 +1392,58 @@ __global__ void __launch_bounds__(64 * W)
 k_sweep_e(const KArgs<T> a)
 {
     sweep_e_body<T, S, W, NS, NO, PER, NFMAX, MODE>(a, blockIdx.x);
+}
+
+// Between the two passes: one lane per column of one column group (blockIdx.x
+// over outer x column groups) and one combination (blockIdx.y); the tile
+// aggregates are read eight tiles at a time (all loads in flight before the
+// serial recurrences use them) and overwritten in place: TL_t <- cTop_t,
+// TR_t <- cBot_t, slot 2 of tile 0 <- E^R_0, slot 2 of the last tile <- E^L_M
+// (the host requires two tiles or more).
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_exact_scan(const KArgs<T> a)
+{
+    constexpr int U = 8;
+    const int lane = threadIdx.x;
+    const int k = blockIdx.y;
+    const int ntiles = a.ntiles, last = ntiles - 1;
+    T *tab = a.agg + (size_t)blockIdx.x * (size_t)ntiles * (MAXS * 3 * 64) + (size_t)k * (3 * 64) + lane;
+    const size_t tstride = (size_t)MAXS * 3 * 64;
+    const T dT = a.dT;
+    // forward: carries entering each tile from above
+    T c = T(0);
+    for (int t0 = 0; t0 < ntiles; t0 += U) {
+        T x[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) x[i] = (t0 + i < ntiles) ? tab[(size_t)(t0 + i) * tstride] : T(0);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (t0 + i < ntiles) {
+                tab[(size_t)(t0 + i) * tstride] = c;
+                if (t0 + i < last) c = dT * c + x[i];
+            }
+        }
+    }
+    // c is now the carry entering the last tile: E^L at node M from it
+    const int M = (int)a.n - 1;
+    const T em = tab[(size_t)last * tstride + 128];
+    // backward: carries entering each tile from below, and E^R_0
+    T e = T(0);
+    for (int t0 = last; t0 >= 0; t0 -= U) {
+        T x[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) x[i] = (t0 - i >= 0) ? tab[(size_t)(t0 - i) * tstride + 64] : T(0);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (t0 - i >= 0) {
+                tab[(size_t)(t0 - i) * tstride + 64] = e;
+                e = dT * e + x[i];
+            }
+        }
+    }
+    tab[128] = e;
+    tab[(size_t)last * tstride + 128] = em + expneg<T>(a.nu * (double)(M - last * a.tile_rows + 1)) * c;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # status codes / enums (include/molt.h)
 MOL_OK, MOL_E_INVALID, MOL_E_UNSUPPORTED, MOL_E_UNSTABLE, MOL_E_NOMEM, MOL_E_DEVICE = range(6)
-DIRICHLET, PERIODIC = 0, 1
+DIRICHLET, PERIODIC, NEUMANN = 0, 1, 2
 F64, F32 = 0, 1
 ALLOW_UNSTABLE, INCREMENT_FORM, NO_GRAPH, SPLIT_Y, UNIFORM_CONFIG, SYMMETRIC_D = 1, 2, 4, 8, 16, 32
 OPS = {"linv_x": 0, "linv_y": 1, "linv_z": 2, "d_x": 3, "d_y": 4, "d_z": 5, "C": 6, "D": 7, "rhs": 8}
@@ -86,6 +86,7 @@ _lib.mol_solve_source.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctype
 _lib.mol_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
 _lib.mol_solve_prepare.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
 _lib.mol_step_static.argtypes = [ctypes.POINTER(_Desc), _vp, _vp, _vp, _vp]
+_lib.mol_step_bdata.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.mol_step_static_max_bytes.restype = ctypes.c_size_t
 _lib.mol_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
 _lib.mol_step_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -127,7 +128,8 @@ _lib.mol_server_last_error.restype = ctypes.c_char_p
 for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tune_key",
            "mol_profile_step", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info", "mol_start", "mol_step",
            "mol_step_source", "mol_solve_source",
-           "mol_solve", "mol_solve_prepare", "mol_step_static", "mol_apply", "mol_step_batch",
+           "mol_solve", "mol_solve_prepare", "mol_step_static", "mol_step_bdata", "mol_apply",
+           "mol_step_batch",
            "mol_server_create",
            "mol_server_create_ex",
            "mol_server_destroy", "mol_server_submit", "mol_server_poll", "mol_server_result", "mol_server_stats"):
@@ -135,7 +137,8 @@ for _f in ("mol_plan_kernel_configs", "mol_plan_set_kernel_config", "mol_plan_tu
 
 EXPORTS = ("mol_beta_max", "mol_plan_create", "mol_plan_destroy", "mol_plan_get_info",
            "mol_workspace_bytes", "mol_start", "mol_step", "mol_step_source", "mol_solve",
-           "mol_solve_prepare", "mol_step_static", "mol_step_static_max_bytes", "mol_solve_source",
+           "mol_solve_prepare", "mol_step_static", "mol_step_static_max_bytes", "mol_step_bdata",
+           "mol_solve_source",
            "mol_step_batch",
            "mol_apply", "mol_profile_step", "mol_plan_kernel_configs",
            "mol_plan_set_kernel_config", "mol_plan_tune_key", "mol_last_error",
@@ -285,6 +288,18 @@ class Plan:
                                      self._t(G), None if CG is None else self._t(CG),
                                      fa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      _stream(stream)))
+
+    def step_bdata(self, u_prev, u_curr, u_next, da, db, next_a=0.0, next_b=0.0, stream=None):
+        """One 1D step with boundary data (Dirichlet plans: values; Neumann
+        plans: slopes u_x): da, db = even time derivatives d_t^{2j} of the
+        data at a and b at t_n, j = 0..P; next_a, next_b = the Dirichlet data
+        at t_{n+1} (unused for Neumann)."""
+        import numpy as np
+        if len(da) != len(db):
+            raise ValueError("da and db must hold the same number of derivatives")
+        b = np.ascontiguousarray(list(da) + [next_a] + list(db) + [next_b], dtype=np.float64)
+        _check(_lib.mol_step_bdata(self._h, self._t(u_prev), self._t(u_curr), self._t(u_next),
+                                   b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream)))
 
     def solve(self, u_prev, u_curr, nsteps, stream=None):
         _check(_lib.mol_solve(self._h, self._t(u_prev), self._t(u_curr), int(nsteps),

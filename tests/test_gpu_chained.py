@@ -99,9 +99,15 @@ def test_chained_y_sweep(torch_cuda, molt, oracle_mod, case):
 
 
 def test_chained_not_taken(torch_cuda, molt):
-    # short y lines and FP64 keep the split y sweeps
+    # short y lines and FP64 keep the split y sweeps (square cells: nu_y =
+    # nu_x = 0.74, above the threshold of the L^{-1}-composed steps)
     for kw in (dict(shape=(48, 96), dtype="f32"), dict(shape=(1100, 70), dtype="f64")):
         shape = kw.pop("shape")
-        plan = molt.Plan(shape, (1.0 / (shape[1] - 1), 1.0 / (shape[0] - 1)), 0, P=2, cfl=2.0, **kw)
+        plan = molt.Plan(shape, 1.0 / (shape[1] - 1), 0, P=2, cfl=2.0, **kw)
         assert plan.info["kernels_per_step"] == 3, kw
         plan.close()
+    # small nu (0.0047 along y): C from L^{-1} and D sweeps, no chained launch
+    # (4 per step)
+    plan = molt.Plan((1100, 70), (1.0 / 69, 1.0 / 1099), 0, P=2, cfl=20.0, dtype="f32")
+    assert plan.info["kernels_per_step"] == 4
+    plan.close()

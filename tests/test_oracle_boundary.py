@@ -1,0 +1,183 @@
+"""Pins of the oracle's non-homogeneous boundary data (Sec. 3.2, inverse
+Lax-Wendroff: even space derivatives at the boundary from time derivatives of
+the data; Neumann data through the odd derivatives).
+
+Dirichlet:
+* With zero data it is the homogeneous scheme (the oracle's own step).
+* A standing wave cos(w t) cos(k x + phi) on [0, 1] whose boundary values
+  move in time reaches order 2P in time (P = 1, 2, 3) at a spatial step small
+  enough to leave the temporal error alone; with the boundary data taken as
+  plain values (no curvature of the data in the end cells, L^{-1} keeping the
+  data's value at the ends) the same run stays first/second order.
+* pass_data against a direct expansion of the power series in X.
+
+Neumann (linv_slopes, a numpy evaluation of I^L + I^R of its own):
+* closed by end values instead of slopes, it equals the C oracle's L^{-1}
+  with the end-cell curvatures the slopes imply;
+* with zero slopes it equals the C oracle's periodic L^{-1} of the even
+  extension of the line (2M nodes) -- the reflection the zero slope means;
+* quadratic data with their own slopes: exact, W = q + q''/alpha^2;
+* the standing wave with moving slopes u_x(a, t), u_x(b, t) reaches order 2P,
+  and with the slopes taken as plain values it does not.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import boundary as B
+
+
+def _exact(x, t, k, phi):
+    return np.cos(k * t) * np.cos(k * x + phi)
+
+
+def _run(P, dt, n, k=2.5 * np.pi, phi=0.3, T=1.0, ilw=True):
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    beta = float(oracle.beta_max(P))
+    alpha = beta / dt
+    nsteps = int(round(T / dt))
+    a, b = _exact(x, 0.0, k, phi), _exact(x, dt, k, phi)          # analytic u^1
+    for s in range(1, nsteps):
+        t = s * dt
+        da = [(-k * k) ** j * np.cos(k * t) * np.cos(phi) for j in range(P + 1)]
+        db = [(-k * k) ** j * np.cos(k * t) * np.cos(k + phi) for j in range(P + 1)]
+        if not ilw:
+            da = [da[0]] + [0.0] * P
+            db = [db[0]] + [0.0] * P
+        na = np.cos(k * (t + dt)) * np.cos(phi)
+        nb = np.cos(k * (t + dt)) * np.cos(k + phi)
+        a, b = b, B.step_dirichlet(a, b, h, alpha, P, beta, da, db, na, nb, dt)
+    e = b - _exact(x, nsteps * dt, k, phi)
+    return float(np.sqrt(h * np.sum(e * e)))
+
+
+def test_zero_data_is_the_homogeneous_step():
+    n, P = 201, 3
+    h = 1.0 / (n - 1)
+    beta = float(oracle.beta_max(P))
+    alpha = beta / (2.0 * h)
+    g = np.random.default_rng(5)
+    up, uc = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
+    up[0] = up[-1] = uc[0] = uc[-1] = 0.0
+    got = B.step_dirichlet(up, uc, h, alpha, P, beta, [0.0] * (P + 1), [0.0] * (P + 1), 0.0, 0.0,
+                           2.0 * h)
+    ref = oracle.Problem((n,), h, oracle.DIRICHLET, alpha).step(up, uc, P, beta)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("P,rate_min", [(1, 1.9), (2, 3.8), (3, 5.6)])
+def test_moving_boundary_values_reach_order_2P(P, rate_min):
+    # measured: rates 1.91 1.98 2.00 / 3.64 3.89 3.97 / 5.25 5.77 5.94; with
+    # the data as plain values 2.03 2.13 3.13 (P = 2) and 1.99 2.12 3.14
+    # (P = 3), errors 54 and 4200 times larger at dt = 0.0125
+    n = 20001
+    dts = (0.1, 0.05, 0.025, 0.0125)
+    errs = [_run(P, dt, n) for dt in dts]
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    print("P=%d errors %s rates %s" % (P, ["%.3e" % e for e in errs], ["%.2f" % r for r in rates]))
+    assert rates[-1] >= rate_min and rates[-2] >= rate_min - 0.3, rates
+    if P >= 2:
+        plain = [_run(P, dt, n, ilw=False) for dt in dts[1:3]]
+        rp = np.log2(plain[0] / plain[1])
+        print("  data as plain values: errors %s rate %.2f" % (["%.3e" % e for e in plain], rp))
+        assert rp < 2.5
+        assert plain[1] > 10 * errs[2]
+
+
+def test_pass_data_against_series():
+    # the three series against a direct expansion of the operators in X
+    from numpy.polynomial import polynomial as Pl
+    P = 4
+    U = np.array([0.7, -0.3, 0.2, 0.05, -0.01])
+
+    def ser(coefs):          # sum_j coefs[j] U_j, truncated at j <= P
+        c = np.zeros(P + 1)
+        c[:min(len(coefs), P + 1)] = coefs[:P + 1]
+        return float(np.dot(c, U))
+
+    inv1mX = np.ones(P + 1)                       # (1 - X)^-1 = 1 + X + X^2 + ...
+    Dpoly = -Pl.polymul([0, 1], inv1mX)[:P + 1]   # D = -X (1 - X)^-1
+    w = np.array([1.0])                           # D^0
+    for p in range(1, P + 1):
+        val, kap, tgt = B.pass_data(p, U, alpha=2.0)
+        assert abs(val - ser(w)) < 1e-14
+        assert abs(kap - 4.0 * ser(Pl.polymul([0, 1], w))) < 1e-14
+        assert abs(tgt - ser(Pl.polymul(inv1mX, w))) < 1e-14
+        w = Pl.polymul(Dpoly, w)[:P + 1]
+
+
+def test_linv_slopes_dirichlet_closure_is_the_c_oracle():
+    n = 301
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    g = np.random.default_rng(11)
+    for alpha in (0.9, 7.3, 140.0):
+        v = g.uniform(-1, 1, n)
+        pa, pb = g.uniform(-1, 1, 2)
+        ka = 2.0 * (v[1] - v[0] - h * pa) / h ** 2
+        kb = 2.0 * (v[-2] - v[-1] + h * pb) / h ** 2
+        got = B.linv_slopes(v, h, alpha, (pa, pb), (0.2, -0.4), closure="dirichlet")
+        ref = oracle.linv_line(x, v, alpha, (0.2, -0.4, ka, kb))
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), alpha
+
+
+def test_zero_slopes_are_the_even_periodic_extension():
+    n = 257
+    h = 1.0 / (n - 1)
+    g = np.random.default_rng(12)
+    for alpha in (0.5, 9.0, 300.0):
+        v = g.uniform(-1, 1, n)
+        ext = np.concatenate((v, v[-2:0:-1]))           # 2 (n - 1) nodes, period 2 (b - a)
+        ref = oracle.linv_periodic_line(ext, h, alpha)[:n]
+        got = B.linv_slopes(v, h, alpha, (0.0, 0.0), (0.0, 0.0))
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), alpha
+
+
+def test_quadratic_with_its_slopes_is_exact():
+    n = 101
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    q = 0.4 + 1.3 * x - 2.1 * x ** 2
+    qp = 1.3 - 4.2 * x
+    for alpha in (2.0, 30.0, 500.0):
+        got = B.linv_slopes(q, h, alpha, (qp[0], qp[-1]), (qp[0], qp[-1]))
+        assert np.abs(got - (q - 4.2 / alpha ** 2)).max() <= 1e-13
+
+
+def _run_neumann(P, dt, n, k=2.5 * np.pi, phi=0.3, T=1.0, ilw=True):
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    beta = float(oracle.beta_max(P))
+    alpha = beta / dt
+    nsteps = int(round(T / dt))
+    a, b = _exact(x, 0.0, k, phi), _exact(x, dt, k, phi)
+    for s in range(1, nsteps):
+        t = s * dt
+        ga = [(-k * k) ** j * (-k * np.sin(phi)) * np.cos(k * t) for j in range(P + 1)]
+        gb = [(-k * k) ** j * (-k * np.sin(k + phi)) * np.cos(k * t) for j in range(P + 1)]
+        if not ilw:
+            ga = [ga[0]] + [0.0] * P
+            gb = [gb[0]] + [0.0] * P
+        a, b = b, B.step_neumann(a, b, h, alpha, P, beta, ga, gb, dt)
+    e = b - _exact(x, nsteps * dt, k, phi)
+    return float(np.sqrt(h * np.sum(e * e)))
+
+
+@pytest.mark.parametrize("P,rate_min", [(1, 1.9), (2, 3.8), (3, 5.6)])
+def test_moving_slopes_reach_order_2P(P, rate_min):
+    # measured: rates 2.00 2.02 2.01 / 3.62 3.87 3.96 / 5.22 5.70 5.91; with
+    # the slopes as plain values 2.50 (P = 2) and 2.20 (P = 3)
+    n = 20001
+    dts = (0.1, 0.05, 0.025, 0.0125)
+    errs = [_run_neumann(P, dt, n) for dt in dts]
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    print("P=%d errors %s rates %s" % (P, ["%.3e" % e for e in errs], ["%.2f" % r for r in rates]))
+    assert rates[-1] >= rate_min and rates[-2] >= rate_min - 0.3, rates
+    if P >= 2:
+        plain = [_run_neumann(P, dt, n, ilw=False) for dt in dts[1:3]]
+        rp = np.log2(plain[0] / plain[1])
+        print("  slopes as plain values: errors %s rate %.2f" % (["%.3e" % e for e in plain], rp))
+        assert rp < 2.7
+        assert plain[1] > 5 * errs[2]
