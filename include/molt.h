@@ -241,10 +241,18 @@ mol_status mol_solve_prepare(mol_plan *plan, void *u_prev_io, void *u_curr_io, i
 mol_status mol_solve_source(mol_plan *plan, void *u_prev_io, void *u_curr_io, int64_t nsteps,
                             const void *G, const void *CG, const double *f, void *stream);
 
-/* One step for each of count independent plans: equivalent to
- * mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream) for every i, in
- * order, on one stream.  Plans must be distinct.  (Concurrent serving of many
- * requests is the request server below.) */
+/* One step (eq. Full_2D; 1D eq. update_P) for each of count independent
+ * plans, with the results of mol_step(plans[i], u_prev[i], u_curr[i],
+ * u_next[i], stream) for every i, bit for bit.  The launches at the same
+ * position of the plans' steps that use the same kernel instantiation run as
+ * one launch over a table of their argument sets (plans created with
+ * MOL_UNIFORM_CONFIG share instantiations across sizes); launches that cannot
+ * share one (masked plans, exact two-pass sweeps) run by themselves at their
+ * position.  Arrays of count HOST pointers to device fields; plans must be
+ * distinct; u_next[i] must not be u_curr[i].  The argument tables are copied
+ * through pinned staging into a stream-ordered allocation freed on the stream
+ * after the launches.  Asynchronous on stream.  (Serving many requests
+ * concurrently is the request server below.) */
 mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
                           const void *const *u_curr, void *const *u_next, int count,
                           void *stream);

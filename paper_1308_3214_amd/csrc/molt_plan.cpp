@@ -1480,6 +1480,22 @@ namespace {
 // that the fields return to their buffers), one graph launch per unit
 constexpr int64_t UNIT_STEPS = 8;
 
+// Pinned staging of mol_step_batch's argument tables: a ring of slots, each
+// reused once the copy that last read it has completed (its event).
+struct BatchStaging {
+    static constexpr int NSLOT = 4;
+    struct Slot {
+        void *h = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    };
+    std::mutex mu;
+    Slot slot[NSLOT];
+    unsigned next = 0;
+};
+BatchStaging g_batch;
+
 // count steps of the solve program on (A, B), launched directly; the
 // three-level form alternates the roles of the two buffers
 hipError_t solve_steps(mol_plan_ *pl, void *A, void *B, int64_t count, bool inc, hipStream_t s)
@@ -1788,10 +1804,137 @@ mol_status mol_step_batch(mol_plan *const *plans, const void *const *u_prev,
     if (count < 0 || (count > 0 && (!plans || !u_prev || !u_curr || !u_next)))
         return fail(MOL_E_INVALID, "bad batch arguments");
     for (int i = 0; i < count; ++i) {
-        mol_status s = mol_step(plans[i], u_prev[i], u_curr[i], u_next[i], stream);
-        if (s != MOL_OK) return s;
+        if (!plans[i] || !u_prev[i] || !u_curr[i] || !u_next[i]) return fail(MOL_E_INVALID, "NULL argument");
+        if (u_next[i] == u_curr[i]) return fail(MOL_E_INVALID, "u_next must not overlap u_curr");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(MOL_E_INVALID, "plans of a batch must be distinct");
     }
-    return MOL_OK;
+    if (count == 0) return MOL_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    // argument sets of every plan's step: launches at the same position of
+    // their steps that share a kernel instantiation form one group; launches
+    // that cannot share one (line objects, exact two-pass sweeps, L^{-1} and
+    // boundary-data sweeps) run by themselves at their position
+    struct Ent {
+        int64_t blocks;
+        size_t off, bytes;        // in args
+    };
+    struct Direct {
+        int k, i;
+    };
+    std::vector<unsigned char> args;
+    std::map<std::pair<int, SweepKey>, std::vector<Ent>> groups;
+    std::vector<Direct> direct;
+    int maxk = 0;
+    for (int i = 0; i < count; ++i) {
+        mol_plan_ *pl = plans[i];
+        const Program &prog = pl->step;
+        maxk = std::max(maxk, (int)prog.size());
+        const size_t asz = sweep_args_bytes(pl->fp64);
+        for (int k = 0; k < (int)prog.size(); ++k) {
+            if (pl->masked) {
+                direct.push_back({k, i});
+                continue;
+            }
+            const void *fp[MAXF];
+            void *op[MAXO + 1];
+            resolve_op(pl, prog[k], u_prev[i], u_curr[i], u_next[i], nullptr, nullptr, fp, op);
+            const size_t off = args.size();
+            args.resize(off + asz);
+            SweepKey key;
+            int64_t blocks = 0;
+            if (!sweep_prepare(prog[k].op, pl->geom, pl->dc[prog[k].op.dir], pl->fp64, fp, op, prog[k].cfg,
+                               args.data() + off, key, blocks)) {
+                args.resize(off);
+                direct.push_back({k, i});
+                continue;
+            }
+            groups[{k, key}].push_back({blocks, off, asz});
+        }
+    }
+    // one table per group: first[] (nent + 1 workgroup offsets), then the
+    // argument sets; all tables in one stream-ordered device allocation,
+    // copied from pinned staging
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t total = 0;
+    for (auto &g : groups) {
+        total += a256((g.second.size() + 1) * sizeof(int64_t));
+        for (const Ent &e : g.second) total += e.bytes;
+        total = a256(total);
+    }
+    struct Launch {
+        int k;
+        SweepKey key;
+        size_t tab, first;
+        int nent;
+        int64_t blocks;
+    };
+    std::vector<Launch> ls;
+    void *dtab = nullptr;
+    if (total > 0) {
+        std::unique_lock<std::mutex> lk(g_batch.mu);
+        BatchStaging::Slot &sl = g_batch.slot[g_batch.next++ % BatchStaging::NSLOT];
+        if (sl.used && hipEventSynchronize(sl.ev) != hipSuccess) return fail(MOL_E_DEVICE, "staging wait failed");
+        if (total > sl.cap) {
+            if (sl.h) (void)hipHostFree(sl.h);
+            sl.h = nullptr;
+            sl.cap = 0;
+            const size_t cap = std::max(total * 2, (size_t)1 << 16);
+            if (hipHostMalloc(&sl.h, cap, hipHostMallocDefault) != hipSuccess)
+                return fail(MOL_E_NOMEM, "pinned staging allocation failed");
+            sl.cap = cap;
+        }
+        if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
+            return fail(MOL_E_DEVICE, "staging event failed");
+        unsigned char *h = static_cast<unsigned char *>(sl.h);
+        size_t pos = 0;
+        for (auto &g : groups) {
+            const size_t nent = g.second.size();
+            int64_t *first = reinterpret_cast<int64_t *>(h + pos);
+            const size_t fpos = pos;
+            pos += a256((nent + 1) * sizeof(int64_t));
+            const size_t tpos = pos;
+            int64_t b = 0;
+            for (size_t e = 0; e < nent; ++e) {
+                first[e] = b;
+                b += g.second[e].blocks;
+                std::memcpy(h + pos, args.data() + g.second[e].off, g.second[e].bytes);
+                pos += g.second[e].bytes;
+            }
+            first[nent] = b;
+            pos = a256(pos);
+            ls.push_back({g.first.first, g.first.second, tpos, fpos, (int)nent, b});
+        }
+        if (hipMallocAsync(&dtab, total, st) != hipSuccess) return fail(MOL_E_NOMEM, "table allocation failed");
+        hipError_t e = hipMemcpyAsync(dtab, sl.h, total, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(dtab, st);
+            return dev_err(e, "mol_step_batch table copy");
+        }
+        sl.used = true;
+    }
+    // position k of every plan's step after position k - 1
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < maxk && e == hipSuccess; ++k) {
+        for (const Direct &dr : direct) {
+            if (dr.k != k || e != hipSuccess) continue;
+            mol_plan_ *pl = plans[dr.i];
+            const Program one(1, pl->step[k]);
+            e = run_program(pl, one, u_prev[dr.i], u_curr[dr.i], u_next[dr.i], nullptr, nullptr, st);
+        }
+        for (const Launch &l : ls) {
+            if (l.k != k || e != hipSuccess) continue;
+            unsigned char *d = static_cast<unsigned char *>(dtab);
+            e = launch_sweep_batch(l.key, d + l.tab, reinterpret_cast<const int64_t *>(d + l.first), l.nent,
+                                   l.blocks, st);
+        }
+    }
+    if (dtab) {
+        const hipError_t ef = hipFreeAsync(dtab, st);
+        if (e == hipSuccess) e = ef;
+    }
+    return e == hipSuccess ? MOL_OK : dev_err(e, "mol_step_batch");
 }
 
 }  // extern "C"

@@ -502,9 +502,12 @@ __device__ __forceinline__ void seg_fix_bdata(int p0, int M, T v0, T v1, T vM1, 
 // Interior segments carry two decaying terms, advanced by repeated products with d;
 // a segment holding node M (or nodes beyond it) adds the B term
 // node by node and zeroes what lies beyond M; Dirichlet end nodes get D = 0.
+// mwave (wave-uniform) = false: no lane of this wave holds node M or lies
+// beyond it, so the per-lane end handling is skipped by a branch instead of
+// being evaluated (and discarded) by every lane.
 template <typename T, int S>
 __device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A, double B, int p0,
-                                               int M, double nu, T d, bool dir_end)
+                                               int M, double nu, T d, bool dir_end, bool mwave = true)
 {
     const int jm = M - p0;
     const bool holdsM = jm < S;
@@ -520,7 +523,7 @@ __device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A
     }
 #pragma unroll
     for (int j = 0; j < S; ++j) sum[j] = -sum[j];
-    if (holdsM) {
+    if (mwave && holdsM) {
         T pw = (T)B;
 #pragma unroll
         for (int j = S - 1; j >= 0; --j) {
@@ -554,10 +557,14 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
     constexpr bool KF = (XM == 1), BD = (XM == 2);
     constexpr int NT = 64 * WPL;
     constexpr int NPAD = NT * (S + 1);
-    const int lane = t & 63, wave = t >> 6;
+    const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int M = n - 1;
     const int p0 = t * S;
     const int jm = M - p0;
+    // the wave whose lanes hold node M (n <= NT S): only waves 0 and waveM
+    // take the Dirichlet end fix-ups, only waves from waveM on the closure's
+    // end handling (wave-uniform branches; the other waves skip that code)
+    const int waveM = (M / S) >> 6;
     constexpr bool dir_end = !PER;
     const bool slow = PER && (p0 + S - 1 > M);          // periodic lane crossing the end
     T sum[NSW][S];
@@ -579,7 +586,7 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
             if (KF && a.kform[k]) seg_recur_fast_I<T, S>(v, a.d, a.w0, a.w1, a.w2, sum[k], aL[k], aR[k]);
             else seg_recur_fast<T, S>(v, a.d, a.gw, a.w2, sum[k], aL[k], aR[k]);
             eLM[k] = aL[k];                            // periodic: node M ends its lane
-            if (dir_end) {
+            if (dir_end && (BD || wave == 0 || wave == waveM)) {
                 const T v1 = (p0 == 0 && n > 1) ? sk[1] : T(0);
                 const int q = M - 1;
                 const T vM1 = (jm >= 0 && jm < S && q >= 0) ? sk[(q / S) * (S + 1) + (q % S)] : T(0);
@@ -658,7 +665,7 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
         const double A = a.K00 * er0 + a.K01 * elm;
         const double B = a.K10 * er0 + a.K11 * elm;
         if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, false);
-        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end && !BD);
+        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end && !BD, wave >= waveM);
 #pragma unroll
         for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
     }
@@ -1918,10 +1925,18 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
     const int rowb = (int)(ls * (int64_t)sizeof(T));
     const int lineb = n * rowb;
     const int vl = (int)lo * (int)sizeof(T);
+    // Dirichlet lines: the load resources cover only the rows of the line
+    // that hold data for this walk, [wlo, whi); rows before them (negative
+    // offsets), after them, and every row past the walk fall outside and read
+    // 0, so the loads need no per-row choice of resource.  Periodic lines wrap
+    // rows and keep the choice below.
+    const int wlo = PER ? 0 : (rlo > 0 ? rlo : 0);
+    const int whi = PER ? n : (rhi < n ? rhi : n);
     __amdgpu_buffer_rsrc_t rsf[NFP];
 #pragma unroll
     for (int c = 0; c < NFP; ++c)
-        rsf[c] = make_rsrc(c < a.nf ? a.f[c] + blk : a.f[0] + blk, c < a.nf ? lineb : 0);
+        rsf[c] = make_rsrc((c < a.nf ? a.f[c] : a.f[0]) + blk + (int64_t)wlo * ls,
+                           c < a.nf ? (whi - wlo) * rowb : 0);
     __amdgpu_buffer_rsrc_t rso[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) rso[o] = make_rsrc(a.o[o] + blk, lineb);
@@ -1942,13 +1957,24 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
     const __amdgpu_buffer_rsrc_t rnone = make_rsrc(a.f[0] + blk, 0);
     auto issue = [&](int t, Raw &xr) {
         const int p0 = wst + t * WS + wave * S;
+        if (PER) {
 #pragma unroll
-        for (int j = 0; j < S + 2; ++j) {
-            const int r = p0 - 1 + j;
-            const bool ok = t < Rw && r >= rlo && r < rhi;
-            const int off = vl + wrap(r) * rowb;
+            for (int j = 0; j < S + 2; ++j) {
+                const int r = p0 - 1 + j;
+                const bool ok = t < Rw && r >= rlo && r < rhi;
+                const int off = vl + wrap(r) * rowb;
 #pragma unroll
-            for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(ok ? rsf[c] : rnone, off);
+                for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(ok ? rsf[c] : rnone, off);
+            }
+        } else {
+            // rows past the walk lie at or beyond whi: rhi <= the walk's end
+            // when the strip has a successor, else whi = n
+            const int off0 = vl + (p0 - 1 - wlo) * rowb;
+#pragma unroll
+            for (int j = 0; j < S + 2; ++j) {
+#pragma unroll
+                for (int c = 0; c < NFP; ++c) xr[c][j] = buf_load<T>(rsf[c], off0 + j * rowb);
+            }
         }
     };
 

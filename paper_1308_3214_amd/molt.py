@@ -464,9 +464,13 @@ def step_static(u_prev, u_curr, u_next, shape, h, stream=None, **kw):
 
 
 def step_batch(plans, u_prev, u_curr, u_next, stream=None):
+    """One step of every plan (mol_step_batch): launches shared across plans
+    where they use the same kernel instantiation."""
     n = len(plans)
-    arr = lambda xs: (_vp * n)(*[ctypes.c_void_p(x) for x in xs])  # noqa: E731
+    if not (len(u_prev) == len(u_curr) == len(u_next) == n):
+        raise ValueError("one u_prev, u_curr and u_next per plan")
+    arr = lambda xs: (_vp * n)(*xs)  # noqa: E731
     hs = (_vp * n)(*[p.handle for p in plans])
-    _check(_lib.mol_step_batch(hs, arr([t.data_ptr() for t in u_prev]),
-                               arr([t.data_ptr() for t in u_curr]),
-                               arr([t.data_ptr() for t in u_next]), n, _stream(stream)))
+    _check(_lib.mol_step_batch(hs, arr([p._t(t) for p, t in zip(plans, u_prev)]),
+                               arr([p._t(t) for p, t in zip(plans, u_curr)]),
+                               arr([p._t(t) for p, t in zip(plans, u_next)]), n, _stream(stream)))
