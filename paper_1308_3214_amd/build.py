@@ -4,6 +4,7 @@ from __future__ import annotations
 import fcntl
 import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -25,16 +26,30 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wno-unused-command-line-argument"]
 
 
+def _includes(path: str, seen: set) -> None:
+    """The library's own headers path includes, transitively (quoted
+    includes resolved beside the including file)."""
+    with open(path) as f:
+        for line in f:
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                dep = os.path.normpath(os.path.join(os.path.dirname(path), m.group(1)))
+                if dep not in seen and os.path.exists(dep):
+                    seen.add(dep)
+                    _includes(dep, seen)
+
+
 def _inputs_digest(src: str) -> str:
-    """Digest of what an object is compiled from: the source, every header
-    of the library, the public header and the flags."""
+    """Digest of what an object is compiled from: the source, the headers it
+    includes (transitively) and the flags."""
     h = hashlib.sha256()
     h.update(" ".join(FLAGS).encode())
-    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".h", ".inc")))
-    for path in [os.path.join(CSRC, src)] + [os.path.join(CSRC, f) for f in names] + \
-            [os.path.join(HERE, "..", "include", "molt.h")]:
-        with open(path, "rb") as f:
-            h.update(os.path.basename(path).encode())
+    path = os.path.join(CSRC, src)
+    deps = set()
+    _includes(path, deps)
+    for dep in [path] + sorted(deps):
+        with open(dep, "rb") as f:
+            h.update(os.path.basename(dep).encode())
             h.update(f.read())
     return h.hexdigest()
 

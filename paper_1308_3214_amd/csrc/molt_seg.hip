@@ -103,23 +103,35 @@ k_seg_sweep(const SegArgs<T> a)
 #pragma unroll
         for (int o = 0; o < NO; ++o) ev[o][i] = T(0);
     }
-    for (int f = 0; f < a.nf; ++f) {
-        const T *src = a.f[f] + base;
-        T x[S];
+    // every load of a chunk of up to four fields is issued before any value
+    // is used (clamped indices, values past the object zeroed afterwards), so
+    // that a chunk costs one memory latency, not one per field
+    auto load_chunk = [&](int f0, auto cc) {
+        constexpr int C = decltype(cc)::value;
+        T x[C][S];
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const int e = i * NT + t;
-            const T val = src[(int64_t)(e < m ? e : 0) * ps];
-            x[i] = (e < m) ? val : T(0);
+        for (int c = 0; c < C; ++c) {
+            const T *src = a.f[f0 + c] + base;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const int e = i * NT + t;
+                x[c][i] = src[(int64_t)(e < m ? e : 0) * ps];
+            }
         }
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
+        for (int c = 0; c < C; ++c) {
+            const int f = f0 + c;
 #pragma unroll
-            for (int k = 0; k < NS; ++k) sv[k][i] += a.mS[k][f] * x[i];
+            for (int i = 0; i < S; ++i) {
+                const T xv = (i * NT + t < m) ? x[c][i] : T(0);
 #pragma unroll
-            for (int o = 0; o < NO; ++o) ev[o][i] += a.mOF[o][f] * x[i];
+                for (int k = 0; k < NS; ++k) sv[k][i] += a.mS[k][f] * xv;
+#pragma unroll
+                for (int o = 0; o < NO; ++o) ev[o][i] += a.mOF[o][f] * xv;
+            }
         }
-    }
+    };
+    field_chunks<4, MAXF>(a.nf, load_chunk);
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         const int e = i * NT + t;
@@ -314,7 +326,7 @@ __global__ void k_mask_zero(int64_t n, const unsigned char *mask, T *out)
 }
 
 struct SegCfg { int S, WPL; };
-constexpr SegCfg kSegCfg[NSEGCLS] = {{4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {16, 8}};
+constexpr SegCfg kSegCfg[NSEGCLS] = {{4, 1}, {8, 1}, {8, 2}, {8, 4}, {8, 8}, {16, 8}};
 
 template <typename T, int S, int WPL, int NS, int NO>
 hipError_t run_seg(const SegArgs<T> &k, int64_t count, hipStream_t st)
