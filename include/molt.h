@@ -120,10 +120,13 @@ typedef struct mol_plan_info {
  * (Theorem of Sec. 3.1, eq. Stab_cond); returns -1 for P outside 1..8. */
 double mol_beta_max(int P);
 
-/* Size limits: at most 16384 nodes along x (one workgroup per x line; 8192 in
- * FP64 for launches that sweep two combinations, and for the line objects of a
- * mask), any length along y and z, and fewer than 2^31 nodes per field; beyond
- * them MOL_E_UNSUPPORTED.
+/* Size limits: fewer than 2^31 nodes per field; any length along y and z; an
+ * x line of up to 16384 nodes is one workgroup (8192 in FP64 for launches that
+ * sweep two combinations); longer x lines of homogeneous Dirichlet type are
+ * swept in chunks of 4096 nodes, exact across them (a carry table and scan
+ * between two passes; L^{-1} applied as v - D v there), while periodic,
+ * Neumann and K-form (small nu) x lines must fit one workgroup, and the line
+ * objects of a mask at most 8192 nodes; beyond them MOL_E_UNSUPPORTED.
  * Validates the descriptor, derives alpha, the quadrature weights and the
  * stage coefficients in FP64, builds the kernel schedule (and for a mask the
  * line-object tables), and allocates the device workspace on the current

@@ -110,6 +110,28 @@ void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *con
     key.cfg = cfg[0];
     key.nsno = op.ns * 10 + op.no;
     key.periodic = dc.periodic ? 1 : 0;
+    if (dir == 0 && cfg[0] == NXCFG) {
+        // chunked x lines (exact across chunks)
+        const int64_t nlines = g.n[1] * g.n[2];
+        k.nlines = nlines;
+        k.lineoff = g.n[0];
+        k.ntiles = (int)((g.n[0] + XC_C - 1) / XC_C);
+        k.tile_rows = XC_C;
+        k.nblocks = nlines * k.ntiles;
+        k.dS = (T)exp(-dc.nu * XC_S);
+        k.dBlk = (T)exp(-dc.nu * XC_S * 64.0);
+        k.dT = (T)exp(-dc.nu * (double)XC_C);
+        for (int i = 0; i < 6; ++i) k.dpw[i] = (T)exp(-dc.nu * XC_S * (double)(1 << i));
+        k.pn1 = g.n[1];
+        k.pn2 = g.n[2];
+        k.pd1 = g.ndim > 1 ? g.dirichlet[1] : 0;
+        k.pd2 = g.ndim > 2 ? g.dirichlet[2] : 0;
+        key.cls = 5;
+        key.cfg = 0;
+        key.nfb = op.nf <= 4 ? 4 : 16;
+        blocks = k.nblocks;
+        return;
+    }
     if (dir == 0) {
         const XCfg c = kXCfg[cfg[0]];
         const int64_t nlines = g.n[1] * g.n[2];
@@ -258,6 +280,13 @@ hipError_t dispatch_t(const KArgs<T> &k, const SweepKey &key, int64_t blocks, co
             return small ? dispatch_e_f32_n4(k, key.nsno, key.cfg, st) : dispatch_e_f32_n16(k, key.nsno, key.cfg, st);
         else
             return small ? dispatch_e_f64_n4(k, key.nsno, key.cfg, st) : dispatch_e_f64_n16(k, key.nsno, key.cfg, st);
+    case 5:
+        // chunked x lines: three launches of their own, no batched table
+        if (bt) return hipErrorInvalidValue;
+        if constexpr (sizeof(T) == 4)
+            return small ? dispatch_xc_f32_n4(k, key.nsno, st) : dispatch_xc_f32_n16(k, key.nsno, st);
+        else
+            return small ? dispatch_xc_f64_n4(k, key.nsno, st) : dispatch_xc_f64_n16(k, key.nsno, st);
     default:
         return hipErrorInvalidValue;
     }
@@ -306,6 +335,15 @@ bool config_valid(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp64
     }
     // (ns, no) in {(1, 1), (1, 2), (2, 1), (2, 2), (2, 3)}; (2, 1) not for the strip kernel
     if (!((ns == 1 && (no == 1 || no == 2)) || (ns == 2 && (no >= 1 && no <= 3)))) return false;
+    if (dir == 0 && cfg[0] == NXCFG) {
+        // chunked x lines: D sweeps of Dirichlet lines (no periodic wrap, no
+        // L^{-1} or boundary-data sweeps, no chained second sweep)
+        if (dc.periodic || kf || op.bmode || op.chain) return false;
+        // lines of more than one chunk (the plan holds the chunk table then)
+        if (g.n[0] <= XC_C) return false;
+        const size_t lds = (size_t)ns * 64 * XC_WPL * (XC_S + 1) * es;
+        return lds <= (size_t)max_lds();
+    }
     if (dir == 0) {
         if (cfg[0] < 0 || cfg[0] >= NXCFG) return false;
         const XCfg c = kXCfg[cfg[0]];
@@ -386,7 +424,9 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
             const XCfg c = kXCfg[cfg[0]];
             if (64 * c.WPL * c.S >= n && config_valid(g, dc, op, fp64, cfg)) return 0;
         }
-        return -1;
+        // longer than any workgroup holds: chunks, exact across them
+        cfg[0] = NXCFG;
+        return config_valid(g, dc, op, fp64, cfg) ? 0 : -1;
     }
     // strided: the pipelined strip kernel for one swept combination, else
     // tall tiles (16 waves x 16 nodes) for FP32 single sweeps, shorter lanes
@@ -436,11 +476,19 @@ int config_count(const SweepOp &op)
 
 bool config_exact(const SweepOp &op, const int *cfg)
 {
-    return !op.yy && op.dir != 0 && cfg[0] >= NSCFG + NPCFG;
+    if (op.dir == 0) return !op.yy && cfg[0] == NXCFG;
+    return !op.yy && cfg[0] >= NSCFG + NPCFG;
 }
 
 size_t exact_agg_bytes(const Geom &g, int dir, bool fp64)
 {
+    if (dir == 0) {
+        // chunked x lines (only where a line exceeds one chunk)
+        if (g.n[0] <= XC_C) return 0;
+        const int64_t groups = (g.n[1] * g.n[2] + 63) / 64;
+        const int64_t chunks = (g.n[0] + XC_C - 1) / XC_C;
+        return (size_t)(groups * chunks) * MAXS * 3 * 64 * (fp64 ? 8 : 4);
+    }
     if (dir < 1 || dir >= g.ndim) return 0;
     const int64_t ncg = (g.n[0] + 63) / 64;
     const int64_t nouter = dir == 1 ? g.n[2] : g.n[1];

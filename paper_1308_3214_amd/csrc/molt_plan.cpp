@@ -770,7 +770,13 @@ bool build_apply(Builder &b, Program &prog, int op)
             o.dc[0] = -1.0;
             return b.emit(prog, dir, {lin(B_IN)}, {o}, 1);
         }
-        return b.emit(prog, dir, {lin(B_IN)}, {o}, 1, -1, {op <= MOL_OP_LINV_Z ? 1 : 0});
+        if (b.emit(prog, dir, {lin(B_IN)}, {o}, 1, -1, {op <= MOL_OP_LINV_Z ? 1 : 0})) return true;
+        if (op > MOL_OP_LINV_Z) return false;
+        // lines swept in chunks carry the D recurrences only: L^{-1} v = v - D v
+        b.err.clear();
+        o.elem = lin(B_IN);
+        o.dc[0] = -1.0;
+        return b.emit(prog, dir, {lin(B_IN)}, {o}, 1);
     }
     if (pl.masked) return build_apply_masked(b, prog, op);
     if (op == MOL_OP_RHS) return build_rhs(b, prog, B_IN, {{B_OUT, Lin{}, 1.0}});
@@ -1050,7 +1056,8 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
     pl->kmode = !pl->masked && g.ndim == 2 &&
                 std::min(pl->dc[0].nu, pl->dc[1].nu) < KMODE_NU;
     if (!pl->masked)
-        pl->agg_bytes = std::max(exact_agg_bytes(g, 1, pl->fp64), exact_agg_bytes(g, 2, pl->fp64));
+        pl->agg_bytes = std::max(exact_agg_bytes(g, 0, pl->fp64),
+                                 std::max(exact_agg_bytes(g, 1, pl->fp64), exact_agg_bytes(g, 2, pl->fp64)));
     if (pl->masked) {
         std::string err;
         pl->h_mask.assign(d->mask, d->mask + pl->npts);
@@ -1067,20 +1074,31 @@ mol_status build_plan(const mol_desc *d, mol_plan_ *pl, bool dry)
     // increment form: (u, du) -> (u + du + rhs, du + rhs), in place
     ok = ok && build_rhs(b, pl->inc_step, B_UCURR,
                          {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0}, {B_UPREV, lin(B_UPREV), 1.0}});
-    // fused solve programs (2D rectangles, P >= 2)
+    // fused solve programs (2D rectangles, P >= 2); where they cannot be
+    // built (x lines longer than one workgroup: the chained x sweep needs the
+    // whole line), mol_solve takes the step programs
     if (ok && !pl->masked && !pl->kmode && g.ndim == 2 && d->P >= 2) {
+        const int n0 = pl->nws;
         pl->chain_a = b.new_ws();
         OutSpec o{};
         o.buf = pl->chain_a;
         o.dc[0] = 1.0;
-        ok = ok && b.emit(pl->solve_pro, 0, {lin(B_UCURR)}, {o}, 0);
-        ok = ok && build_rhs_box(b, pl->solve_step, B_UCURR,
-                                 {{B_UNEXT, lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0), 1.0}},
-                                 pl->chain_a);
-        ok = ok && build_rhs_box(b, pl->solve_inc_step, B_UCURR,
-                                 {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0},
-                                  {B_UPREV, lin(B_UPREV), 1.0}},
-                                 pl->chain_a);
+        bool fused = b.emit(pl->solve_pro, 0, {lin(B_UCURR)}, {o}, 0);
+        fused = fused && build_rhs_box(b, pl->solve_step, B_UCURR,
+                                       {{B_UNEXT, lin(B_UCURR, 2.0) + lin(B_UPREV, -1.0), 1.0}},
+                                       pl->chain_a);
+        fused = fused && build_rhs_box(b, pl->solve_inc_step, B_UCURR,
+                                       {{B_UCURR, lin(B_UCURR) + lin(B_UPREV), 1.0},
+                                        {B_UPREV, lin(B_UPREV), 1.0}},
+                                       pl->chain_a);
+        if (!fused) {
+            pl->solve_pro.clear();
+            pl->solve_step.clear();
+            pl->solve_inc_step.clear();
+            pl->chain_a = -1;
+            pl->nws = n0;
+            b.err.clear();
+        }
     }
     // step with a source term: its workspace ids start again from the first
     // field (the other programs keep nothing there between calls)

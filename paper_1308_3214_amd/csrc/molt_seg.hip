@@ -104,30 +104,30 @@ k_seg_sweep(const SegArgs<T> a)
         for (int o = 0; o < NO; ++o) ev[o][i] = T(0);
     }
     // every load of a chunk of up to four fields is issued before any value
-    // is used (clamped indices, values past the object zeroed afterwards), so
-    // that a chunk costs one memory latency, not one per field
+    // is used, so that a chunk costs one memory latency, not one per field.
+    // Buffer loads over the object's nodes: 32-bit offsets, and nodes past
+    // the object (offsets beyond the resource) read 0 in hardware.
+    const int rbytes = (int)((int64_t)m * ps * (int64_t)sizeof(T));
+    const int ostep = (int)(NT * ps * (int64_t)sizeof(T));      // bytes between a lane's nodes
+    const int off0 = (int)(t * ps * (int64_t)sizeof(T));
     auto load_chunk = [&](int f0, auto cc) {
         constexpr int C = decltype(cc)::value;
         T x[C][S];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const T *src = a.f[f0 + c] + base;
+            const __amdgpu_buffer_rsrc_t r = make_rsrc(a.f[f0 + c] + base, rbytes);
 #pragma unroll
-            for (int i = 0; i < S; ++i) {
-                const int e = i * NT + t;
-                x[c][i] = src[(int64_t)(e < m ? e : 0) * ps];
-            }
+            for (int i = 0; i < S; ++i) x[c][i] = buf_load<T>(r, off0 + i * ostep);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int f = f0 + c;
 #pragma unroll
             for (int i = 0; i < S; ++i) {
-                const T xv = (i * NT + t < m) ? x[c][i] : T(0);
 #pragma unroll
-                for (int k = 0; k < NS; ++k) sv[k][i] += a.mS[k][f] * xv;
+                for (int k = 0; k < NS; ++k) sv[k][i] += a.mS[k][f] * x[c][i];
 #pragma unroll
-                for (int o = 0; o < NO; ++o) ev[o][i] += a.mOF[o][f] * xv;
+                for (int o = 0; o < NO; ++o) ev[o][i] += a.mOF[o][f] * x[c][i];
             }
         }
     };
@@ -144,7 +144,13 @@ k_seg_sweep(const SegArgs<T> a)
     // ---- recurrences over S consecutive nodes per lane ----
     const int p0 = t * S;
     const int jm = m - 1 - p0;                       // position of the last node in this lane
-    const bool interior = (p0 >= 1) && (p0 + S - 1 <= m - 2);
+    // lanes wholly past the object force nothing (their data read 0, and the
+    // node before the first of them is zeroed below): the uniform recurrence;
+    // the object's end cells only in the lanes holding node 0 or node m-1
+    const bool beyond = p0 >= m;
+    const bool interior = ((p0 >= 1) && (p0 + S - 1 <= m - 2)) || beyond;
+    // a wave wholly past the object (wave-uniform) skips the recurrences
+    const bool idle = __builtin_amdgcn_readfirstlane(wave) * 64 * S >= m;
     T sum[NS][S], aL[NS], aR[NS], eLast[NS], v0s[NS], vls[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -152,9 +158,13 @@ k_seg_sweep(const SegArgs<T> a)
         T v[S + 2];
 #pragma unroll
         for (int j = 0; j < S; ++j) v[j + 1] = sk[t * (S + 1) + j];
-        v[0] = (t > 0) ? sk[(t - 1) * (S + 1) + (S - 1)] : T(0);
+        v[0] = (t > 0 && !beyond) ? sk[(t - 1) * (S + 1) + (S - 1)] : T(0);
         v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : T(0);
-        if (interior) {
+        if (idle) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) sum[k][j] = T(0);
+            aL[k] = aR[k] = eLast[k] = T(0);
+        } else if (interior) {
             seg_recur_fast<T, S>(v, d, a.gw, w2, sum[k], aL[k], aR[k]);
             eLast[k] = T(0);
         } else {
@@ -224,21 +234,22 @@ k_seg_sweep(const SegArgs<T> a)
     __syncthreads();
 
     // ---- epilogue in the load layout ----
+    __amdgpu_buffer_rsrc_t ro[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) ro[o] = make_rsrc(a.o[o] + base, rbytes);
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         const int e = i * NT + t;
-        if (e < m) {
-            const int slot = (e / S) * (S + 1) + (e % S);
-            T Dk[NS];
+        const int slot = (e / S) * (S + 1) + (e % S);
+        T Dk[NS];
 #pragma unroll
-            for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
+        for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
 #pragma unroll
-            for (int o = 0; o < NO; ++o) {
-                T r = ev[o][i];
+        for (int o = 0; o < NO; ++o) {
+            T r = ev[o][i];
 #pragma unroll
-                for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
-                a.o[o][base + (int64_t)e * ps] = r;
-            }
+            for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
+            buf_store<T>(r, ro[o], off0 + i * ostep);         // nodes past the object: dropped
         }
     }
 }

@@ -1840,6 +1840,232 @@ k_sweep_p_b(const KArgs<T> *__restrict__ tab, const int64_t *__restrict__ first,
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// x lines longer than one workgroup: chunks of XC_C = 64 XC_WPL XC_S nodes,
+// one workgroup per (line, chunk), exact across chunks (Dirichlet lines)
+// ---------------------------------------------------------------------------
+// Pass 1 (MODE 1) sweeps a chunk with zero carries at its ends and writes the
+// chunk's forward aggregate (E^L at its last node), its backward aggregate
+// (E^R at its first node) and, in the chunk holding node M, E^L at M, into
+// the table the exact strided sweeps use, a line taking the place of a column:
+// ((line/64 * nchunks + chunk) * MAXS + k) * 3 * 64 + slot * 64 + line % 64.
+// k_exact_scan folds them into the carries entering every chunk and the two
+// line ends; pass 2 (MODE 2) sweeps the chunk again with those carries, forms
+// the closure from the line ends and writes the outputs.
+constexpr int XC_S = 8, XC_WPL = 8, XC_C = 64 * XC_WPL * XC_S;
+template <typename T, int NS, int NO, int NFMAX, int MODE>
+__device__ __forceinline__ void sweep_xc_body(const KArgs<T> &a, const int64_t bid)
+{
+    constexpr int S = XC_S, WPL = XC_WPL, C = XC_C;
+    constexpr int NT = 64 * WPL;
+    constexpr int NPAD = NT * (S + 1);
+    constexpr int NOE = (MODE == 2) ? NO : 1;
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);          // [NS][NPAD]
+    __shared__ T wtot[2][MAXS][WPL];
+    __shared__ T halo[2][MAXS];                       // combinations at nodes cs - 1 and cs + C
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int nch = a.ntiles;
+    const int64_t line = bid / nch;
+    const int chunk = (int)(bid % nch);
+    const int n = (int)a.n, M = n - 1;
+    const int cs = chunk * C;                        // first node of the chunk
+    const int cn = (n - cs < C) ? n - cs : C;        // nodes in the chunk
+    const int64_t base = line * a.lineoff + cs;
+    const T d = a.d, w2 = a.w2;
+    T *tab = a.agg + (size_t)(line >> 6) * (size_t)nch * (MAXS * 3 * 64) + (int)(line & 63);
+
+    // ---- loads of node cs + e, e = i*NT + t: combinations and field terms ----
+    T sv[NS][S], ev[NOE][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sv[k][i] = T(0);
+#pragma unroll
+        for (int o = 0; o < NOE; ++o) ev[o][i] = T(0);
+    }
+    auto load_fields = [&](int f0, auto cc) {
+        constexpr int CC = decltype(cc)::value;
+        T x[CC][S];
+#pragma unroll
+        for (int c = 0; c < CC; ++c) {
+            const T *src = a.f[f0 + c] + base;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const int e = i * NT + t;
+                x[c][i] = src[e < cn ? e : 0];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CC; ++c) {
+            const int f = f0 + c;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const T xv = (i * NT + t < cn) ? x[c][i] : T(0);
+#pragma unroll
+                for (int k = 0; k < NS; ++k) sv[k][i] += a.mS[k][f] * xv;
+                if (MODE == 2) {
+#pragma unroll
+                    for (int o = 0; o < NOE; ++o) ev[o][i] += a.mOF[o][f] * xv;
+                }
+            }
+        }
+    };
+    field_chunks<4, NFMAX>(a.nf, load_fields);
+    // staging; the Dirichlet end nodes and nodes past the line read as 0
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const int e = i * NT + t;
+        const int ge = cs + e;
+        const int slot = (e / S) * (S + 1) + (e % S);
+        const bool zero = (e >= cn) || ge == 0 || ge == M;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sm[k * NPAD + slot] = zero ? T(0) : sv[k][i];
+    }
+    // the combinations at the nodes just outside the chunk (0 at and past the
+    // line ends), for the forcing of its first and last node
+    if (t < 2) {
+        const int gn = (t == 0) ? cs - 1 : cs + C;
+        const bool in = gn >= 1 && gn < M;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T sk = T(0);
+            if (in)
+                for (int f = 0; f < a.nf; ++f) sk += a.mS[k][f] * a.f[f][line * a.lineoff + gn];
+            halo[t][k] = sk;
+        }
+    }
+    __syncthreads();
+
+    // ---- recurrences over S consecutive nodes per lane (global node p0..) ----
+    const int p0l = t * S, p0 = cs + p0l;
+    const int jm = M - p0;
+    T sum[NS][S], aL[NS], aR[NS], eLM[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const T *sk = sm + k * NPAD;
+        T v[S + 2];
+#pragma unroll
+        for (int j = 0; j < S; ++j) v[j + 1] = sk[t * (S + 1) + j];
+        v[0] = (t == 0) ? halo[0][k] : sk[(t - 1) * (S + 1) + (S - 1)];
+        v[S + 1] = (t + 1 < NT) ? sk[(t + 1) * (S + 1)] : halo[1][k];
+        seg_recur_fast<T, S>(v, d, a.gw, w2, sum[k], aL[k], aR[k]);
+        eLM[k] = aL[k];
+        if (p0 == 0 || (jm >= 0 && jm < S)) {
+            const T v1 = (p0 == 0 && n > 1) ? sk[1] : T(0);
+            T vM1 = T(0);
+            if (jm >= 0 && jm < S) {
+                const int q = M - 1 - cs;                // node M-1, local
+                vM1 = (q >= 0) ? sk[(q / S) * (S + 1) + (q % S)] : halo[0][k];
+            }
+            seg_fix_dirichlet<T, S>(p0, M, v1, vM1, d, w2, sum[k], aL[k], aR[k], eLM[k]);
+        }
+    }
+    // lane scan (multiplier d^S per lane), then waves through LDS
+    T cL[NS], cR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T xl = aL[k], xr = aR[k];
+#pragma unroll
+        for (int i = 0, off = 1; off < 64; ++i, off <<= 1) {
+            const T m = a.dpw[i];
+            const T yl = shfl_up(xl, off);
+            const T yr = shfl_down(xr, off);
+            if (lane >= off) xl += m * yl;
+            if (lane + off < 64) xr += m * yr;
+        }
+        const T exl = shfl_up(xl, 1);
+        const T exr = shfl_down(xr, 1);
+        cL[k] = (lane == 0) ? T(0) : exl;
+        cR[k] = (lane == 63) ? T(0) : exr;
+        if (lane == 63) wtot[0][k][wave] = xl;
+        if (lane == 0) wtot[1][k][wave] = xr;
+    }
+    __syncthreads();
+    {
+        const T pl = expneg<T>(a.nu * (double)S * (double)lane);
+        const T pr = expneg<T>(a.nu * (double)S * (double)(63 - lane));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T cw = T(0), cwr = T(0);
+            for (int w = 0; w < wave; ++w) cw = a.dBlk * cw + wtot[0][k][w];
+            for (int w = WPL - 1; w > wave; --w) cwr = a.dBlk * cwr + wtot[1][k][w];
+            cL[k] += pl * cw;
+            cR[k] += pr * cwr;
+        }
+    }
+    if (MODE == 1) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            T *tk = tab + ((size_t)chunk * MAXS + k) * (3 * 64);
+            if (t == 0) {
+                T c = T(0), cr = T(0);
+                for (int w = 0; w < WPL; ++w) c = a.dBlk * c + wtot[0][k][w];
+                for (int w = WPL - 1; w >= 0; --w) cr = a.dBlk * cr + wtot[1][k][w];
+                tk[0] = c;
+                tk[64] = cr;
+            }
+            if (jm >= 0 && jm < S) tk[128] = eLM[k] + expneg<T>(a.nu * (double)(jm + 1)) * cL[k];
+        }
+        return;
+    }
+
+    // ---- pass 2: carries entering the chunk, line ends, closure ----
+    const int last = nch - 1;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const T cinL = tab[((size_t)chunk * MAXS + k) * (3 * 64)];
+        const T cinR = tab[((size_t)chunk * MAXS + k) * (3 * 64) + 64];
+        cL[k] += expneg<T>(a.nu * (double)p0l) * cinL;
+        cR[k] += expneg<T>(a.nu * (double)(C - p0l - S)) * cinR;
+        const double er0 = (double)tab[(size_t)k * (3 * 64) + 128];
+        const double elm = (double)tab[((size_t)last * MAXS + k) * (3 * 64) + 128];
+        const double A = a.K00 * er0 + a.K01 * elm;
+        const double B = a.K10 * er0 + a.K11 * elm;
+        seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, true);
+    }
+    __syncthreads();                                 // every read of the staged data is done
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        T *sk = sm + k * NPAD;
+#pragma unroll
+        for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
+    }
+    __syncthreads();
+    bool bline = false;
+    if (a.proj) {
+        const int64_t i1 = line % a.pn1, i2 = line / a.pn1;
+        bline = (a.pd1 && (i1 == 0 || i1 == a.pn1 - 1)) || (a.pd2 && (i2 == 0 || i2 == a.pn2 - 1));
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const int e = i * NT + t;
+        if (e < cn) {
+            const int ge = cs + e;
+            const int slot = (e / S) * (S + 1) + (e % S);
+            T Dk[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Dk[k] = sm[k * NPAD + slot];
+            const bool z = a.proj && (bline || ge == 0 || ge == M);
+#pragma unroll
+            for (int o = 0; o < NOE; ++o) {
+                T r = ev[o][i];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) r += a.mOD[o][k] * Dk[k];
+                a.o[o][base + e] = z ? T(0) : r;
+            }
+        }
+    }
+}
+template <typename T, int NS, int NO, int NFMAX, int MODE>
+__global__ void __launch_bounds__(64 * XC_WPL)
+k_sweep_xc(const KArgs<T> a)
+{
+    sweep_xc_body<T, NS, NO, NFMAX, MODE>(a, blockIdx.x);
+}
+
 // chained strided sweep: v1 = e1 + D s1 and y = D v1 along the same lines in
 // one strip walk (2D: the two y sweeps of a step, stage 1 and stage 2)
 // ---------------------------------------------------------------------------
@@ -2261,6 +2487,11 @@ hipError_t dispatch_e_f32_n4(const KArgs<float> &k, int nsno, int id, hipStream_
 hipError_t dispatch_e_f64_n4(const KArgs<double> &k, int nsno, int id, hipStream_t st);
 hipError_t dispatch_e_f32_n16(const KArgs<float> &k, int nsno, int id, hipStream_t st);
 hipError_t dispatch_e_f64_n16(const KArgs<double> &k, int nsno, int id, hipStream_t st);
+// chunked exact x kernels (lines longer than one workgroup, k.agg set)
+hipError_t dispatch_xc_f32_n4(const KArgs<float> &k, int nsno, hipStream_t st);
+hipError_t dispatch_xc_f64_n4(const KArgs<double> &k, int nsno, hipStream_t st);
+hipError_t dispatch_xc_f32_n16(const KArgs<float> &k, int nsno, hipStream_t st);
+hipError_t dispatch_xc_f64_n16(const KArgs<double> &k, int nsno, hipStream_t st);
 // chained strided kernels (FP32, op.nf <= 3, one or two outputs)
 hipError_t dispatch_yy_f32(const KArgs<float> &k, int no, int id, const BatchTab *bt, hipStream_t st);
 

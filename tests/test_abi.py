@@ -80,13 +80,22 @@ def test_descriptor_validation_and_workspace(lib):
 
 
 def test_size_limits(lib):
-    # an x line is one workgroup (at most 16384 nodes: 16 waves of 64 lanes x
-    # 16 nodes); y and z lines are walked in strips (any length); fields of
-    # 2^31 nodes or more are refused (the kernels index a field with 32-bit
-    # offsets)
+    # an x line of up to 16384 nodes is one workgroup (16 waves of 64 lanes x
+    # 16 nodes); longer Dirichlet x lines are swept in chunks of 4096 nodes,
+    # exact across them (a carry table of 3 values per chunk and line); y and
+    # z lines are walked in strips or tiles (any length); fields of 2^31 nodes
+    # or more are refused (the kernels index a field with 32-bit offsets)
     from paper_1308_3214_amd import molt
     assert molt.workspace_bytes(shape=(4, 16384), h=1e-4, P=2, cfl=2.0, dtype="f32") > 0
-    assert molt.workspace_bytes(shape=(4, 16385), h=1e-4, P=2, cfl=2.0, dtype="f32") == 0
+    w = molt.workspace_bytes(shape=(4, 16385), h=1e-4, P=2, cfl=2.0, dtype="f32")
+    assert w > 0, molt.last_error()
+    w1 = molt.workspace_bytes(shape=(1 << 20,), h=1e-6, P=3, cfl=2.0, dtype="f64")
+    assert w1 > 0, molt.last_error()
+    # the chunk table of a 1D line of 2^20 nodes: 256 chunks x 2 combinations
+    # x 3 values x 64 lanes, FP64
+    assert w1 % ((1 << 20) * 8) == 256 * 2 * 3 * 64 * 8
+    # periodic x lines must fit one workgroup (the wrap needs the whole line)
+    assert molt.workspace_bytes(shape=(4, 16385), h=1e-4, bc=1, P=2, cfl=2.0, dtype="f32") == 0
     assert "line length" in molt.last_error()
     tall = (1 << 31) // 16384                     # 131072 rows of 16384 nodes = 2^31
     w = molt.workspace_bytes(shape=(tall - 1, 16384), h=1e-6, P=2, cfl=2.0, dtype="f32")
