@@ -1211,14 +1211,16 @@ void free_plan(mol_plan_ *pl, hipStream_t st)
 {
     if (!pl) return;
     drop_graphs(pl);
-    for (void *p : pl->ws) {
-        if (!p) continue;
-        if (pl->async_ws) (void)hipFreeAsync(p, st);
-        else (void)hipFree(p);
+    if (pl->async_ws) {
+        if (pl->slab) (void)hipFreeAsync(pl->slab, st);
+        pl->slab = nullptr;
+        pl->ws.clear();
+        pl->agg = nullptr;
     }
+    for (void *p : pl->ws)
+        if (p) (void)hipFree(p);
     if (pl->agg) {
-        if (pl->async_ws) (void)hipFreeAsync(pl->agg, st);
-        else (void)hipFree(pl->agg);
+        (void)hipFree(pl->agg);
         pl->agg = nullptr;
     }
     masked_free(pl);
@@ -1235,7 +1237,8 @@ mol_status dev_err(hipError_t e, const char *what)
     return fail(MOL_E_DEVICE, m);
 }
 
-mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out)
+mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out,
+                             hipMemPool_t pool)
 {
     if (!out) return fail(MOL_E_INVALID, "plan out-pointer is NULL");
     mol_plan_ *pl = new (std::nothrow) mol_plan_();
@@ -1247,20 +1250,24 @@ mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **o
     }
     hipGetDevice(&pl->dev);
     pl->async_ws = true;
+    // one block: the workspace fields (256-byte aligned), then the table;
+    // a single allocation and a single clear per plan keep the host cost of
+    // admitting a request low
+    const size_t fb = ((size_t)pl->npts * pl->es + 255) & ~(size_t)255;
+    const size_t total = fb * (size_t)pl->nws + pl->agg_bytes;
     pl->ws.assign(pl->nws, nullptr);
-    for (int i = 0; i < pl->nws; ++i) {
-        hipError_t e = hipMallocAsync(&pl->ws[i], (size_t)pl->npts * pl->es, st);
+    if (total) {
+        const hipError_t e = pool ? hipMallocFromPoolAsync(&pl->slab, total, pool, st)
+                                  : hipMallocAsync(&pl->slab, total, st);
         if (e != hipSuccess) {
-            pl->ws[i] = nullptr;
+            pl->slab = nullptr;
             free_plan(pl, st);
             return fail(MOL_E_NOMEM, "stream-ordered allocation of the workspace failed");
         }
-        (void)hipMemsetAsync(pl->ws[i], 0, (size_t)pl->npts * pl->es, st);
-    }
-    if (pl->agg_bytes && hipMallocAsync(&pl->agg, pl->agg_bytes, st) != hipSuccess) {
-        pl->agg = nullptr;
-        free_plan(pl, st);
-        return fail(MOL_E_NOMEM, "stream-ordered allocation of the aggregate table failed");
+        unsigned char *base = static_cast<unsigned char *>(pl->slab);
+        for (int i = 0; i < pl->nws; ++i) pl->ws[i] = base + (size_t)i * fb;
+        if (pl->nws) (void)hipMemsetAsync(base, 0, fb * (size_t)pl->nws, st);
+        if (pl->agg_bytes) pl->agg = base + fb * (size_t)pl->nws;
     }
     *out = pl;
     return MOL_OK;

@@ -86,8 +86,10 @@ struct mol_plan_ {
     std::vector<double> h_cross;
     // tuned launch configurations: key "dir nf ns no" -> config id
     std::vector<std::pair<std::string, int>> tuned;
-    // workspace from the stream-ordered allocator (plans of the request server)
+    // workspace from the stream-ordered allocator (plans of the request
+    // server): one block holding the workspace fields and the aggregate table
     bool async_ws = false;
+    void *slab = nullptr;
     // 2D box plans at small nu: the ADI operator C composed as
     // D_x(L_y^-1 v) + L_x^-1(D_y v), with L^-1 swept by its own recurrences
     bool kmode = false;
@@ -201,8 +203,10 @@ mol_status set_error(mol_status s, const std::string &msg);
 mol_status dev_err(hipError_t e, const char *what);
 
 // plans whose workspace is allocated and freed in stream order on st (no
-// device-wide synchronisation; used by the request server)
-mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out);
+// device-wide synchronisation; used by the request server), as one block from
+// pool (nullptr: the device's default pool)
+mol_status plan_create_async(const mol_desc *desc, hipStream_t st, mol_plan_ **out,
+                             hipMemPool_t pool = nullptr);
 void plan_destroy_async(mol_plan_ *pl, hipStream_t st);
 
 }  // namespace molt

@@ -81,7 +81,12 @@ struct mol_server_ {
     size_t budget = 0, used = 0, peak = 0;
     std::vector<hipStream_t> streams;
     std::vector<double> load;         // outstanding point-updates per stream
-    hipStream_t copy = nullptr;       // results leave on their own stream
+    hipStream_t copy = nullptr;       // results leave, and finished requests' memory
+                                      // returns to the pool, on their own stream
+    // device memory of the requests and round tables; what is freed stays
+    // reserved in the pool (no release threshold), so that admitting a
+    // request costs no allocation from the driver once the pool has grown
+    hipMemPool_t pool = nullptr;
     int64_t next_id = 1;
     std::deque<Req *> queue;
     std::map<int64_t, Req *> reqs;
@@ -124,10 +129,15 @@ int64_t npoints(const mol_desc &d)
     return n;
 }
 
-// Release everything but the result field.
+// Release everything but the result field.  The request's work is complete
+// (its event fired, or its stream was synchronised), so the memory goes back
+// to the pool on the copy stream, which holds no pending work here: freed at
+// the tail of the request's own stream it would be ordered after the solves
+// queued there since, and a request on another stream that is handed the
+// same memory by the pool would wait for all of them.
 void retire(mol_server_ *s, Req *r)
 {
-    hipStream_t st = s->streams[r->stream];
+    hipStream_t st = s->copy;
     s->load[r->stream] -= r->work;
     r->work = 0;
     if (r->plan) molt::plan_destroy_async(r->plan, st);
@@ -154,10 +164,10 @@ mol_status launch(mol_server_ *s, Req *r)
     mol_desc d = r->desc;
     d.mask = r->mask.empty() ? nullptr : r->mask.data();
     d.cross = r->cross.empty() ? nullptr : r->cross.data();
-    mol_status ms = molt::plan_create_async(&d, st, &r->plan);
+    mol_status ms = molt::plan_create_async(&d, st, &r->plan, s->pool);
     if (ms != MOL_OK) return sfail(ms, mol_last_error());
-    if (hipMallocAsync(&r->d_prev, r->field, st) != hipSuccess ||
-        hipMallocAsync(&r->d_curr, r->field, st) != hipSuccess)
+    if (hipMallocFromPoolAsync(&r->d_prev, r->field, s->pool, st) != hipSuccess ||
+        hipMallocFromPoolAsync(&r->d_curr, r->field, s->pool, st) != hipSuccess)
         return sfail(MOL_E_NOMEM, "stream-ordered allocation of the state fields failed");
     if (hipMemcpyAsync(r->d_prev, r->u0, r->field,
                        r->u0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -182,10 +192,10 @@ mol_status admit_batched(mol_server_ *s, Req *r)
     mol_desc d = r->desc;
     d.mask = r->mask.empty() ? nullptr : r->mask.data();
     d.cross = r->cross.empty() ? nullptr : r->cross.data();
-    mol_status ms = molt::plan_create_async(&d, st, &r->plan);
+    mol_status ms = molt::plan_create_async(&d, st, &r->plan, s->pool);
     if (ms != MOL_OK) return sfail(ms, mol_last_error());
-    if (hipMallocAsync(&r->d_prev, r->field, st) != hipSuccess ||
-        hipMallocAsync(&r->d_curr, r->field, st) != hipSuccess)
+    if (hipMallocFromPoolAsync(&r->d_prev, r->field, s->pool, st) != hipSuccess ||
+        hipMallocFromPoolAsync(&r->d_curr, r->field, s->pool, st) != hipSuccess)
         return sfail(MOL_E_NOMEM, "stream-ordered allocation of the state fields failed");
     if (hipMemcpyAsync(r->d_prev, r->u0, r->field,
                        r->u0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -283,7 +293,7 @@ bool issue_round(mol_server_ *s)
         sl.cap = 0;
         const size_t cap = std::max(total * 2, (size_t)1 << 20);
         if (hipHostMalloc(&sl.h, cap, hipHostMallocDefault) != hipSuccess ||
-            hipMallocAsync(&sl.d, cap, st) != hipSuccess) {
+            hipMallocFromPoolAsync(&sl.d, cap, s->pool, st) != hipSuccess) {
             s_err = "round table allocation failed";
             for (Req *r : act) {
                 r->err = s_err;
@@ -454,6 +464,22 @@ mol_status mol_server_create(size_t hbm_budget_bytes, int nstreams, mol_server *
         delete s;
         return sfail(MOL_E_DEVICE, "stream creation failed");
     }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipMemPoolProps pp{};
+    pp.allocType = hipMemAllocationTypePinned;
+    pp.handleTypes = hipMemHandleTypeNone;
+    pp.location.type = hipMemLocationTypeDevice;
+    pp.location.id = dev;
+    uint64_t keep = UINT64_MAX;
+    if (hipMemPoolCreate(&s->pool, &pp) != hipSuccess ||
+        hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+        if (s->pool) (void)hipMemPoolDestroy(s->pool);
+        for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+        (void)hipStreamDestroy(s->copy);
+        delete s;
+        return sfail(MOL_E_DEVICE, "memory pool creation failed");
+    }
     *out = s;
     return MOL_OK;
 }
@@ -486,7 +512,7 @@ mol_status mol_server_destroy(mol_server *s)
         for (auto &kv : s->reqs) {
             Req *r = kv.second;
             if (r->state == Q_RUNNING) retire(s, r);
-            if (r->d_curr) (void)hipFreeAsync(r->d_curr, s->streams[r->stream]);
+            if (r->d_curr) (void)hipFreeAsync(r->d_curr, s->copy);
             delete r;
         }
         s->reqs.clear();
@@ -495,13 +521,15 @@ mol_status mol_server_destroy(mol_server *s)
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
-    (void)hipStreamSynchronize(s->copy);
-    (void)hipStreamDestroy(s->copy);
     for (auto &sl : s->slots) {
         if (sl.h) (void)hipHostFree(sl.h);
-        if (sl.d) (void)hipFree(sl.d);
+        if (sl.d) (void)hipFreeAsync(sl.d, s->copy);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
     }
+    (void)hipStreamSynchronize(s->copy);
+    (void)hipStreamDestroy(s->copy);
+    // every allocation from the pool has been freed and the frees completed
+    if (s->pool) (void)hipMemPoolDestroy(s->pool);
     delete s;
     return MOL_OK;
 }
