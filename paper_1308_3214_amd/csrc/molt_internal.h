@@ -81,7 +81,7 @@ hipError_t launch_sweep(const SweepOp &op, const Geom &g, const DirCoef &dc, boo
 // Exact two-pass strided configurations: the smallest tile they use, whether
 // cfg is one, and the bytes of the aggregate table a plan holds for sweeps
 // along dir (0 for x).
-constexpr int EXACT_MIN_TILE = 128;
+constexpr int EXACT_MIN_TILE = 64;
 bool config_exact(const SweepOp &op, const int *cfg);
 size_t exact_agg_bytes(const Geom &g, int dir, bool fp64);
 

@@ -441,26 +441,28 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
     }
     const int regs = (2 * ns + no) * (fp64 ? 2 : 1);
     const int tcfg = (regs <= 4) ? 0 : 2;   // {16,16} or {8,16}
+    // exact two-pass tiles of 512 threads, so that two or more workgroups
+    // share a CU and one's loads overlap another's recurrences and barriers:
+    // {16,8} (128 rows) for one FP32 combination, else {8,8} (64 rows; the
+    // fastest measured at 4096^2 for D-form FP64 and every K-form sweep)
+    const int ecfg = NSCFG + NPCFG + ((regs <= 4) ? 2 : 3);
     if (op.kform[0] || op.kform[1]) {
         // L^{-1} sweeps: one tile, else the exact two-pass sweep
         cfg[0] = tcfg;
         if (config_valid(g, dc, op, fp64, cfg)) return 0;
         cfg[0] = 0;
         if (config_valid(g, dc, op, fp64, cfg)) return 0;
-        cfg[0] = NSCFG + NPCFG + (tcfg == 0 ? 0 : 1);
+        cfg[0] = ecfg;
         if (config_valid(g, dc, op, fp64, cfg)) return 0;
         cfg[0] = NSCFG + NPCFG;
         return config_valid(g, dc, op, fp64, cfg) ? 0 : -1;
     }
     // carries longer than half a tile (small nu): the tile kernel's halo sums
-    // would read more than the tile itself; the exact two-pass sweep of the
-    // same tile shape reads the tile twice, whatever the carry length
+    // would read more than the tile itself; the exact two-pass sweep reads
+    // each tile twice, whatever the carry length
     const SCfg tc = kSCfg[tcfg];
     if (2 * (int64_t)dc.halo > (int64_t)tc.S * tc.W) {
-        cfg[0] = NSCFG + NPCFG + (tcfg == 0 ? 0 : 1);
-        static_assert(kECfg[0].S == kSCfg[0].S && kECfg[0].W == kSCfg[0].W &&
-                      kECfg[1].S == kSCfg[2].S && kECfg[1].W == kSCfg[2].W,
-                      "exact tile shapes follow the tile configurations 0 and 2");
+        cfg[0] = ecfg;
         if (config_valid(g, dc, op, fp64, cfg)) return 0;
     }
     cfg[0] = tcfg;

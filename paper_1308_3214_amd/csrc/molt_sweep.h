@@ -1322,22 +1322,26 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
     }
     __syncthreads();
 
+    // sums across the waves of the tile (and, in the scan, across tiles) are
+    // accumulated in FP64 and rounded once: with small nu they add up to
+    // hundreds of terms of like size
+    const double dS = exp(-a.nu * (double)S);
     if (MODE == 1) {
         // the tile's aggregates; E^L at node M from the wave holding it
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             T *tk = tab + ((size_t)tile * MAXS + k) * (3 * 64);
             if (wave == 0) {
-                T c = T(0), cr = T(0);
-                for (int w = 0; w < W; ++w) c = a.dS * c + red[0][k][w][lane];
-                for (int w = W - 1; w >= 0; --w) cr = a.dS * cr + red[1][k][w][lane];
-                tk[lane] = c;
-                tk[64 + lane] = cr;
+                double c = 0.0, cr = 0.0;
+                for (int w = 0; w < W; ++w) c = dS * c + (double)red[0][k][w][lane];
+                for (int w = W - 1; w >= 0; --w) cr = dS * cr + (double)red[1][k][w][lane];
+                tk[lane] = (T)c;
+                tk[64 + lane] = (T)cr;
             }
             if (jm >= 0 && jm < S) {
-                T c = T(0);
-                for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
-                tk[128 + lane] = eLM[k] + expneg<T>(a.nu * (double)(jm + 1)) * c;
+                double c = 0.0;
+                for (int w = 0; w < wave; ++w) c = dS * c + (double)red[0][k][w][lane];
+                tk[128 + lane] = (T)((double)eLM[k] + exp(-a.nu * (double)(jm + 1)) * c);
             }
         }
         return;
@@ -1358,12 +1362,12 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
     T cL[NS], cR[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        T c = carry[0][k][lane];
-        for (int w = 0; w < wave; ++w) c = a.dS * c + red[0][k][w][lane];
-        cL[k] = c;
-        T cr = carry[1][k][lane];
-        for (int w = W - 1; w > wave; --w) cr = a.dS * cr + red[1][k][w][lane];
-        cR[k] = cr;
+        double c = (double)carry[0][k][lane];
+        for (int w = 0; w < wave; ++w) c = dS * c + (double)red[0][k][w][lane];
+        cL[k] = (T)c;
+        double cr = (double)carry[1][k][lane];
+        for (int w = W - 1; w > wave; --w) cr = dS * cr + (double)red[1][k][w][lane];
+        cR[k] = (T)cr;
     }
 
     // ---- closure and epilogue ----
@@ -1403,7 +1407,7 @@ k_sweep_e(const KArgs<T> a)
 
 // Between the two passes: one lane per column of one column group (blockIdx.x
 // over outer x column groups) and one combination (blockIdx.y); the tile
-// aggregates are read eight tiles at a time (all loads in flight before the
+// aggregates are read sixteen tiles at a time (all loads in flight before the
 // serial recurrences use them) and overwritten in place: TL_t <- cTop_t,
 // TR_t <- cBot_t, slot 2 of tile 0 <- E^R_0, slot 2 of the last tile <- E^L_M
 // (the host requires two tiles or more).
@@ -1411,24 +1415,27 @@ template <typename T>
 __global__ void __launch_bounds__(64)
 k_exact_scan(const KArgs<T> a)
 {
-    constexpr int U = 8;
+    constexpr int U = 16;
     const int lane = threadIdx.x;
     const int k = blockIdx.y;
     const int ntiles = a.ntiles, last = ntiles - 1;
     T *tab = a.agg + (size_t)blockIdx.x * (size_t)ntiles * (MAXS * 3 * 64) + (size_t)k * (3 * 64) + lane;
     const size_t tstride = (size_t)MAXS * 3 * 64;
-    const T dT = a.dT;
+    // carries accumulated in FP64 (many terms of like size when nu is small)
+    const double dT = exp(-a.nu * (double)a.tile_rows);
     // forward: carries entering each tile from above
-    T c = T(0);
+    double c = 0.0;
     for (int t0 = 0; t0 < ntiles; t0 += U) {
+        // unconditional loads (clamped to the last tile) so that all U are in
+        // flight together; values past the end are not used
         T x[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) x[i] = (t0 + i < ntiles) ? tab[(size_t)(t0 + i) * tstride] : T(0);
+        for (int i = 0; i < U; ++i) x[i] = tab[(size_t)min(t0 + i, last) * tstride];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             if (t0 + i < ntiles) {
-                tab[(size_t)(t0 + i) * tstride] = c;
-                if (t0 + i < last) c = dT * c + x[i];
+                tab[(size_t)(t0 + i) * tstride] = (T)c;
+                if (t0 + i < last) c = dT * c + (double)x[i];
             }
         }
     }
@@ -1436,21 +1443,22 @@ k_exact_scan(const KArgs<T> a)
     const int M = (int)a.n - 1;
     const T em = tab[(size_t)last * tstride + 128];
     // backward: carries entering each tile from below, and E^R_0
-    T e = T(0);
+    double e = 0.0;
     for (int t0 = last; t0 >= 0; t0 -= U) {
         T x[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) x[i] = (t0 - i >= 0) ? tab[(size_t)(t0 - i) * tstride + 64] : T(0);
+        for (int i = 0; i < U; ++i) x[i] = tab[(size_t)max(t0 - i, 0) * tstride + 64];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             if (t0 - i >= 0) {
-                tab[(size_t)(t0 - i) * tstride + 64] = e;
-                e = dT * e + x[i];
+                tab[(size_t)(t0 - i) * tstride + 64] = (T)e;
+                e = dT * e + (double)x[i];
             }
         }
     }
-    tab[128] = e;
-    tab[(size_t)last * tstride + 128] = em + expneg<T>(a.nu * (double)(M - last * a.tile_rows + 1)) * c;
+    tab[128] = (T)e;
+    tab[(size_t)last * tstride + 128] =
+        (T)((double)em + exp(-a.nu * (double)(M - last * a.tile_rows + 1)) * c);
 }
 
 // ---------------------------------------------------------------------------
@@ -2446,7 +2454,7 @@ struct PCfg { int S, W, target; };
 constexpr PCfg kPCfg[] = {{8, 16, 256}, {16, 8, 512}, {8, 8, 512}, {8, 16, 512}, {16, 8, 256}, {4, 16, 256}};
 constexpr int NPCFG = sizeof(kPCfg) / sizeof(kPCfg[0]);
 // exact two-pass strided configurations (tile shapes, S x W rows per tile)
-constexpr SCfg kECfg[] = {{16, 16}, {8, 16}};
+constexpr SCfg kECfg[] = {{16, 16}, {8, 16}, {16, 8}, {8, 8}};
 constexpr int NECFG = sizeof(kECfg) / sizeof(kECfg[0]);
 // chained strided configurations (same fields as PCfg)
 constexpr PCfg kYCfg[] = {{8, 8, 256}, {4, 16, 256}, {8, 8, 512}, {4, 16, 512}, {4, 8, 256}};

@@ -50,7 +50,7 @@ def test_descriptor_validation_and_workspace(lib):
     # workspace sizing needs no device
     w = molt.workspace_bytes(shape=(64, 64), h=1 / 63, P=2, cfl=2.0, dtype="f32")
     # whole fields plus the carry table of the exact strided sweeps (one
-    # column group, one tile of 128 rows, 2 combinations x 3 values x 64 lanes)
+    # column group, one tile of 64 rows, 2 combinations x 3 values x 64 lanes)
     agg = 1 * 1 * 1 * 2 * 3 * 64 * 4
     assert w > agg and (w - agg) % (64 * 64 * 4) == 0
     assert molt.workspace_bytes(shape=(64, 64), h=1 / 63, P=9, cfl=2.0) == 0
@@ -99,7 +99,7 @@ def test_size_limits(lib):
     assert "line length" in molt.last_error()
     tall = (1 << 31) // 16384                     # 131072 rows of 16384 nodes = 2^31
     w = molt.workspace_bytes(shape=(tall - 1, 16384), h=1e-6, P=2, cfl=2.0, dtype="f32")
-    agg = 256 * ((tall - 1 + 127) // 128) * 2 * 3 * 64 * 4     # carry table of the exact y sweeps
+    agg = 256 * ((tall - 1 + 63) // 64) * 2 * 3 * 64 * 4       # carry table of the exact y sweeps
     assert w > agg and (w - agg) % ((tall - 1) * 16384 * 4) == 0
     assert molt.workspace_bytes(shape=(tall, 16384), h=1e-6, P=2, cfl=2.0, dtype="f32") == 0
     assert "2^31" in molt.last_error()
