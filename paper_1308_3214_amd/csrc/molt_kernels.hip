@@ -393,8 +393,10 @@ int default_config(const Geom &g, const DirCoef &dc, const SweepOp &op, bool fp6
     (void)no;
     if (op.yy) {
         // the first valid configuration whose strips fill the chip (>= 256
-        // workgroups), else the first valid one
-        static const int order[] = {0, 4, 1, 2, 3};
+        // workgroups), else the first valid one; 32-row sub-tiles of 8 waves
+        // first (the fastest measured at 1024^2 and 4096^2 where the carry
+        // length lets them in), then 64-row ones
+        static const int order[] = {4, 0, 1, 2, 3};
         static_assert(NYCFG == 5, "chained configuration order out of step");
         const int64_t groups = ((g.n[0] + 63) / 64) * (dir == 1 ? g.n[2] : g.n[1]);
         int first = -1;
