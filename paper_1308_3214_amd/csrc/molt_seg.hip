@@ -175,21 +175,13 @@ k_seg_sweep(const SegArgs<T> a)
         vls[k] = sk[((m - 1) / S) * (S + 1) + ((m - 1) % S)];
     }
     T cL[NS], cR[NS];
+    const LaneW<T> lw = lane_weights<T>(a.nu * (double)S, lane);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         T xl = aL[k], xr = aR[k];
-#pragma unroll
-        for (int i = 0, off = 1; off < 64; ++i, off <<= 1) {
-            const T mm = a.dpw[i];       // d^(S off), rounded once from FP64
-            const T yl = shfl_up(xl, off);
-            const T yr = shfl_down(xr, off);
-            if (lane >= off) xl += mm * yl;
-            if (lane + off < 64) xr += mm * yr;
-        }
-        const T exl = shfl_up(xl, 1);
-        const T exr = shfl_down(xr, 1);
-        cL[k] = (lane == 0) ? T(0) : exl;
-        cR[k] = (lane == 63) ? T(0) : exr;
+        lane_scans<T>(xl, xr, a.dpw, lw, lane);  // multipliers d^(S off), rounded once from FP64
+        cL[k] = dpp_mov<0x138>(xl);              // lane - 1 (0 at lane 0)
+        cR[k] = dpp_mov<0x130>(xr);              // lane + 1 (0 at lane 63)
         if (WPL > 1) {
             if (lane == 63) wtot[0][k][wave] = xl;
             if (lane == 0) wtot[1][k][wave] = xr;

@@ -175,10 +175,36 @@ __device__ __forceinline__ void field_chunks(int nf, F &&body)
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_up(T v, int off) { return __shfl_up(v, off, 64); }
-template <typename T>
-__device__ __forceinline__ T shfl_down(T v, int off) { return __shfl_down(v, off, 64); }
+// Lane moves through DPP (data-parallel primitives on the VALU, no LDS):
+// CTRL 0x111+n / 0x101+n = row shift right / left by n inside rows of 16
+// lanes, 0x138 / 0x130 = whole-wave shift right / left by one, 0x142 / 0x143
+// = lane 15 / lane 31 broadcast into the rows that ROWM enables.  Lanes
+// without a source (and lanes of disabled rows) read 0.
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWM,
+                                                                 0xf, false));
+}
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWM, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWM, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_read(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
 // A row of zeros in device memory.  Loads of nodes that read as 0 (outside a
 // line, Dirichlet end rows of a halo) are pointed here instead of being
@@ -237,6 +263,52 @@ template <>
 __device__ __forceinline__ double expneg<double>(double x)
 {
     return exp(-x);
+}
+
+// Weights of the lane scans below for a lane with multiplier m = d^S per lane:
+// wA = m^(j+1) (from the last lane of the row above), wB = m^(l-31) for rows 2
+// and 3 (from lane 31), wR = m^(16-j) (from the first lane of the row below);
+// l = lane, j = l mod 16.  Each rounded once from FP64 arguments.
+template <typename T>
+struct LaneW {
+    T wA, wB, wR;
+};
+template <typename T>
+__device__ __forceinline__ LaneW<T> lane_weights(double nuS, int lane)
+{
+    const int j = lane & 15;
+    LaneW<T> w;
+    w.wA = expneg<T>(nuS * (double)(j + 1));
+    w.wB = expneg<T>(nuS * (double)(lane >= 32 ? lane - 31 : j + 1));
+    w.wR = expneg<T>(nuS * (double)(16 - j));
+    return w;
+}
+
+// Weighted inclusive scans over the 64 lanes of a wave, in place:
+// xl_l = sum_{k <= l} m^(l-k) x_k and xr_l = sum_{k >= l} m^(k-l) x_k, m = d^S;
+// dpw[i] = m^(2^i).  Row shifts by 1, 2, 4, 8 scan each row of 16 lanes;
+// forward, the row ends are then broadcast into the rows below; backward, the
+// row heads are read into scalars and their carries formed there.
+template <typename T>
+__device__ __forceinline__ void lane_scans(T &xl, T &xr, const T *dpw, const LaneW<T> &w, int lane)
+{
+    xl += dpw[0] * dpp_mov<0x111>(xl);
+    xr += dpw[0] * dpp_mov<0x101>(xr);
+    xl += dpw[1] * dpp_mov<0x112>(xl);
+    xr += dpw[1] * dpp_mov<0x102>(xr);
+    xl += dpw[2] * dpp_mov<0x114>(xl);
+    xr += dpw[2] * dpp_mov<0x104>(xr);
+    xl += dpw[3] * dpp_mov<0x118>(xl);
+    xr += dpw[3] * dpp_mov<0x108>(xr);
+    xl += w.wA * dpp_mov<0x142, 0xa>(xl);       // rows 1, 3 from lanes 15, 47
+    xl += w.wB * dpp_mov<0x143, 0xc>(xl);       // rows 2, 3 from lane 31
+    const T m16 = dpw[4];
+    const T q2 = lane_read(xr, 48);
+    const T q1 = lane_read(xr, 32) + m16 * q2;
+    const T q0 = lane_read(xr, 16) + m16 * q1;
+    const int r = lane >> 4;
+    const T q = (r == 0) ? q0 : (r == 1) ? q1 : (r == 2) ? q2 : T(0);
+    xr += w.wR * q;
 }
 
 // Forcing of the two recurrences at node p from its neighbours vm, v0, vp
@@ -607,25 +679,17 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
             }
         }
     }
-    // lane scan (multiplier d^S per lane), then waves through LDS
+    // lane scan (multiplier d^S per lane; multipliers d^(S off) rounded once
+    // from FP64: repeated squaring in FP32 would compound its rounding), then
+    // waves through LDS
     T cL[NSW], cR[NSW];
+    const LaneW<T> lw = lane_weights<T>(a.nu * (double)S, lane);
 #pragma unroll
     for (int k = 0; k < NSW; ++k) {
         T xl = aL[k], xr = aR[k];
-#pragma unroll
-        for (int i = 0, off = 1; off < 64; ++i, off <<= 1) {
-            // multiplier d^(S off), rounded once from FP64 (repeated squaring
-            // in FP32 would compound its rounding 32-fold)
-            const T m = a.dpw[i];
-            const T yl = shfl_up(xl, off);
-            const T yr = shfl_down(xr, off);
-            if (lane >= off) xl += m * yl;
-            if (lane + off < 64) xr += m * yr;
-        }
-        const T exl = shfl_up(xl, 1);
-        const T exr = shfl_down(xr, 1);
-        cL[k] = (lane == 0) ? T(0) : exl;
-        cR[k] = (lane == 63) ? T(0) : exr;
+        lane_scans<T>(xl, xr, a.dpw, lw, lane);
+        cL[k] = dpp_mov<0x138>(xl);              // lane - 1 (0 at lane 0)
+        cR[k] = dpp_mov<0x130>(xr);              // lane + 1 (0 at lane 63)
         if (WPL > 1) {
             if (lane == 63) wtot[0][k][wave] = xl;
             if (lane == 0) wtot[1][k][wave] = xr;
@@ -1973,21 +2037,13 @@ __device__ __forceinline__ void sweep_xc_body(const KArgs<T> &a, const int64_t b
     }
     // lane scan (multiplier d^S per lane), then waves through LDS
     T cL[NS], cR[NS];
+    const LaneW<T> lw = lane_weights<T>(a.nu * (double)S, lane);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         T xl = aL[k], xr = aR[k];
-#pragma unroll
-        for (int i = 0, off = 1; off < 64; ++i, off <<= 1) {
-            const T m = a.dpw[i];
-            const T yl = shfl_up(xl, off);
-            const T yr = shfl_down(xr, off);
-            if (lane >= off) xl += m * yl;
-            if (lane + off < 64) xr += m * yr;
-        }
-        const T exl = shfl_up(xl, 1);
-        const T exr = shfl_down(xr, 1);
-        cL[k] = (lane == 0) ? T(0) : exl;
-        cR[k] = (lane == 63) ? T(0) : exr;
+        lane_scans<T>(xl, xr, a.dpw, lw, lane);
+        cL[k] = dpp_mov<0x138>(xl);              // lane - 1 (0 at lane 0)
+        cR[k] = dpp_mov<0x130>(xr);              // lane + 1 (0 at lane 63)
         if (lane == 63) wtot[0][k][wave] = xl;
         if (lane == 0) wtot[1][k][wave] = xr;
     }
