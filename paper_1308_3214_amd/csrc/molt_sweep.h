@@ -577,14 +577,17 @@ __device__ __forceinline__ void seg_fix_bdata(int p0, int M, T v0, T v1, T vM1, 
 // mwave (wave-uniform) = false: no lane of this wave holds node M or lies
 // beyond it, so the per-lane end handling is skipped by a branch instead of
 // being evaluated (and discarded) by every lane.
+// ea = e^{-nu p0}, eb = e^{-nu (M - p0 - S + 1)}: the closure's decay factors
+// at this segment (seg_close_fast forms them; a caller that closes several
+// sweeps with the same segments passes them in)
 template <typename T, int S>
-__device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A, double B, int p0,
-                                               int M, double nu, T d, bool dir_end, bool mwave = true)
+__device__ __forceinline__ void seg_close_fast_w(T (&sum)[S], T cL, T cR, double A, double B, int p0,
+                                                 int M, T ea, T eb, T d, bool dir_end, bool mwave = true)
 {
     const int jm = M - p0;
     const bool holdsM = jm < S;
-    const T lt = d * cL + ((A != 0.0) ? (T)A * expneg<T>(nu * (double)p0) : T(0));
-    const T rt = d * cR + ((!holdsM && B != 0.0) ? (T)B * expneg<T>(nu * (double)(jm - (S - 1))) : T(0));
+    const T lt = d * cL + ((A != 0.0) ? (T)A * ea : T(0));
+    const T rt = d * cR + ((!holdsM && B != 0.0) ? (T)B * eb : T(0));
     T tl = lt, tr = rt;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -614,6 +617,15 @@ __device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A
     }
     if (dir_end && p0 == 0) sum[0] = T(0);
 }
+template <typename T, int S>
+__device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A, double B, int p0,
+                                               int M, double nu, T d, bool dir_end, bool mwave = true)
+{
+    const int jm = M - p0;
+    const T ea = (A != 0.0) ? expneg<T>(nu * (double)p0) : T(0);
+    const T eb = (jm >= S && B != 0.0) ? expneg<T>(nu * (double)(jm - (S - 1))) : T(0);
+    seg_close_fast_w<T, S>(sum, cL, cR, A, B, p0, M, ea, eb, d, dir_end, mwave);
+}
 
 // ---------------------------------------------------------------------------
 // x sweep: contiguous lines, one line per workgroup of NT = 64*WPL threads
@@ -622,9 +634,32 @@ __device__ __forceinline__ void seg_close_fast(T (&sum)[S], T cL, T cR, double A
 // values replace the inputs in place.  Ends with a __syncthreads.
 // XM: 0 = D sweeps, 1 = some combination swept for L^{-1}, 2 = a line with
 // boundary data (Dirichlet or Neumann, one combination)
+// Per-thread decay factors of an x sweep (the same for every sweep of the
+// workgroup's line): the lane scans' weights, d^{S lane} and d^{S (63 - lane)}
+// for the carries between waves, and the closure's factors at the thread's
+// segment.  Formed once and shared by the chained sweeps.
+template <typename T>
+struct XW {
+    LaneW<T> lw;
+    T pl, pr, ea, eb;
+};
+template <typename T, int S>
+__device__ __forceinline__ XW<T> x_weights(const KArgs<T> &a, int t, int n)
+{
+    const int lane = t & 63;
+    const int p0 = t * S, jm = n - 1 - p0;
+    XW<T> w;
+    w.lw = lane_weights<T>(a.nu * (double)S, lane);
+    w.pl = expneg<T>(a.nu * (double)S * (double)lane);
+    w.pr = expneg<T>(a.nu * (double)S * (double)(63 - lane));
+    w.ea = expneg<T>(a.nu * (double)p0);
+    w.eb = (jm >= S) ? expneg<T>(a.nu * (double)(jm - (S - 1))) : T(0);
+    return w;
+}
+
 template <typename T, int S, int WPL, int NSW, bool PER, int XM = 0>
 __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)[MAXS][WPL],
-                                             T (*ends)[MAXS], int t, int n)
+                                             T (*ends)[MAXS], int t, int n, const XW<T> &xw)
 {
     constexpr bool KF = (XM == 1), BD = (XM == 2);
     constexpr int NT = 64 * WPL;
@@ -683,11 +718,10 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
     // from FP64: repeated squaring in FP32 would compound its rounding), then
     // waves through LDS
     T cL[NSW], cR[NSW];
-    const LaneW<T> lw = lane_weights<T>(a.nu * (double)S, lane);
 #pragma unroll
     for (int k = 0; k < NSW; ++k) {
         T xl = aL[k], xr = aR[k];
-        lane_scans<T>(xl, xr, a.dpw, lw, lane);
+        lane_scans<T>(xl, xr, a.dpw, xw.lw, lane);
         cL[k] = dpp_mov<0x138>(xl);              // lane - 1 (0 at lane 0)
         cR[k] = dpp_mov<0x130>(xr);              // lane + 1 (0 at lane 63)
         if (WPL > 1) {
@@ -697,8 +731,7 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
     }
     if (WPL > 1) {
         __syncthreads();
-        const T pl = expneg<T>(a.nu * (double)S * (double)lane);
-        const T pr = expneg<T>(a.nu * (double)S * (double)(63 - lane));
+        const T pl = xw.pl, pr = xw.pr;
 #pragma unroll
         for (int k = 0; k < NSW; ++k) {
             T cw = T(0), cwr = T(0);
@@ -729,15 +762,18 @@ __device__ __forceinline__ void x_line_sweep(const KArgs<T> &a, T *sm, T (*wtot)
         const double A = a.K00 * er0 + a.K01 * elm;
         const double B = a.K10 * er0 + a.K11 * elm;
         if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, false);
-        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, a.d, dir_end && !BD, wave >= waveM);
+        else seg_close_fast_w<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, xw.ea, xw.eb, a.d, dir_end && !BD,
+                                    wave >= waveM);
 #pragma unroll
         for (int j = 0; j < S; ++j) sk[t * (S + 1) + j] = sum[k][j];
     }
     __syncthreads();
 }
 
-template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX, int XM = 0>
-__device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bid)
+// FULL: the line fills the workgroup (n = 64 WPL S), a compile-time length,
+// so that no bounds selects remain on the loads, the staging and the stores
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX, int XM, bool FULL>
+__device__ __forceinline__ void sweep_x_body_n(const KArgs<T> &a, const int64_t bid)
 {
     constexpr bool BD = (XM == 2);
     constexpr int NT = 64 * WPL;
@@ -751,7 +787,7 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
 
     const int t = threadIdx.x;
     const int64_t line = bid;
-    const int n = (int)a.n;
+    const int n = FULL ? NT * S : (int)a.n;
     const int M = n - 1;
     const int64_t base = line * a.lineoff;            // uniform per workgroup
     constexpr bool dir_end = !PER;
@@ -836,7 +872,8 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
     __syncthreads();
 
     // ---- phases 2-3: recurrences, scans, closure (D in LDS) ----
-    x_line_sweep<T, S, WPL, NS, PER, XM>(a, sm, wtot, ends, t, n);
+    const XW<T> xw = x_weights<T, S>(a, t, n);
+    x_line_sweep<T, S, WPL, NS, PER, XM>(a, sm, wtot, ends, t, n, xw);
 
     // ---- phase 4: epilogue in the coalesced layout ----
 #pragma unroll
@@ -889,7 +926,7 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
     }
     if (a.chain) {
         __syncthreads();
-        x_line_sweep<T, S, WPL, 1, PER>(a, sm, wtot, ends, t, n);
+        x_line_sweep<T, S, WPL, 1, PER>(a, sm, wtot, ends, t, n, xw);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int e0 = (i * NT + t) * VW;
@@ -912,6 +949,12 @@ __device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bi
             }
         }
     }
+}
+template <typename T, int S, int WPL, int NS, int NO, int VW, bool PER, int NFMAX, int XM = 0>
+__device__ __forceinline__ void sweep_x_body(const KArgs<T> &a, const int64_t bid)
+{
+    if (a.n == (int64_t)64 * WPL * S) sweep_x_body_n<T, S, WPL, NS, NO, VW, PER, NFMAX, XM, true>(a, bid);
+    else sweep_x_body_n<T, S, WPL, NS, NO, VW, PER, NFMAX, XM, false>(a, bid);
 }
 // XM = 1: some combination is swept for L^{-1} (the I recurrences); XM = 2: a
 // line with Dirichlet data; XM = 0: D recurrences and homogeneous ends only
