@@ -2328,27 +2328,36 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
 
     // level 1, sub-tile t: combinations and local recurrences; wave 0 leaves
     // e1 - F^L at the sub-tile's first row for the look-ahead value of v1
+    // rows p0-1 .. p0+S of a wave hold no end node of a Dirichlet line (the
+    // usual case): a wave-uniform test that spares the per-row end checks
+    auto inner_rows = [&](int p0) -> bool { return !dir_end || (p0 > 1 && p0 + S < M); };
+
     auto combine1 = [&](int t, YYLev1<T, S, NO> &st, const Raw &xr) {
         const int p0 = wst + t * WS + wave * S;
         T v[S + 2], e1[S];
+        auto rows = [&](auto inner) {
 #pragma unroll
-        for (int j = 0; j < S + 2; ++j) {
-            T x = T(0);
+            for (int j = 0; j < S + 2; ++j) {
+                T x = T(0);
 #pragma unroll
-            for (int c = 0; c < NFP; ++c) x += a.mS[0][c] * xr[c][j];
-            const int p = p0 - 1 + j;
-            v[j] = (dir_end && (p == 0 || p == M)) ? T(0) : x;
-            if (j >= 1 && j <= S) {
-                T e = T(0), f = T(0);
+                for (int c = 0; c < NFP; ++c) x += a.mS[0][c] * xr[c][j];
+                const int p = p0 - 1 + j;
+                if constexpr (decltype(inner)::value) v[j] = x;
+                else v[j] = (dir_end && (p == 0 || p == M)) ? T(0) : x;
+                if (j >= 1 && j <= S) {
+                    T e = T(0), f = T(0);
 #pragma unroll
-                for (int c = 0; c < NFP; ++c) {
-                    e += a.mE1[c] * xr[c][j];
-                    f += a.mOF[NO - 1][c] * xr[c][j];
+                    for (int c = 0; c < NFP; ++c) {
+                        e += a.mE1[c] * xr[c][j];
+                        f += a.mOF[NO - 1][c] * xr[c][j];
+                    }
+                    e1[j - 1] = e;
+                    st.fp[j - 1] = f;
                 }
-                e1[j - 1] = e;
-                st.fp[j - 1] = f;
             }
-        }
+        };
+        if (inner_rows(p0)) rows(ic<1>{});
+        else rows(ic<0>{});
         local(v, p0, st.sum, st.aL, st.aR, st.eLM);
         // D = -(sum + carries + closure): subtracting e1 here makes the closure
         // return v1 = e1 + D (0 at Dirichlet end nodes, which level 2 reads as 0)
@@ -2450,11 +2459,12 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
         if (t2 >= pre && t2 < pre + R) {
             (void)close(t2, q0.sum, q0.eLM, q1.eLM, agg2, cLs2, cRs2, ctopS2, er0S2, endv2);
             if (active) {
+                // rows past the line end lie beyond the output resources:
+                // the hardware drops those stores
                 const int p0 = wst + t2 * WS + wave * S;
 #pragma unroll
                 for (int j = 0; j < S; ++j) {
                     const int p = p0 + j;
-                    if (p >= n) break;
                     buf_store<T>(a.mOD[0][0] * q0.sum[j], rso[0], vl + p * rowb);
                     if (NO == 2) buf_store<T>(q0.gH[j] + a.mOD[NO - 1][0] * q0.sum[j], rso[NO - 1], vl + p * rowb);
                 }
@@ -2480,7 +2490,7 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
 #pragma unroll
             for (int j = 0; j < S; ++j) v[j + 1] = c1.sum[j];            // v1
             v[S + 1] = (wave == W - 1) ? pk : vfirst[wave < W - 1 ? wave + 1 : W - 1][lane];
-            if (dir_end) {
+            if (!inner_rows(p0)) {
 #pragma unroll
                 for (int j = 0; j < S + 2; ++j) {
                     const int p = p0 - 1 + j;
