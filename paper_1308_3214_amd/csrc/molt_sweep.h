@@ -2409,7 +2409,12 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
         const int st0 = wst + t * WS;
         const int p0 = st0 + wave * S;
         const T cL = cLs[wave][lane], cR = cRs[wave][lane];
-        const double A = (dir_end && st0 == 0 && pre == 0) ? a.K00 * (double)er0S[lane] : 0.0;
+        // the closure's terms and their decay factors, formed only in the
+        // sub-tiles that hold a line end (wave-uniform tests)
+        const bool aon = dir_end && st0 == 0 && pre == 0;
+        const double A = aon ? a.K00 * (double)er0S[lane] : 0.0;
+        T ea = T(0), eb = T(0);
+        if (aon) ea = expneg<T>(a.nu * (double)p0);
         double B = 0.0;
         const bool mhere = dir_end && M < rhi && M >= st0 && M < st0 + WS;
         const bool mnext = dir_end && M < rhi && t + 1 < Rw && M >= st0 + WS && M < st0 + 2 * WS;
@@ -2425,8 +2430,9 @@ __device__ __forceinline__ void sweep_yy_body(const KArgs<T> &a, const int64_t b
             }
             __syncthreads();
             B = a.K11 * (double)endv[lane];
+            if (M - p0 >= S) eb = expneg<T>(a.nu * (double)(M - p0 - (S - 1)));
         }
-        seg_close_fast<T, S>(sum, cL, cR, A, B, p0, M, a.nu, d, dir_end);
+        seg_close_fast_w<T, S>(sum, cL, cR, A, B, p0, M, ea, eb, d, dir_end);
         return mnext ? B : 0.0;
     };
 
