@@ -1686,7 +1686,9 @@ __device__ __forceinline__ void sweep_p_body(const KArgs<T> &a, const int64_t bi
                 }
             }
         }
-        if (dir_end) {
+        // rows p0-1 .. p0+S hold no end node (a wave-uniform test) in all but
+        // the end sub-tiles: only those take the per-row end checks
+        if (dir_end && !(p0 > 1 && p0 + S < M)) {
 #pragma unroll
             for (int j = 0; j < S + 2; ++j) {
                 const int p = p0 - 1 + j;
@@ -1913,16 +1915,23 @@ __device__ __forceinline__ void sweep_p_body(const KArgs<T> &a, const int64_t bi
             for (int k = 0; k < NS; ++k) B[k] = a.K11 * (double)endv[k][lane];
         }
         const bool slow = per && (p0 + S - 1 > M);
+        // the closure's decay factors, formed only where A or B can be
+        // nonzero (wave-uniform tests: the first sub-tile of a Dirichlet line,
+        // the sub-tiles next to node M, the bottom of a split periodic strip)
+        T ea = T(0), eb = T(0);
+        if (dir_end && st0 == 0) ea = expneg<T>(a.nu * (double)p0);
+        if ((botAsB || mhere || mnext) && M - p0 >= S) eb = expneg<T>(a.nu * (double)(M - p0 - (S - 1)));
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             if (PER && slow) seg_close<T, S>(cur.sum[k], cL[k], cR[k], A[k], B[k], p0, M, a.nu, d, false);
-            else seg_close_fast<T, S>(cur.sum[k], cL[k], cR[k], A[k], B[k], p0, M, a.nu, d, dir_end);
+            else seg_close_fast_w<T, S>(cur.sum[k], cL[k], cR[k], A[k], B[k], p0, M, ea, eb, d, dir_end);
         }
         if (active) {
+            // rows past node M lie beyond the output resources: the hardware
+            // drops those stores
 #pragma unroll
             for (int j = 0; j < S; ++j) {
                 const int p = p0 + j;
-                if (p > M) break;
                 const bool z = a.proj && (bline || (dir_end && (p == 0 || p == M)));
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
