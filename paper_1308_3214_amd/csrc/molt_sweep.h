@@ -1391,7 +1391,9 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
         }
     };
     field_chunks<2, NFMAX>(a.nf, load_fields);
-    if (dir_end) {
+    // only waves whose rows p0-1 .. p0+S hold an end node take the per-row
+    // end checks (a wave-uniform test)
+    if (dir_end && !(p0 > 1 && p0 + S < M)) {
 #pragma unroll
         for (int j = 0; j < S + 2; ++j) {
             const int p = p0 - 1 + j;
@@ -1482,13 +1484,19 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
     if (a.proj)
         bline = (a.pd1 && (col == 0 || col == a.pn1 - 1)) ||
                 (a.pd2 && (outer == 0 || outer == a.pn2 - 1));
+    // the closure's decay factors at this wave's rows, skipped (wave-uniform
+    // tests) where they fall below the smallest number of the type
+    const double elim = sizeof(T) == 4 ? 104.0 : 745.0;
+    T ea = T(0), eb = T(0);
+    if (a.nu * (double)p0 < elim) ea = expneg<T>(a.nu * (double)p0);
+    if (jm >= S && a.nu * (double)(jm - (S - 1)) < elim) eb = expneg<T>(a.nu * (double)(jm - (S - 1)));
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const double er0 = (double)carry[2][k][lane], elm = (double)carry[3][k][lane];
         const double A = a.K00 * er0 + a.K01 * elm;
         const double B = a.K10 * er0 + a.K11 * elm;
         if (PER && slow) seg_close<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, false);
-        else seg_close_fast<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, a.nu, d, dir_end);
+        else seg_close_fast_w<T, S>(sum[k], cL[k], cR[k], A, B, p0, M, ea, eb, d, dir_end);
     }
     if (!active) return;
 #pragma unroll
