@@ -285,7 +285,10 @@ mol_status mol_step_static(const mol_desc *desc, const void *u_prev, const void 
  * running; it then owns a plan and two resident fields, runs mol_start and
  * nsteps - 1 steps (mol_solve, graph-captured) on one stream of the server's
  * pool, and finishes with an event.  Requests on different streams run
- * concurrently.  Allocations are stream-ordered: admitting or retiring a
+ * concurrently.  Allocations are stream-ordered, from a memory pool the
+ * server owns (one block per request's plan workspace, plus its two fields);
+ * memory a finished request frees stays reserved in that pool, and is given
+ * back to the device when the server is destroyed.  Admitting or retiring a
  * request never synchronises the device.  One host thread at a time per
  * server (calls are serialised by a mutex).
  *
