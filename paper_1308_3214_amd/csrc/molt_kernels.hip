@@ -120,7 +120,6 @@ void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *con
         k.nblocks = nlines * k.ntiles;
         k.dS = (T)exp(-dc.nu * XC_S);
         k.dBlk = (T)exp(-dc.nu * XC_S * 64.0);
-        k.dT = (T)exp(-dc.nu * (double)XC_C);
         for (int i = 0; i < 6; ++i) k.dpw[i] = (T)exp(-dc.nu * XC_S * (double)(1 << i));
         k.pn1 = g.n[1];
         k.pn2 = g.n[2];
@@ -203,7 +202,6 @@ void prep_t(const SweepOp &op, const Geom &g, const DirCoef &dc, const void *con
         k.nblocks = (int64_t)k.ntiles * ncg * k.nouter;
         k.dS = (T)exp(-dc.nu * c.S);
         k.dBlk = k.dS;
-        k.dT = (T)exp(-dc.nu * (double)WS);
         k.tile_rows = (int)WS;
         key.cls = 4;
         key.cfg = cfg[0] - NSCFG - NPCFG;

@@ -102,9 +102,8 @@ struct KArgs {
     // mOD[1][0] mV[0] / mOD[0][0] (weight of v1 left in output 1)
     T ykv, yk0, ykh;
     // exact two-pass strided sweeps: per-tile aggregates (device table of
-    // nouter x column groups x ntiles x MAXS x 3 x 64 values) and d^(W S)
+    // nouter x column groups x ntiles x MAXS x 3 x 64 values)
     T *agg;
-    T dT;
     int tile_rows;    // exact sweeps: rows per tile (W S)
     // x sweeps of a line with boundary data.  bmode = 1 (Dirichlet): the
     // L^{-1} targets at the two ends, the data's curvature there times h^2,
