@@ -1520,59 +1520,92 @@ k_sweep_e(const KArgs<T> a)
 }
 
 // Between the two passes: one lane per column of one column group (blockIdx.x
-// over outer x column groups) and one combination (blockIdx.y); the tile
-// aggregates are read sixteen tiles at a time (all loads in flight before the
-// serial recurrences use them) and overwritten in place: TL_t <- cTop_t,
-// TR_t <- cBot_t, slot 2 of tile 0 <- E^R_0, slot 2 of the last tile <- E^L_M
-// (the host requires two tiles or more).
+// over outer x column groups) and one combination (blockIdx.y), the tiles
+// split into 8 contiguous blocks, one per wave.  Each wave folds its block's
+// aggregates into a block aggregate (both directions), the waves combine the
+// block aggregates through LDS into the carries entering their blocks, and
+// each wave then walks its block again writing the exact carries in place:
+// TL_t <- cTop_t, TR_t <- cBot_t, slot 2 of tile 0 <- E^R_0, slot 2 of the last
+// tile <- E^L_M (the host requires two tiles or more).  Sixteen tiles' loads
+// are in flight at a time; sums in FP64, each stored value rounded once.
 template <typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(512)
 k_exact_scan(const KArgs<T> a)
 {
-    constexpr int U = 16;
-    const int lane = threadIdx.x;
+    constexpr int NW = 8, U = 16;
+    __shared__ double blkF[NW][64], blkB[NW][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k = blockIdx.y;
     const int ntiles = a.ntiles, last = ntiles - 1;
     T *tab = a.agg + (size_t)blockIdx.x * (size_t)ntiles * (MAXS * 3 * 64) + (size_t)k * (3 * 64) + lane;
     const size_t tstride = (size_t)MAXS * 3 * 64;
-    // carries accumulated in FP64 (many terms of like size when nu is small)
-    const double dT = exp(-a.nu * (double)a.tile_rows);
-    // forward: carries entering each tile from above
-    double c = 0.0;
-    for (int t0 = 0; t0 < ntiles; t0 += U) {
-        // unconditional loads (clamped to the last tile) so that all U are in
-        // flight together; values past the end are not used
-        T x[U];
-#pragma unroll
-        for (int i = 0; i < U; ++i) x[i] = tab[(size_t)min(t0 + i, last) * tstride];
+    const double rows = (double)a.tile_rows;
+    const double dT = exp(-a.nu * rows);
+    const int per = (ntiles + NW - 1) / NW;
+    auto bstart = [&](int w) { return min(w * per, ntiles); };
+    const int b0 = bstart(wave), b1 = bstart(wave + 1);
+    // block aggregates: forward sum_t dT^(b1-1-t) TL_t, backward sum_t dT^(t-b0) TR_t
+    double fa = 0.0, ba = 0.0, bp = 1.0;
+    for (int t0 = b0; t0 < b1; t0 += U) {
+        T x[U], y[U];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
-            if (t0 + i < ntiles) {
-                tab[(size_t)(t0 + i) * tstride] = (T)c;
-                if (t0 + i < last) c = dT * c + (double)x[i];
+            const size_t tt = (size_t)min(t0 + i, b1 - 1);
+            x[i] = tab[tt * tstride];
+            y[i] = tab[tt * tstride + 64];
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (t0 + i < b1) {
+                fa = dT * fa + (double)x[i];
+                ba += bp * (double)y[i];
+                bp *= dT;
             }
         }
     }
-    // c is now the carry entering the last tile: E^L at node M from it
-    const int M = (int)a.n - 1;
-    const T em = tab[(size_t)last * tstride + 128];
-    // backward: carries entering each tile from below, and E^R_0
-    double e = 0.0;
-    for (int t0 = last; t0 >= 0; t0 -= U) {
+    blkF[wave][lane] = fa;
+    blkB[wave][lane] = ba;
+    __syncthreads();
+    // carries entering this block: from the blocks before it (forward) and
+    // after it (backward), each block's decay dT^(its tile count)
+    double cf = 0.0, cb = 0.0;
+    for (int w = 0; w < wave; ++w) cf = exp(-a.nu * rows * (double)(bstart(w + 1) - bstart(w))) * cf + blkF[w][lane];
+    for (int w = NW - 1; w > wave; --w) cb = exp(-a.nu * rows * (double)(bstart(w + 1) - bstart(w))) * cb + blkB[w][lane];
+    // forward walk of the block: the carry entering each tile; E^L at node M
+    // from the carry entering the last tile
+    for (int t0 = b0; t0 < b1; t0 += U) {
         T x[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) x[i] = tab[(size_t)max(t0 - i, 0) * tstride + 64];
+        for (int i = 0; i < U; ++i) x[i] = tab[(size_t)min(t0 + i, b1 - 1) * tstride];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
-            if (t0 - i >= 0) {
-                tab[(size_t)(t0 - i) * tstride + 64] = (T)e;
-                e = dT * e + (double)x[i];
+            if (t0 + i < b1) {
+                tab[(size_t)(t0 + i) * tstride] = (T)cf;
+                if (t0 + i == last) {
+                    const int M = (int)a.n - 1;
+                    const T em = tab[(size_t)last * tstride + 128];
+                    tab[(size_t)last * tstride + 128] =
+                        (T)((double)em + exp(-a.nu * (double)(M - last * a.tile_rows + 1)) * cf);
+                }
+                cf = dT * cf + (double)x[i];
             }
         }
     }
-    tab[128] = (T)e;
-    tab[(size_t)last * tstride + 128] =
-        (T)((double)em + exp(-a.nu * (double)(M - last * a.tile_rows + 1)) * c);
+    // backward walk: the carry entering each tile from below; E^R_0 after tile 0
+    for (int t0 = b1 - 1; t0 >= b0; t0 -= U) {
+        T y[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) y[i] = tab[(size_t)max(t0 - i, b0) * tstride + 64];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (t0 - i >= b0) {
+                tab[(size_t)(t0 - i) * tstride + 64] = (T)cb;
+                cb = dT * cb + (double)y[i];
+            }
+        }
+    }
+    if (b0 == 0 && b1 > 0) tab[128] = (T)cb;
 }
 
 // ---------------------------------------------------------------------------
