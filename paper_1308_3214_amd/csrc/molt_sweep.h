@@ -1366,14 +1366,26 @@ __device__ __forceinline__ void sweep_e_body(const KArgs<T> &a, const int64_t bi
         }
         return (p >= 0 && p <= M) ? fb + (int64_t)p * ls : zero_row<T>();
     };
+    // rows p0-1 .. p0+S all inside the line (a wave-uniform test): plain row
+    // addresses, no per-row choice of the zero row
+    const bool rows_in = p0 >= 1 && p0 + S <= M;
     auto load_fields = [&](int f0, auto cc) {
         constexpr int C = decltype(cc)::value;
         T x[C][S + 2];
+        if (rows_in) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const T *fb = a.f[f0 + c] + blk;
+            for (int c = 0; c < C; ++c) {
+                const T *fb = a.f[f0 + c] + blk + (int64_t)(p0 - 1) * ls + lo;
 #pragma unroll
-            for (int j = 0; j < S + 2; ++j) x[c][j] = rowptr(fb, p0 - 1 + j)[lo];
+                for (int j = 0; j < S + 2; ++j) x[c][j] = fb[(int64_t)j * ls];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T *fb = a.f[f0 + c] + blk;
+#pragma unroll
+                for (int j = 0; j < S + 2; ++j) x[c][j] = rowptr(fb, p0 - 1 + j)[lo];
+            }
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
