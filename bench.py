@@ -158,7 +158,7 @@ def solve_from_start(shape, h, bc, P, cfl, dtype, u0, nsteps, **kw):
     return out
 
 
-def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None, flags=0, reps=5):
+def run_gpu(n, P, cfl, dtype, steps, warmup, seed=1, keep=None, flags=0, reps=15):
     from paper_1308_3214_amd import workloads as W
     u0 = W.gaussian_pulses_2d(n, seed=seed)
     return run_plan((n, n), 1.0 / (n - 1), 0, P, cfl, dtype, u0, steps, warmup, keep=keep,
@@ -185,6 +185,11 @@ def cfl_lines(n, P, dtype, steps, warmup):
         lc["nu"] = round(infc["nu"][0], 6)
         lc["kernels"] = [{"dir": x["dir"], "sweeps": x["sweeps"], "ms": round(x["ms"], 5),
                           "GB/s": round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1)} for x in kc]
+        if n == 4096 and P == 2:
+            from paper_1308_3214_amd import workloads as W
+            u10 = solve_from_start((n, n), 1.0 / (n - 1), 0, P, cfl, dtype,
+                                   W.gaussian_pulses_2d(n, seed=1), 10)
+            lc["error_u10"] = fixture_error("adi4096_p2_cfl%d_10" % cfl, u10)
         out["%dx%d_P%d_%s_cfl%g" % (n, n, P, dtype, cfl)] = lc
     return out
 

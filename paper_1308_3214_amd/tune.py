@@ -8,6 +8,11 @@ MOLT_TUNE_CACHE): one line per (problem, kernel shape).
 
     python -m paper_1308_3214_amd.tune                  # default problem set
     python -m paper_1308_3214_amd.tune --n 4096 --P 2 --dtype f32
+    python -m paper_1308_3214_amd.tune --n 4096 --P 2 --dtype f32 --cfl 100
+
+The key of a kernel shape does not hold the CFL number; the sweeps of the
+small-nu step (the L^{-1} form) carry their own key suffix, so tuning at a
+large CFL adds entries beside those of CFL 2.
 """
 from __future__ import annotations
 
@@ -87,15 +92,17 @@ def main():
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--ndim", type=int, default=2)
     ap.add_argument("--bc", type=int, default=0)
+    ap.add_argument("--cfl", type=float, default=2.0)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--report", default="")
     args = ap.parse_args()
     probs = DEFAULT_PROBLEMS if args.n == 0 else [dict(shape=(args.n,) * args.ndim, P=args.P,
-                                                        dtype=args.dtype, bc=args.bc)]
+                                                        dtype=args.dtype, bc=args.bc, cfl=args.cfl)]
     allent, allrep = {}, []
     for pr in probs:
         print("tuning", pr, flush=True)
-        ent, rep = tune_problem(pr["shape"], pr["P"], pr["dtype"], bc=pr.get("bc", 0))
+        ent, rep = tune_problem(pr["shape"], pr["P"], pr["dtype"], cfl=pr.get("cfl", 2.0),
+                                bc=pr.get("bc", 0))
         allent.update(ent)
         allrep.append({"problem": {k: list(v) if isinstance(v, tuple) else v
                                    for k, v in pr.items()}, "kernels": rep})

@@ -98,6 +98,17 @@ def adi4096():
             "beta %.17e alpha %.17e" % (beta, alpha)], b, idx
 
 
+def _adi4096_cfl(cfl):
+    b, beta, alpha, idx = _box_run(4096, 2, cfl, 10)
+    return ["2D 4096^2 Dirichlet on [0,1]^2, P = 2, CFL %g, 8 Gaussian pulses (sigma 0.02, seed 1)" % cfl,
+            "u^10 after mol_start and 9 steps; 80-bit oracle",
+            "beta %.17e alpha %.17e" % (beta, alpha)], b, idx
+
+
+for _c in (10, 100, 1000):
+    fixture("adi4096_p2_cfl%d_10" % _c)(lambda _c=_c: _adi4096_cfl(float(_c)))
+
+
 def _star_run(n, P, cfl, N):
     h = 1.0 / (n - 1)
     beta = float(oracle.beta_max(P))

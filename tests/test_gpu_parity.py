@@ -203,6 +203,10 @@ STRIP_CASES = [
     ((1100, 70), (1.0 / 70, 1.0 / 1100), (0, 1), 2.0),
     ((1024, 100), 1.0 / 1024, 1, 3.0),
     ((700, 130), 1.0 / 699, 0, 4.0),
+    # small nu: exact two-pass sweeps of the L^{-1} form in both directions,
+    # x lines of 4096 nodes (every x configuration the headline grid offers)
+    ((1100, 70), 1.0 / 1099, 0, 100.0),
+    ((96, 4096), 1.0 / 4095, 0, 100.0),
 ]
 
 
