@@ -166,6 +166,10 @@ hipError_t launch_seg_sweep(const SweepOp &op, const SegTable &tab, const DirCoe
 // layout) the outside nodes of out are written as 0
 hipError_t launch_transpose(bool fp64, const void *in, void *out, int64_t R, int64_t C,
                             const unsigned char *d_mask, hipStream_t st);
+// the same for nt (1..4) pairs in[i] -> out[i] of one shape, in one launch
+// where every array allows 16-byte accesses
+hipError_t launch_transpose_n(bool fp64, int nt, const void *const *in, void *const *out, int64_t R,
+                              int64_t C, const unsigned char *d_mask, hipStream_t st);
 // out[i] = 0 where mask[i] == 0 (outside nodes of a user-visible output)
 hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, void *out,
                             hipStream_t st);

@@ -245,17 +245,18 @@ hipError_t launch_seg_op(const SweepOp &op, const mol_plan_ *pl, const void *con
     if (op.dir == 1 && op.nf + op.no <= mol_plan_::NTBUF) {
         // y objects as rows of the transposed grid: coalesced sweeps; the
         // outputs come back with their outside nodes written as 0
+        // (every input transposed in one launch, every output in one launch)
         const void *tf[MAXF];
+        void *tin[MAXF];
         void *to[MAXO];
+        const void *tout[MAXO];
         hipError_t e = hipSuccess;
-        for (int f = 0; f < op.nf && e == hipSuccess; ++f) {
-            tf[f] = pl->tbuf[f];
-            e = launch_transpose(pl->fp64, fptr[f], pl->tbuf[f], ny, nx, nullptr, st);
-        }
-        for (int o = 0; o < op.no; ++o) to[o] = pl->tbuf[op.nf + o];
+        for (int f = 0; f < op.nf; ++f) tf[f] = tin[f] = pl->tbuf[f];
+        for (int o = 0; o < op.no; ++o) tout[o] = to[o] = pl->tbuf[op.nf + o];
+        if (op.nf > 0) e = launch_transpose_n(pl->fp64, op.nf, fptr, tin, ny, nx, nullptr, st);
         if (e == hipSuccess) e = launch_seg_sweep(op, pl->segT, pl->dc[1], pl->fp64, tf, to, st);
-        for (int o = 0; o < op.no && e == hipSuccess; ++o)
-            e = launch_transpose(pl->fp64, pl->tbuf[op.nf + o], optr[o], nx, ny, pl->d_mask, st);
+        if (e == hipSuccess && op.no > 0)
+            e = launch_transpose_n(pl->fp64, op.no, tout, optr, nx, ny, pl->d_mask, st);
         return e;
     }
     hipError_t e = launch_seg_sweep(op, pl->seg[op.dir], pl->dc[op.dir], pl->fp64, fptr, optr, st);

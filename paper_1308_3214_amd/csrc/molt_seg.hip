@@ -275,12 +275,20 @@ k_transpose(const T *__restrict__ in, T *__restrict__ out, int R, int C, const u
 // The same with 16-byte accesses on both sides (R and C multiples of 4 and
 // 16-byte aligned arrays): thread t reads rows t/16 + 16 i, four columns
 // 4 (t % 16) .. + 3, of a 64 x 64 tile, and writes four consecutive entries
-// of the transposed rows.
+// of the transposed rows.  Up to four arrays of the same shape in one launch:
+// grid slice z transposes pair z.
+struct TPairs {
+    const void *in[4];
+    void *out[4];
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_transpose4(const T *__restrict__ in, T *__restrict__ out, int R, int C, const unsigned char *mask)
+k_transpose4(const TPairs pr, int R, int C, const unsigned char *mask)
 {
     typedef T v4 __attribute__((ext_vector_type(4)));
+    const T *__restrict__ in = static_cast<const T *>(pr.in[blockIdx.z]);
+    T *__restrict__ out = static_cast<T *>(pr.out[blockIdx.z]);
     __shared__ T tile[64][65];
     const int t = threadIdx.x;
     const int tr = t >> 4, tc = (t & 15) * 4;
@@ -417,32 +425,46 @@ hipError_t launch_seg_sweep(const SweepOp &op, const SegTable &tab, const DirCoe
                 : seg_sweep_t<float>(op, tab, dc, fptr, optr, st);
 }
 
+hipError_t launch_transpose_n(bool fp64, int nt, const void *const *in, void *const *out, int64_t R,
+                              int64_t C, const unsigned char *d_mask, hipStream_t st)
+{
+    if (nt < 1 || nt > 4) return hipErrorInvalidValue;
+    const size_t es = fp64 ? 8 : 4;
+    bool v4 = (R % 4 == 0) && (C % 4 == 0) && (reinterpret_cast<uintptr_t>(d_mask) % 4 == 0);
+    for (int i = 0; i < nt; ++i)
+        v4 = v4 && (reinterpret_cast<uintptr_t>(in[i]) % (4 * es) == 0) &&
+             (reinterpret_cast<uintptr_t>(out[i]) % (4 * es) == 0);
+    if (v4) {
+        TPairs pr{};
+        for (int i = 0; i < nt; ++i) {
+            pr.in[i] = in[i];
+            pr.out[i] = out[i];
+        }
+        const dim3 grid((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64), (unsigned)nt);
+        if (fp64)
+            hipLaunchKernelGGL(k_transpose4<double>, grid, dim3(256), 0, st, pr, (int)R, (int)C, d_mask);
+        else
+            hipLaunchKernelGGL(k_transpose4<float>, grid, dim3(256), 0, st, pr, (int)R, (int)C, d_mask);
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64));
+    for (int i = 0; i < nt; ++i) {
+        if (fp64)
+            hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, st, static_cast<const double *>(in[i]),
+                               static_cast<double *>(out[i]), (int)R, (int)C, d_mask);
+        else
+            hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, st, static_cast<const float *>(in[i]),
+                               static_cast<float *>(out[i]), (int)R, (int)C, d_mask);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_transpose(bool fp64, const void *in, void *out, int64_t R, int64_t C,
                             const unsigned char *d_mask, hipStream_t st)
 {
-    const dim3 grid((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64));
-    const size_t es = fp64 ? 8 : 4;
-    const bool v4 = (R % 4 == 0) && (C % 4 == 0) && (reinterpret_cast<uintptr_t>(in) % (4 * es) == 0) &&
-                    (reinterpret_cast<uintptr_t>(out) % (4 * es) == 0) &&
-                    (reinterpret_cast<uintptr_t>(d_mask) % 4 == 0);
-    if (v4) {
-        if (fp64)
-            hipLaunchKernelGGL(k_transpose4<double>, grid, dim3(256), 0, st,
-                               static_cast<const double *>(in), static_cast<double *>(out), (int)R,
-                               (int)C, d_mask);
-        else
-            hipLaunchKernelGGL(k_transpose4<float>, grid, dim3(256), 0, st,
-                               static_cast<const float *>(in), static_cast<float *>(out), (int)R,
-                               (int)C, d_mask);
-        return hipGetLastError();
-    }
-    if (fp64)
-        hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, st, static_cast<const double *>(in),
-                           static_cast<double *>(out), (int)R, (int)C, d_mask);
-    else
-        hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, st, static_cast<const float *>(in),
-                           static_cast<float *>(out), (int)R, (int)C, d_mask);
-    return hipGetLastError();
+    return launch_transpose_n(fp64, 1, &in, &out, R, C, d_mask, st);
 }
 
 hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, void *out,
