@@ -18,6 +18,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libmolt.so is not built (run __graft_entry__.build() or "
                       "python paper_1308_3214_amd/build.py)")
 
+# torch (the binding's device memory and streams) loads first, so that the
+# library binds to the HIP runtime torch already holds: with the library
+# loaded first, torch's later device initialisation found no GPU
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # status codes / enums (include/molt.h)
