@@ -335,6 +335,21 @@ __global__ void k_mask_zero(int64_t n, const unsigned char *mask, T *out)
     for (int64_t k = i; k < n; k += stride)
         if (!mask[k]) out[k] = T(0);
 }
+// The same four nodes per thread (n a multiple of 4, mask 4-byte aligned):
+// one mask load per four nodes; inside nodes are not touched
+template <typename T>
+__global__ void k_mask_zero4(int64_t n4, const unsigned char *mask, T *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n4; k += stride) {
+        const uchar4 m = reinterpret_cast<const uchar4 *>(mask)[k];
+        if (!m.x) out[4 * k + 0] = T(0);
+        if (!m.y) out[4 * k + 1] = T(0);
+        if (!m.z) out[4 * k + 2] = T(0);
+        if (!m.w) out[4 * k + 3] = T(0);
+    }
+}
 
 struct SegCfg { int S, WPL; };
 constexpr SegCfg kSegCfg[NSEGCLS] = {{4, 1}, {8, 1}, {8, 2}, {8, 4}, {8, 8}, {16, 8}};
@@ -471,6 +486,19 @@ hipError_t launch_mask_zero(bool fp64, int64_t n, const unsigned char *d_mask, v
                             hipStream_t st)
 {
     const int bs = 256;
+    if (n % 4 == 0 && reinterpret_cast<uintptr_t>(d_mask) % 4 == 0) {
+        const int64_t n4 = n / 4;
+        int64_t nb4 = (n4 + bs - 1) / bs;
+        if (nb4 > 65536) nb4 = 65536;
+        if (nb4 < 1) nb4 = 1;
+        if (fp64)
+            hipLaunchKernelGGL(k_mask_zero4<double>, dim3((unsigned)nb4), dim3(bs), 0, st, n4, d_mask,
+                               static_cast<double *>(out));
+        else
+            hipLaunchKernelGGL(k_mask_zero4<float>, dim3((unsigned)nb4), dim3(bs), 0, st, n4, d_mask,
+                               static_cast<float *>(out));
+        return hipGetLastError();
+    }
     int64_t nb = (n + bs - 1) / bs;
     if (nb > 65536) nb = 65536;
     if (nb < 1) nb = 1;
